@@ -1,0 +1,186 @@
+/*
+ * liblb: finite-volume and streaming lattice Boltzmann time steps on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Shrestha, Mompean & Calzavarini, "Finite Volume vs. Streaming-based
+ * Lattice Boltzmann algorithm for fluid-dynamics simulations: a one-to-one
+ * accuracy and performance study" (arXiv:1505.03271).
+ *
+ *   FV step   sec. 2.2: cell-centred finite volumes (eq:fv), semi-implicit
+ *             collision (eq:semi) with a Heun predictor-corrector on the
+ *             advection (eq:semi-heun), QUICK face values (sec. 2.2.3),
+ *             Guo forcing (eq:F2), double-reflection no-slip walls
+ *             ("Boundary conditions").
+ *   ST step   sec. 2.1, eq:ST: collide and stream, dt = dx = 1, half-way
+ *             bounce-back walls.
+ *   Thermal   sec. 5, eq:LBg: second population set g with
+ *             g_eq = (T/rho) f_eq, Boussinesq acceleration
+ *             a = beta g (T - T0) along +y, isothermal walls at y = 0 (bottom)
+ *             and y = H (top).
+ *
+ * Units are lattice units throughout.  tau is the paper's relaxation time
+ * (nu = tau cs^2, cs^2 = 1/3); the library uses tau~ = tau + dt/2 internally.
+ *
+ * Populations: D2Q9, index a = 0..8 with velocities
+ *   (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ * Field arrays crossing this interface are row-major [ny][nx] (x fastest);
+ * population arrays are [9][ny][nx].
+ *
+ * Every function returns LB_OK (0) or an LB_E* code and never throws; the
+ * message of the last error on the calling thread is lb_last_error().  A
+ * handle must not be used from two threads at once; distinct handles are
+ * independent.  Device work is enqueued on the handle's stream; functions
+ * that return data to the host synchronise that stream first.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lb_status {
+    LB_OK = 0,
+    LB_EINVAL = 1,    /* bad argument: sizes, NULL pointers, tau <= 0, ... */
+    LB_ENOMEM = 2,    /* device or host allocation failed */
+    LB_EDEVICE = 3,   /* a HIP call failed (message has the HIP error) */
+    LB_ESTATE = 4,    /* call out of order (e.g. lb_step before lb_init) */
+    LB_EUNSTABLE = 5  /* a non-finite population was found (simulation blew up) */
+};
+
+enum lb_scheme {
+    LB_FV_HEUN = 0,   /* eq:semi-heun: the paper's method */
+    LB_FV_SEMI = 1,   /* eq:semi: semi-implicit collision, Euler advection */
+    LB_FV_EULER = 2,  /* eq:euler: explicit Euler */
+    LB_ST = 3         /* eq:ST: streaming, dt = dx = 1, uniform unit grid */
+};
+
+enum lb_storage {
+    LB_F64 = 0,   /* double populations, double arithmetic (parity path) */
+    LB_F32 = 1,   /* float offsets f - w rho_ref, float arithmetic */
+    LB_BF16 = 2,  /* bfloat16 offsets (round to nearest even), float arithmetic */
+    LB_F16 = 3    /* IEEE half offsets (round to nearest even), float arithmetic */
+};
+
+enum lb_boundary {
+    LB_PERIODIC = 0,
+    LB_WALL = 1   /* no-slip; for g isothermal on y walls, adiabatic on x walls */
+};
+
+enum lb_flags {
+    /* ST only: streaming without collision, moving raw stored words (the
+     * thermal rule degenerates to plain bounce-back).  A check of the
+     * streaming permutation, bit for bit. */
+    LB_FLAG_STREAM_ONLY = 1
+};
+
+typedef struct lb_params {
+    int32_t nx, ny;          /* cells along x and y, >= 4 */
+    int32_t scheme;          /* enum lb_scheme */
+    int32_t storage;         /* enum lb_storage */
+    int32_t thermal;         /* 1: evolve g as well (sec. 5) */
+    int32_t bc_x, bc_y;      /* enum lb_boundary */
+    int32_t flags;           /* enum lb_flags */
+    double dt;               /* time step (ignored by LB_ST, which uses 1) */
+    double tau, tau_g;       /* paper's relaxation times, > 0 */
+    double ax, ay;           /* constant body acceleration */
+    double beta_g, T0;       /* Boussinesq: a_y += beta_g (T - T0) */
+    double T_bottom, T_top;  /* wall temperatures at y = y_faces[0], y_faces[ny] */
+    double rho_ref, T_ref;   /* storage offsets (LB_F32/BF16/F16): f - w rho_ref, g - w T_ref */
+    void* stream;            /* hipStream_t to enqueue on, or NULL (null stream) */
+} lb_params;
+
+typedef struct lb_sim lb_sim;
+
+/* Create a simulation.  The library owns the handle and all device buffers
+ * (two population buffers of 9 or 18 planes each).  Errors: LB_EINVAL for
+ * unsupported sizes/values (nx or ny < 4, tau or tau_g <= 0, dt <= 0 for FV,
+ * thermal with bc_y periodic is allowed but lb_nusselt then fails),
+ * LB_ENOMEM, LB_EDEVICE. */
+int lb_create(const lb_params* p, lb_sim** out);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+void lb_destroy(lb_sim* sim);
+
+/* Grid (sec. 3, eq:grids; sec. 2.2.3).  x_faces[0..nx] and y_faces[0..ny]
+ * are the cell-face coordinates, strictly increasing; cell centres are face
+ * midpoints.  Copied; the caller keeps ownership.  The library derives 1/dx,
+ * 1/dy and the QUICK coefficients gamma_1..4 of every face, with mirrored
+ * ghost centres at walls and periodic images otherwise.  LB_ST requires unit
+ * spacing (faces 0, 1, ..., n up to a common offset) or returns LB_EINVAL.
+ * Must precede lb_init. */
+int lb_set_grid(lb_sim* sim, const double* x_faces, int64_t n_xf,
+                const double* y_faces, int64_t n_yf);
+
+/* Face helpers (eq:grids), write n+1 faces on [0, L]. */
+int lb_grid_uniform(int64_t n, double L, double* faces);
+/* Hyperbolic tangent with the paper's factor s1 = tanh(stretch). */
+int lb_grid_tanh(int64_t n, double L, double stretch, double* faces);
+
+/* Initial state at equilibrium (sec. 3.2, sec. 5): host arrays [ny][nx],
+ * caller-owned; T is ignored (may be NULL) unless thermal.  Populations are
+ * f~ = f_eq(rho, u) - dt/2 F(rho, u, a) and g~ = (T/rho) f_eq (appendix A),
+ * so lb_moments returns the given fields.  LB_ESTATE without a grid. */
+int lb_init(lb_sim* sim, const double* rho, const double* ux, const double* uy,
+            const double* T);
+
+/* Enqueue nsteps time steps (asynchronous).  Returns LB_EUNSTABLE if an
+ * earlier check (lb_diagnostics, lb_nusselt, lb_check) found non-finite
+ * populations, LB_ESTATE before lb_init. */
+int lb_step(lb_sim* sim, int64_t nsteps);
+
+/* Wait for the handle's stream. */
+int lb_sync(lb_sim* sim);
+
+/* Macroscopic fields (eq:ST relations and "Force term"): rho = sum f~,
+ * u = sum c f~ / rho + dt/2 a, T = sum g~.  Synchronises; writes caller-owned
+ * host arrays [ny][nx] computed in double; any pointer may be NULL. */
+int lb_moments(lb_sim* sim, double* rho, double* ux, double* uy, double* T);
+
+/* Nusselt numbers (sec. 5): wall-averaged -H dT/dy / dT at the bottom and top
+ * walls from the second-order one-sided difference through the wall value
+ * and the first two cell centres, and the volume value
+ * 1 + H <u_y T>_V / (kappa dT), kappa = tau_g / 3, dT = T_bottom - T_top.
+ * FP64 reductions on the device.  LB_EINVAL unless thermal with y walls. */
+int lb_nusselt(lb_sim* sim, double* nu_bottom, double* nu_top, double* nu_vol);
+
+/* FP64 device reductions, out[8]: mass sum V rho, kinetic sum V rho|u|^2/2,
+ * thermal sum V T, Nu bottom, Nu top, Nu volume (0 if not applicable),
+ * volume sum V, and 1.0 if any population is non-finite (which also makes
+ * later lb_step calls return LB_EUNSTABLE). */
+int lb_diagnostics(lb_sim* sim, double* out);
+
+/* Decoded populations in double, [9][ny][nx] for f and g (g may be NULL; it
+ * is ignored unless thermal). */
+int lb_get_populations(lb_sim* sim, double* f, double* g);
+int lb_set_populations(lb_sim* sim, const double* f, const double* g);
+
+/* Raw state (checkpoint): stored words of f then g plus nothing else, exactly
+ * lb_state_bytes() bytes; restoring it and stepping is bit-identical to not
+ * having stopped. */
+size_t lb_state_bytes(const lb_sim* sim);
+int lb_get_state(lb_sim* sim, void* host, size_t bytes);
+int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
+
+/* Kernel timing: when enabled, every launch made by lb_step is bracketed by
+ * HIP events on the handle's stream.  lb_kernel_times synchronises and
+ * returns, per kernel kind (0: FV predictor or single FV pass, 1: FV
+ * corrector, 2: ST), the number of launches and their total milliseconds
+ * since the last reset (arrays of length 3). */
+int lb_set_timing(lb_sim* sim, int enable);
+int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
+
+/* Number of bytes of device memory held by the handle. */
+size_t lb_device_bytes(const lb_sim* sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */
