@@ -1,0 +1,212 @@
+"""Benchmark of the FV-LB time step on one MI355X.
+
+Workload (headline): 2D Rayleigh-Benard convection, Ra = 1e10, Pr = 1,
+4096 x 4096 cells, tanh(2.5) wall refinement in y, periodic in x, D2Q9 flow
++ thermal populations, semi-implicit + Heun FV step, FP32 arithmetic with
+BF16 storage of the offsets p - w_a ref; FP64 Nusselt/energy reductions every
+1000 steps inside the timed region.  Inputs are synthetic and seeded
+(conductive profile, hydrostatic density, +-1e-3 dT noise) and resident in
+HBM before timing starts.
+
+One "step" is one full FV time step (predictor + corrector kernels) of the
+whole grid.  value = cells * steps / time in MLUPS.
+
+Also reported: the same grid with FP32 and FP16 storage, the ST step on a
+uniform grid of the same size, per-kernel durations (HIP events on the
+library's stream), the roofline of the dominant kernel and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "FV-LB MLUPS & % HBM roofline (FP32 vs BF16 storage); serving p50/p99 latency"
+KERNEL_SOURCES = ["paper_1505_03271_amd/csrc/fv.hip", "paper_1505_03271_amd/csrc/lb_device.h",
+                  "paper_1505_03271_amd/csrc/lb_kernels.h"]
+COUNTERS = os.path.join(ROOT, "profiles", "fv_rb4096_bf16_counters.json")
+STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_fv(lb, torch, cfg, storage, steps, warmup, diag_every=1000, scheme="heun"):
+    n = cfg["nx"]
+    kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
+              T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
+    sim = lb.Sim(n, n, scheme=scheme, storage=storage, stream=lb.current_stream(), **kw)
+    sim.set_grid(cfg["xf"], cfg["yf"])
+    sim.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"])
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nus = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    while done < steps:
+        k = min(diag_every, steps - done)
+        sim.step(k)
+        done += k
+        if done % diag_every == 0:
+            nus.append(sim.nusselt())  # FP64 reductions; synchronises
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = e0.elapsed_time(e1) / 1e3
+    kt = sim.kernel_times()
+    d = sim.diagnostics()
+    sim.close()
+    return dict(seconds=max(wall, ev), event_seconds=ev, wall_seconds=wall, kernels=kt, diag=d, nusselt=nus,
+                cells=n * n, steps=steps)
+
+
+def run_st(lb, torch, n, storage, steps, warmup):
+    """ST on a uniform n x n grid (dt = dx = 1), thermal RB parameters with
+    tau = tau_g = 1/2 and free-fall velocity 0.1."""
+    import workloads
+    H = float(n)
+    beta_g = 0.01 / H
+    xf = workloads.faces_uniform(n, H)
+    rho, ux, uy, T = workloads.rb_fields(n, xf, 1.0, 0.0, beta_g, seed_index=6)
+    sim = lb.Sim(n, n, scheme="st", storage=storage, thermal=True, wall_y=True, tau=0.5, tau_g=0.5,
+                 beta_g=beta_g, T_bottom=0.5, T_top=-0.5, stream=lb.current_stream())
+    sim.set_grid(xf, xf)
+    sim.init(rho, ux, uy, T)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.kernel_times()
+    sim.close()
+    return dict(seconds=wall, kernels=kt, cells=n * n, steps=steps)
+
+
+def cpu_baseline(cfg, steps=2):
+    """The FP64 oracle, as is, on `steps` steps of the full workload."""
+    import oracle
+    n = cfg["nx"]
+    c = oracle.Case(n, n, scheme="heun", thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"],
+                    tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"], T_bottom=cfg["T_bottom"],
+                    T_top=cfg["T_top"], xf=cfg["xf"], yf=cfg["yf"])
+    c.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"])
+    t0 = time.perf_counter()
+    c.step(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=n * n * steps / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample=f"{steps} FV semi-implicit+Heun steps of the full {n}x{n} thermal workload, FP64, "
+                       f"{oracle.threads()} OpenMP threads, {dt:.1f} s")
+
+
+def traffic_from_counters(launch_cells):
+    """HBM bytes per corrector launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as fh:
+        c = json.load(fh)
+    if c.get("kernel_hash") != kernel_hash() or c.get("cells") != launch_cells:
+        return None
+    return c.get("corrector_hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--storage", default="bf16")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(a multi-GPU slab decomposition is described in the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1505_03271_amd as lb
+    import workloads
+
+    torch.cuda.set_device(0)
+    cfg = workloads.rb4096_config()
+    n = cfg["nx"]
+    log(f"rb4096: dt={cfg['dt']:.3f} tau={cfg['tau']} H={cfg['H']:.0f}")
+
+    head = run_fv(lb, torch, cfg, args.storage, args.steps, args.warmup)
+    cells, K = head["cells"], head["steps"]
+    mlups = cells * K / head["seconds"] / 1e6
+    log(f"FV {args.storage}: {mlups:.0f} MLUPS ({head['seconds']:.3f} s for {K} steps)")
+
+    # roofline of the dominant kernel (per launch: one pass over all cells)
+    Q = 18
+    b = STORE_BYTES[args.storage]
+    (np_, tp), (nc, tc) = head["kernels"]["fv_first_pass"], head["kernels"]["fv_corrector"]
+    avg_p, avg_c = tp / np_ / 1e3, tc / nc / 1e3
+    if tc >= tp:
+        name, avg, per_cell = "fv_pass<corrector>", avg_c, 3 * Q * b   # reads f~n and f~*, writes f~n+1
+    else:
+        name, avg, per_cell = "fv_pass<predictor>", avg_p, 2 * Q * b   # reads f~n, writes f~*
+    achieved = per_cell * cells / avg / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells),
+            "kernel": name, "avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_cell": per_cell}
+
+    extra = {"storage": args.storage, "predictor_avg_ms": round(avg_p * 1e3, 4),
+             "corrector_avg_ms": round(avg_c * 1e3, 4),
+             "step_effective_GBps_2Qb": round(2 * Q * b * cells * K / head["seconds"] / 1e9, 1),
+             "step_compulsory_GBps_5Qb": round(5 * Q * b * cells * K / head["seconds"] / 1e9, 1),
+             "nusselt_bottom_top_vol_last": head["nusselt"][-1] if head["nusselt"] else None,
+             "nonfinite": head["diag"]["nonfinite"]}
+    if not args.no_variants:
+        vsteps = max(args.steps // 4, 50)
+        for st in ("f32", "f16"):
+            r = run_fv(lb, torch, cfg, st, vsteps, 20)
+            extra[f"fv_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
+            log(f"FV {st}: {extra[f'fv_{st}_mlups']} MLUPS")
+        for st in ("bf16", "f32"):
+            r = run_st(lb, torch, n, st, vsteps, 20)
+            extra[f"st_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
+            log(f"ST {st}: {extra[f'st_{st}_mlups']} MLUPS")
+
+    out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": round(head["seconds"] / K * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"rb4096: 2D Rayleigh-Benard Ra=1e10 Pr=1, {n}x{n}, tanh(2.5) y grid, "
+                                  f"FV semi-implicit+Heun, D2Q9 f+g, {args.storage} storage, FP32 arithmetic",
+                      "cells": cells, "storage": args.storage, "dt": cfg["dt"]},
+           "roofline": roof}
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    out["extra"] = extra
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -128,7 +128,7 @@ int lb_init(lb_sim* sim, const double* rho, const double* ux, const double* uy,
             const double* T);
 
 /* Enqueue nsteps time steps (asynchronous).  Returns LB_EUNSTABLE if an
- * earlier check (lb_diagnostics, lb_nusselt, lb_check) found non-finite
+ * earlier check (lb_diagnostics or lb_nusselt) found non-finite
  * populations, LB_ESTATE before lb_init. */
 int lb_step(lb_sim* sim, int64_t nsteps);
 
@@ -172,6 +172,10 @@ int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
  * since the last reset (arrays of length 3). */
 int lb_set_timing(lb_sim* sim, int enable);
 int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
+
+/* Rows per block of the FV kernels (a launch-shape knob for tuning; the
+ * default gives at least ~2048 blocks).  LB_EINVAL if rows < 1. */
+int lb_set_fv_chunk(lb_sim* sim, int rows);
 
 /* Number of bytes of device memory held by the handle. */
 size_t lb_device_bytes(const lb_sim* sim);

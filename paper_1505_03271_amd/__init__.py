@@ -1,0 +1,223 @@
+"""Python binding of liblb (include/lb.h): argument marshalling only.
+
+Every step of the FV-LB / ST-LB path runs in the HIP kernels of liblb.so;
+this module converts NumPy arrays and torch streams into the C ABI's plain
+pointers.  It raises if liblb.so has not been built: there is no fallback.
+
+    import paper_1505_03271_amd as lb
+    sim = lb.Sim(nx, ny, scheme="heun", storage="bf16", thermal=True, ...)
+    sim.set_grid(x_faces, y_faces)
+    sim.init(rho, ux, uy, T)
+    sim.step(1000)
+    nu_bottom, nu_top, nu_vol = sim.nusselt()
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblb.so")
+
+SCHEMES = {"heun": 0, "semi": 1, "euler": 2, "st": 3}
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+FLAG_STREAM_ONLY = 1
+STATUS = {0: "LB_OK", 1: "LB_EINVAL", 2: "LB_ENOMEM", 3: "LB_EDEVICE", 4: "LB_ESTATE", 5: "LB_EUNSTABLE"}
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("thermal", ctypes.c_int32), ("bc_x", ctypes.c_int32),
+                ("bc_y", ctypes.c_int32), ("flags", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("tau", ctypes.c_double), ("tau_g", ctypes.c_double), ("ax", ctypes.c_double),
+                ("ay", ctypes.c_double), ("beta_g", ctypes.c_double), ("T0", ctypes.c_double),
+                ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double), ("rho_ref", ctypes.c_double),
+                ("T_ref", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load liblb.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        h = ctypes.c_void_p
+        sig = {
+            "lb_create": ([ctypes.POINTER(Params), ctypes.POINTER(h)], ctypes.c_int),
+            "lb_destroy": ([h], None),
+            "lb_set_grid": ([h, _DP, ctypes.c_int64, _DP, ctypes.c_int64], ctypes.c_int),
+            "lb_grid_uniform": ([ctypes.c_int64, ctypes.c_double, _DP], ctypes.c_int),
+            "lb_grid_tanh": ([ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP], ctypes.c_int),
+            "lb_init": ([h, _DP, _DP, _DP, _DP], ctypes.c_int),
+            "lb_step": ([h, ctypes.c_int64], ctypes.c_int),
+            "lb_sync": ([h], ctypes.c_int),
+            "lb_moments": ([h, _DP, _DP, _DP, _DP], ctypes.c_int),
+            "lb_nusselt": ([h, _DP, _DP, _DP], ctypes.c_int),
+            "lb_diagnostics": ([h, _DP], ctypes.c_int),
+            "lb_get_populations": ([h, _DP, _DP], ctypes.c_int),
+            "lb_set_populations": ([h, _DP, _DP], ctypes.c_int),
+            "lb_state_bytes": ([h], ctypes.c_size_t),
+            "lb_get_state": ([h, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+            "lb_set_state": ([h, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+            "lb_set_timing": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
+            "lb_set_fv_chunk": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_device_bytes": ([h], ctypes.c_size_t),
+            "lb_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise LBError(rc, lib().lb_last_error().decode())
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous, "expected C-contiguous float64"
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        a = np.ascontiguousarray(np.broadcast_to(a, shape))
+    return a
+
+
+def grid_uniform(n, L):
+    out = np.empty(n + 1)
+    _check(lib().lb_grid_uniform(n, L, _dptr(out)))
+    return out
+
+
+def grid_tanh(n, L, stretch):
+    out = np.empty(n + 1)
+    _check(lib().lb_grid_tanh(n, L, stretch, _dptr(out)))
+    return out
+
+
+def current_stream():
+    """hipStream_t of torch's current stream on the current device."""
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Sim:
+    """One simulation handle (lb_create ... lb_destroy)."""
+
+    def __init__(self, nx, ny, scheme="heun", storage="f64", thermal=False, wall_x=False, wall_y=False,
+                 dt=1.0, tau=0.5, tau_g=0.5, ax=0.0, ay=0.0, beta_g=0.0, T0=0.0, T_bottom=0.0, T_top=0.0,
+                 rho_ref=1.0, T_ref=0.0, stream=None, stream_only=False):
+        self.nx, self.ny, self.thermal = nx, ny, bool(thermal)
+        self.scheme, self.storage = scheme, storage
+        self.p = Params(nx, ny, SCHEMES[scheme], STORAGE[storage], int(bool(thermal)), int(bool(wall_x)),
+                        int(bool(wall_y)), FLAG_STREAM_ONLY if stream_only else 0, float(dt), float(tau),
+                        float(tau_g), float(ax), float(ay), float(beta_g), float(T0), float(T_bottom),
+                        float(T_top), float(rho_ref), float(T_ref),
+                        stream.value if isinstance(stream, ctypes.c_void_p) else stream)
+        self.h = ctypes.c_void_p()
+        _check(lib().lb_create(ctypes.byref(self.p), ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().lb_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_grid(self, x_faces, y_faces):
+        x, y = _f64(x_faces), _f64(y_faces)
+        _check(lib().lb_set_grid(self.h, _dptr(x), len(x), _dptr(y), len(y)))
+
+    def init(self, rho, ux, uy, T=None):
+        shp = (self.ny, self.nx)
+        r, u, v = _f64(rho, shp), _f64(ux, shp), _f64(uy, shp)
+        t = _f64(T, shp) if T is not None else None
+        _check(lib().lb_init(self.h, _dptr(r), _dptr(u), _dptr(v), _dptr(t)))
+
+    def step(self, n=1):
+        _check(lib().lb_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().lb_sync(self.h))
+
+    def moments(self):
+        out = [np.empty((self.ny, self.nx)) for _ in range(4)]
+        _check(lib().lb_moments(self.h, *[_dptr(o) for o in out]))
+        return dict(rho=out[0], ux=out[1], uy=out[2], T=out[3])
+
+    def nusselt(self):
+        b, t, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().lb_nusselt(self.h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(v)))
+        return b.value, t.value, v.value
+
+    def diagnostics(self):
+        out = np.empty(8)
+        _check(lib().lb_diagnostics(self.h, _dptr(out)))
+        keys = ["mass", "ekin", "etherm", "nu_bottom", "nu_top", "nu_vol", "volume", "nonfinite"]
+        return dict(zip(keys, out))
+
+    def populations(self):
+        f = np.empty((9, self.ny, self.nx))
+        g = np.empty((9, self.ny, self.nx)) if self.thermal else None
+        _check(lib().lb_get_populations(self.h, _dptr(f), _dptr(g)))
+        return f, g
+
+    def set_populations(self, f, g=None):
+        shp = (9, self.ny, self.nx)
+        f = _f64(f, shp)
+        g = _f64(g, shp) if self.thermal else None
+        _check(lib().lb_set_populations(self.h, _dptr(f), _dptr(g)))
+
+    def state_bytes(self):
+        return lib().lb_state_bytes(self.h)
+
+    def get_state(self):
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        _check(lib().lb_get_state(self.h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf).view(np.uint8).reshape(-1)
+        _check(lib().lb_set_state(self.h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+
+    def set_timing(self, on=True):
+        _check(lib().lb_set_timing(self.h, int(bool(on))))
+
+    def kernel_times(self):
+        n = (ctypes.c_int64 * 3)()
+        ms = (ctypes.c_double * 3)()
+        _check(lib().lb_kernel_times(self.h, n, ms))
+        names = ["fv_first_pass", "fv_corrector", "st"]
+        return {names[k]: (int(n[k]), float(ms[k])) for k in range(3)}
+
+    def set_fv_chunk(self, rows):
+        _check(lib().lb_set_fv_chunk(self.h, int(rows)))
+
+    def device_bytes(self):
+        return lib().lb_device_bytes(self.h)

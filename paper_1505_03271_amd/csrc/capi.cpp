@@ -1,0 +1,635 @@
+// C ABI of liblb (include/lb.h): handle lifecycle, grid metric, stepping,
+// diagnostics.  No exception crosses the ABI; every entry point reports
+// failures through its return code and lb_last_error().
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "lb_kernels.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+size_t elem_size(int storage) {
+    switch (storage) {
+        case LB_F64: return 8;
+        case LB_F32: return 4;
+        default: return 2;
+    }
+}
+
+// Centre of node k (ghosts included) on an axis with faces xi[0..n].
+double node_pos(const std::vector<double>& xi, bool periodic, long k) {
+    const long n = long(xi.size()) - 1;
+    if (k >= 0 && k < n) return 0.5 * (xi[k] + xi[k + 1]);
+    if (periodic) {
+        const double L = xi[n] - xi[0];
+        long m = k % n;
+        if (m < 0) m += n;
+        return 0.5 * (xi[m] + xi[m + 1]) + double((k - m) / n) * L;
+    }
+    if (k < 0) return 2.0 * xi[0] - node_pos(xi, periodic, -k - 1);
+    return 2.0 * xi[n] - node_pos(xi, periodic, 2 * n - 1 - k);
+}
+
+// Lagrange weights at x of the parabola through nodes (a, b, c), in that order.
+void lagrange3(double x, double a, double b, double c, double* w) {
+    w[0] = (x - b) * (x - c) / ((a - b) * (a - c));
+    w[1] = (x - a) * (x - c) / ((b - a) * (b - c));
+    w[2] = (x - a) * (x - b) / ((c - a) * (c - b));
+}
+
+// QUICK face weights (sec. 2.2.3) for faces 0..n: 6 per face, laid out as
+// documented in lb_kernels.h: up = (w_P, w_E, w_W) on nodes (k-1, k, k-2),
+// dn = (w_E, w_P, w_EE) on nodes (k, k-1, k+1).
+std::vector<double> quick_weights(const std::vector<double>& xi, bool periodic) {
+    const long n = long(xi.size()) - 1;
+    std::vector<double> out(size_t(n + 1) * 6);
+    for (long k = 0; k <= n; ++k) {
+        const double xf = xi[k];
+        const double W = node_pos(xi, periodic, k - 2), P = node_pos(xi, periodic, k - 1);
+        const double E = node_pos(xi, periodic, k), EE = node_pos(xi, periodic, k + 1);
+        double w[3];
+        lagrange3(xf, P, E, W, w);
+        out[k * 6 + 0] = w[0];
+        out[k * 6 + 1] = w[1];
+        out[k * 6 + 2] = w[2];
+        lagrange3(xf, E, P, EE, w);
+        out[k * 6 + 3] = w[0];
+        out[k * 6 + 4] = w[1];
+        out[k * 6 + 5] = w[2];
+    }
+    return out;
+}
+
+// derivative at x0 of the parabola through (x0, x1, x2): weights of the values
+void d_weights(double x0, double x1, double x2, double* w) {
+    w[0] = 1.0 / (x0 - x1) + 1.0 / (x0 - x2);
+    w[1] = (x0 - x2) / ((x1 - x0) * (x1 - x2));
+    w[2] = (x0 - x1) / ((x2 - x0) * (x2 - x1));
+}
+
+}  // namespace
+
+struct lb_sim {
+    lb_params p{};
+    int nsp = 1;
+    int64_t plane = 0;
+    size_t state_bytes = 0;
+    hipStream_t stream = nullptr;
+    void* A = nullptr;  // current state
+    void* B = nullptr;  // predictor / next state
+    void* metric = nullptr;   // xw, yw, idx, idy in the compute precision
+    double* dxy = nullptr;    // dx[nx], dy[ny] in double
+    double* partial = nullptr;
+    double* dout = nullptr;
+    size_t metric_bytes = 0;
+    bool has_grid = false, has_init = false, unstable = false;
+    std::vector<double> xf, yf;
+    int chunk_h = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> kinds;  // kind of the launch that starts at event k
+    size_t n_rec = 0;
+    int64_t launches[3] = {0, 0, 0};
+    double ms[3] = {0, 0, 0};
+};
+
+namespace {
+
+int check_sim(const lb_sim* s) {
+    if (!s) return fail(LB_EINVAL, "NULL handle");
+    return LB_OK;
+}
+
+// Release every device allocation of a handle (safe on partial creation).
+void release(lb_sim* s) {
+    if (s->A) (void)hipFree(s->A);
+    if (s->B) (void)hipFree(s->B);
+    if (s->metric) (void)hipFree(s->metric);
+    if (s->dxy) (void)hipFree(s->dxy);
+    if (s->partial) (void)hipFree(s->partial);
+    if (s->dout) (void)hipFree(s->dout);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    s->events.clear();
+}
+
+AuxArgs aux_args(const lb_sim* s) {
+    AuxArgs a{};
+    a.state = s->A;
+    a.nx = s->p.nx;
+    a.ny = s->p.ny;
+    a.plane = s->plane;
+    a.thermal = s->p.thermal;
+    const double dt = s->p.scheme == LB_ST ? 1.0 : s->p.dt;
+    a.hdt = s->p.scheme == LB_FV_EULER ? 0.0 : 0.5 * dt;
+    a.ax = s->p.ax;
+    a.ay = s->p.ay;
+    a.bg = s->p.thermal ? s->p.beta_g : 0.0;
+    a.T0 = s->p.T0;
+    a.ref_f = s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref;
+    a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
+    a.dx = s->dxy;
+    a.dy = s->dxy + s->p.nx;
+    return a;
+}
+
+template <class R>
+void fill_stage_const(const lb_params& p, StageConst<R>& k) {
+    const double dt = p.dt;
+    if (p.scheme == LB_FV_EULER) {
+        k.hdt = 0; k.k1 = 0; k.kh = 0;
+        k.kc = R(dt / p.tau); k.kf = R(dt);
+        k.k1g = 0; k.kcg = R(dt / p.tau_g);
+    } else {
+        const double tt = p.tau + 0.5 * dt, ttg = p.tau_g + 0.5 * dt;
+        k.hdt = R(0.5 * dt);
+        k.k1 = R(dt / (2.0 * tt));
+        k.kh = R(0.5 * dt);
+        k.kc = R(dt / tt);
+        k.kf = R(dt * (1.0 - dt / (2.0 * tt)));
+        k.k1g = R(dt / (2.0 * ttg));
+        k.kcg = R(dt / ttg);
+    }
+    k.ax = R(p.ax);
+    k.ay = R(p.ay);
+    k.bg = R(p.thermal ? p.beta_g : 0.0);
+    k.T0 = R(p.T0);
+}
+
+template <class R>
+FvArgs<R> fv_args(const lb_sim* s, const void* src, const void* loc, void* dst, bool corrector) {
+    FvArgs<R> a{};
+    a.src = src;
+    a.loc = loc;
+    a.dst = dst;
+    a.nx = s->p.nx;
+    a.ny = s->p.ny;
+    a.plane = s->plane;
+    a.wall_x = s->p.bc_x == LB_WALL;
+    a.wall_y = s->p.bc_y == LB_WALL;
+    a.strip_w = FV_LANES - 2 * FV_HALO;
+    a.chunk_h = s->chunk_h;
+    const R* m = static_cast<const R*>(s->metric);
+    a.m.xw = m;
+    a.m.yw = m + size_t(s->p.nx + 1) * 6;
+    a.m.idx = a.m.yw + size_t(s->p.ny + 1) * 6;
+    a.m.idy = a.m.idx + s->p.nx;
+    fill_stage_const<R>(s->p, a.k);
+    a.dt_update = R(corrector ? 0.5 * s->p.dt : s->p.dt);
+    a.T_bottom = R(s->p.T_bottom);
+    a.T_top = R(s->p.T_top);
+    a.ref_f = R(s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref);
+    a.ref_g = R(s->p.storage == LB_F64 ? 0.0 : s->p.T_ref);
+    return a;
+}
+
+int record_event(lb_sim* s, int kind) {
+    if (!s->timing) return LB_OK;
+    if (s->n_rec == s->events.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        s->events.push_back(e);
+        s->kinds.push_back(-1);
+    }
+    HIP_TRY(hipEventRecord(s->events[s->n_rec], s->stream));
+    s->kinds[s->n_rec] = kind;
+    ++s->n_rec;
+    return LB_OK;
+}
+
+int fold_timing(lb_sim* s) {
+    if (s->n_rec == 0) return LB_OK;
+    HIP_TRY(hipEventSynchronize(s->events[s->n_rec - 1]));
+    for (size_t k = 0; k + 1 < s->n_rec; ++k) {
+        const int kind = s->kinds[k];
+        if (kind < 0 || kind > 2) continue;
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, s->events[k], s->events[k + 1]));
+        s->ms[kind] += t;
+        s->launches[kind] += 1;
+    }
+    s->n_rec = 0;
+    return LB_OK;
+}
+
+int fv_launch(lb_sim* s, const void* src, const void* loc, void* dst, bool corrector) {
+    const int n_strips = (s->p.nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
+    const int n_chunks = (s->p.ny + s->chunk_h - 1) / s->chunk_h;
+    int rc = record_event(s, corrector ? 1 : 0);
+    if (rc) return rc;
+    hipError_t e;
+    if (s->p.storage == LB_F64) {
+        FvArgs<double> a = fv_args<double>(s, src, loc, dst, corrector);
+        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, n_strips, n_chunks, s->stream);
+    } else {
+        FvArgs<float> a = fv_args<float>(s, src, loc, dst, corrector);
+        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, n_strips, n_chunks, s->stream);
+    }
+    if (e != hipSuccess) return fail(LB_EDEVICE, "FV kernel launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int st_launch(lb_sim* s) {
+    StArgs a{};
+    a.src = s->A;
+    a.dst = s->B;
+    a.nx = s->p.nx;
+    a.ny = s->p.ny;
+    a.plane = s->plane;
+    a.wall_x = s->p.bc_x == LB_WALL;
+    a.wall_y = s->p.bc_y == LB_WALL;
+    a.tau = s->p.tau;
+    a.tau_g = s->p.tau_g;
+    a.ax = s->p.ax;
+    a.ay = s->p.ay;
+    a.bg = s->p.thermal ? s->p.beta_g : 0.0;
+    a.T0 = s->p.T0;
+    a.T_bottom = s->p.T_bottom;
+    a.T_top = s->p.T_top;
+    a.ref_f = s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref;
+    a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
+    int rc = record_event(s, 2);
+    if (rc) return rc;
+    hipError_t e = launch_st(s->p.storage, s->p.thermal, (s->p.flags & LB_FLAG_STREAM_ONLY) != 0, a, s->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "ST kernel launch failed: %s", hipGetErrorString(e));
+    std::swap(s->A, s->B);
+    return LB_OK;
+}
+
+int run_diagnostics(lb_sim* s, double* host8) {
+    DiagArgs d{};
+    d.a = aux_args(s);
+    const int ny = s->p.ny;
+    const auto& yf = s->yf;
+    const double H = yf[ny] - yf[0];
+    const double dT = s->p.T_bottom - s->p.T_top;
+    d.walls = s->p.thermal && s->p.bc_y == LB_WALL && dT != 0.0;
+    if (d.walls) {
+        const double y0 = 0.5 * (yf[0] + yf[1]), y1 = 0.5 * (yf[1] + yf[2]);
+        const double z0 = 0.5 * (yf[ny - 1] + yf[ny]), z1 = 0.5 * (yf[ny - 2] + yf[ny - 1]);
+        d_weights(yf[0], y0, y1, d.nub);
+        d_weights(yf[ny], z0, z1, d.nut);
+        d.nu_scale = -H / dT;
+    }
+    d.Tb = s->p.T_bottom;
+    d.Tt = s->p.T_top;
+    d.inv_Lx = 1.0 / (s->xf[s->p.nx] - s->xf[0]);
+    hipError_t e = launch_diagnostics(s->p.storage, d, s->partial, s->dout, s->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "diagnostics launch failed: %s", hipGetErrorString(e));
+    double o[D_COUNT];
+    HIP_TRY(hipMemcpyAsync(o, s->dout, sizeof o, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double kappa = s->p.tau_g / 3.0;
+    host8[0] = o[D_MASS];
+    host8[1] = o[D_EKIN];
+    host8[2] = o[D_ETH];
+    host8[3] = d.walls ? o[D_NUB] : 0.0;
+    host8[4] = d.walls ? o[D_NUT] : 0.0;
+    host8[5] = d.walls ? 1.0 + H * (o[D_UT] / o[D_VOL]) / (kappa * dT) : 0.0;
+    host8[6] = o[D_VOL];
+    host8[7] = o[D_BAD];
+    if (o[D_BAD] != 0.0) s->unstable = true;
+    return LB_OK;
+}
+
+template <class T>
+int upload_temp(const T* host, size_t n, T** dev, hipStream_t st) {
+    HIP_TRY(hipMalloc(dev, n * sizeof(T)));
+    hipError_t e = hipMemcpyAsync(*dev, host, n * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        return fail(LB_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int lb_grid_uniform(int64_t n, double L, double* faces) {
+    if (n < 1 || !faces || !(L > 0)) return fail(LB_EINVAL, "lb_grid_uniform: bad arguments");
+    for (int64_t i = 0; i <= n; ++i) faces[i] = L * double(i) / double(n);
+    return LB_OK;
+}
+
+int lb_grid_tanh(int64_t n, double L, double stretch, double* faces) {
+    if (n < 1 || !faces || !(L > 0) || !(stretch > 0)) return fail(LB_EINVAL, "lb_grid_tanh: bad arguments");
+    // xi_i = L/2 (1 + tanh((2i/n - 1) atanh(s1)) / s1) with s1 = tanh(stretch)
+    const double s1 = std::tanh(stretch);
+    for (int64_t i = 0; i <= n; ++i)
+        faces[i] = 0.5 * L * (1.0 + std::tanh((2.0 * double(i) / double(n) - 1.0) * stretch) / s1);
+    faces[0] = 0.0;
+    faces[n] = L;
+    return LB_OK;
+}
+
+int lb_create(const lb_params* p, lb_sim** out) {
+    try {
+        if (!p || !out) return fail(LB_EINVAL, "lb_create: NULL argument");
+        *out = nullptr;
+        if (p->nx < 4 || p->ny < 4) return fail(LB_EINVAL, "lb_create: nx and ny must be >= 4 (got %d, %d)", p->nx, p->ny);
+        if (p->scheme < LB_FV_HEUN || p->scheme > LB_ST) return fail(LB_EINVAL, "lb_create: unknown scheme %d", p->scheme);
+        if (p->storage < LB_F64 || p->storage > LB_F16) return fail(LB_EINVAL, "lb_create: unknown storage %d", p->storage);
+        if (!(p->tau > 0) || (p->thermal && !(p->tau_g > 0))) return fail(LB_EINVAL, "lb_create: tau and tau_g must be > 0");
+        if (p->scheme != LB_ST && !(p->dt > 0)) return fail(LB_EINVAL, "lb_create: dt must be > 0");
+        if ((p->bc_x != LB_PERIODIC && p->bc_x != LB_WALL) || (p->bc_y != LB_PERIODIC && p->bc_y != LB_WALL))
+            return fail(LB_EINVAL, "lb_create: bad boundary kind");
+        if ((p->flags & LB_FLAG_STREAM_ONLY) && p->scheme != LB_ST)
+            return fail(LB_EINVAL, "lb_create: LB_FLAG_STREAM_ONLY needs LB_ST");
+        lb_sim* s = new (std::nothrow) lb_sim();
+        if (!s) return fail(LB_ENOMEM, "lb_create: out of host memory");
+        s->p = *p;
+        if (s->p.scheme == LB_ST) s->p.dt = 1.0;
+        s->nsp = p->thermal ? 2 : 1;
+        s->plane = int64_t(p->nx) * p->ny;
+        s->state_bytes = size_t(s->nsp) * 9 * size_t(s->plane) * elem_size(p->storage);
+        s->stream = static_cast<hipStream_t>(p->stream);
+        // chunk height: enough blocks to fill 256 CUs several times over
+        const int n_strips = (p->nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
+        int ch = 128;
+        while (ch > 16 && int64_t(n_strips) * ((p->ny + ch - 1) / ch) < 2048) ch /= 2;
+        s->chunk_h = ch;
+        hipError_t e;
+        if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
+            (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
+            (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess) {
+            release(s);
+            delete s;
+            return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "lb_create: device allocation failed: %s",
+                        hipGetErrorString(e));
+        }
+        *out = s;
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb_create: unexpected failure");
+    }
+}
+
+void lb_destroy(lb_sim* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    release(s);
+    delete s;
+}
+
+int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_faces, int64_t n_yf) {
+    if (int rc = check_sim(s)) return rc;
+    try {
+        if (!x_faces || !y_faces) return fail(LB_EINVAL, "lb_set_grid: NULL faces");
+        if (n_xf != s->p.nx + 1 || n_yf != s->p.ny + 1)
+            return fail(LB_EINVAL, "lb_set_grid: need nx+1 = %d and ny+1 = %d faces", s->p.nx + 1, s->p.ny + 1);
+        for (int64_t i = 0; i + 1 < n_xf; ++i)
+            if (!(x_faces[i + 1] > x_faces[i])) return fail(LB_EINVAL, "lb_set_grid: x faces not increasing at %lld", (long long)i);
+        for (int64_t i = 0; i + 1 < n_yf; ++i)
+            if (!(y_faces[i + 1] > y_faces[i])) return fail(LB_EINVAL, "lb_set_grid: y faces not increasing at %lld", (long long)i);
+        if (s->p.scheme == LB_ST) {
+            for (int64_t i = 0; i < n_xf; ++i)
+                if (std::fabs(x_faces[i] - x_faces[0] - double(i)) > 1e-12) return fail(LB_EINVAL, "lb_set_grid: ST needs unit spacing in x");
+            for (int64_t i = 0; i < n_yf; ++i)
+                if (std::fabs(y_faces[i] - y_faces[0] - double(i)) > 1e-12) return fail(LB_EINVAL, "lb_set_grid: ST needs unit spacing in y");
+        }
+        s->xf.assign(x_faces, x_faces + n_xf);
+        s->yf.assign(y_faces, y_faces + n_yf);
+        const int nx = s->p.nx, ny = s->p.ny;
+        std::vector<double> xw = quick_weights(s->xf, s->p.bc_x == LB_PERIODIC);
+        std::vector<double> yw = quick_weights(s->yf, s->p.bc_y == LB_PERIODIC);
+        std::vector<double> m;
+        m.reserve(xw.size() + yw.size() + nx + ny);
+        m.insert(m.end(), xw.begin(), xw.end());
+        m.insert(m.end(), yw.begin(), yw.end());
+        std::vector<double> dxy(size_t(nx) + ny);
+        for (int i = 0; i < nx; ++i) { dxy[i] = s->xf[i + 1] - s->xf[i]; m.push_back(1.0 / dxy[i]); }
+        for (int j = 0; j < ny; ++j) { dxy[nx + j] = s->yf[j + 1] - s->yf[j]; m.push_back(1.0 / dxy[nx + j]); }
+        if (s->metric) { (void)hipFree(s->metric); s->metric = nullptr; }
+        if (s->dxy) { (void)hipFree(s->dxy); s->dxy = nullptr; }
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (s->p.storage == LB_F64) {
+            s->metric_bytes = m.size() * sizeof(double);
+            HIP_TRY(hipMalloc(&s->metric, s->metric_bytes));
+            HIP_TRY(hipMemcpy(s->metric, m.data(), s->metric_bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> mf(m.begin(), m.end());
+            s->metric_bytes = mf.size() * sizeof(float);
+            HIP_TRY(hipMalloc(&s->metric, s->metric_bytes));
+            HIP_TRY(hipMemcpy(s->metric, mf.data(), s->metric_bytes, hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipMalloc(&s->dxy, dxy.size() * sizeof(double)));
+        HIP_TRY(hipMemcpy(s->dxy, dxy.data(), dxy.size() * sizeof(double), hipMemcpyHostToDevice));
+        s->has_grid = true;
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb_set_grid: out of host memory");
+    }
+}
+
+int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, const double* T) {
+    if (int rc = check_sim(s)) return rc;
+    if (!s->has_grid) return fail(LB_ESTATE, "lb_init: call lb_set_grid first");
+    if (!rho || !ux || !uy || (s->p.thermal && !T)) return fail(LB_EINVAL, "lb_init: NULL field");
+    const size_t n = size_t(s->plane);
+    double *d[4] = {nullptr, nullptr, nullptr, nullptr};
+    const double* h[4] = {rho, ux, uy, s->p.thermal ? T : rho};
+    int rc = LB_OK;
+    for (int q = 0; q < 4 && rc == LB_OK; ++q) rc = upload_temp(h[q], n, &d[q], s->stream);
+    if (rc == LB_OK) {
+        AuxArgs a = aux_args(s);
+        hipError_t e = launch_init(s->p.storage, a, d[0], d[1], d[2], d[3], s->stream);
+        if (e != hipSuccess) rc = fail(LB_EDEVICE, "init launch failed: %s", hipGetErrorString(e));
+        else if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) rc = fail(LB_EDEVICE, "init failed: %s", hipGetErrorString(e));
+    }
+    for (double* p : d) if (p) (void)hipFree(p);
+    if (rc == LB_OK) { s->has_init = true; s->unstable = false; }
+    return rc;
+}
+
+int lb_step(lb_sim* s, int64_t nsteps) {
+    if (int rc = check_sim(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb_step: call lb_init (or lb_set_state) first");
+    if (nsteps < 0) return fail(LB_EINVAL, "lb_step: negative step count");
+    if (s->unstable) return fail(LB_EUNSTABLE, "lb_step: non-finite populations were detected");
+    for (int64_t n = 0; n < nsteps; ++n) {
+        int rc;
+        switch (s->p.scheme) {
+            case LB_FV_HEUN:
+                if ((rc = fv_launch(s, s->A, nullptr, s->B, false))) return rc;  // f~* -> B
+                if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;       // f~n+1 -> A (in place)
+                break;
+            case LB_FV_SEMI:
+            case LB_FV_EULER:
+                if ((rc = fv_launch(s, s->A, nullptr, s->B, false))) return rc;
+                std::swap(s->A, s->B);
+                break;
+            default:
+                if ((rc = st_launch(s))) return rc;
+        }
+    }
+    if (nsteps > 0) return record_event(s, -1);
+    return LB_OK;
+}
+
+int lb_sync(lb_sim* s) {
+    if (int rc = check_sim(s)) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LB_OK;
+}
+
+int lb_moments(lb_sim* s, double* rho, double* ux, double* uy, double* T) {
+    if (int rc = check_sim(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb_moments: no state");
+    const size_t n = size_t(s->plane);
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, 4 * n * sizeof(double)));
+    AuxArgs a = aux_args(s);
+    hipError_t e = launch_moments(s->p.storage, a, d, d + n, d + 2 * n, d + 3 * n, s->stream);
+    double* h[4] = {rho, ux, uy, T};
+    for (int q = 0; q < 4 && e == hipSuccess; ++q)
+        if (h[q]) e = hipMemcpyAsync(h[q], d + q * n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_moments failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int lb_diagnostics(lb_sim* s, double* out) {
+    if (int rc = check_sim(s)) return rc;
+    if (!out) return fail(LB_EINVAL, "lb_diagnostics: NULL output");
+    if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics: no state");
+    return run_diagnostics(s, out);
+}
+
+int lb_nusselt(lb_sim* s, double* nu_bottom, double* nu_top, double* nu_vol) {
+    if (int rc = check_sim(s)) return rc;
+    if (!s->p.thermal || s->p.bc_y != LB_WALL || s->p.T_bottom == s->p.T_top)
+        return fail(LB_EINVAL, "lb_nusselt: needs a thermal run with y walls at different temperatures");
+    if (!s->has_init) return fail(LB_ESTATE, "lb_nusselt: no state");
+    double o[8];
+    if (int rc = run_diagnostics(s, o)) return rc;
+    if (nu_bottom) *nu_bottom = o[3];
+    if (nu_top) *nu_top = o[4];
+    if (nu_vol) *nu_vol = o[5];
+    return LB_OK;
+}
+
+int lb_get_populations(lb_sim* s, double* f, double* g) {
+    if (int rc = check_sim(s)) return rc;
+    if (!f) return fail(LB_EINVAL, "lb_get_populations: NULL f");
+    if (!s->has_init) return fail(LB_ESTATE, "lb_get_populations: no state");
+    const size_t n = size_t(s->nsp) * 9 * size_t(s->plane);
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = launch_get_pops(s->p.storage, aux_args(s), d, s->stream);
+    const size_t nf = 9 * size_t(s->plane);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, nf * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && s->p.thermal && g) e = hipMemcpyAsync(g, d + nf, nf * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_get_populations failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int lb_set_populations(lb_sim* s, const double* f, const double* g) {
+    if (int rc = check_sim(s)) return rc;
+    if (!f || (s->p.thermal && !g)) return fail(LB_EINVAL, "lb_set_populations: NULL input");
+    if (!s->has_grid) return fail(LB_ESTATE, "lb_set_populations: call lb_set_grid first");
+    const size_t nf = 9 * size_t(s->plane);
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, size_t(s->nsp) * nf * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, f, nf * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && s->p.thermal) e = hipMemcpyAsync(d + nf, g, nf * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_set_pops(s->p.storage, aux_args(s), d, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_set_populations failed: %s", hipGetErrorString(e));
+    s->has_init = true;
+    s->unstable = false;
+    return LB_OK;
+}
+
+size_t lb_state_bytes(const lb_sim* s) { return s ? s->state_bytes : 0; }
+
+int lb_get_state(lb_sim* s, void* host, size_t bytes) {
+    if (int rc = check_sim(s)) return rc;
+    if (!host || bytes != s->state_bytes) return fail(LB_EINVAL, "lb_get_state: need %zu bytes", s->state_bytes);
+    if (!s->has_init) return fail(LB_ESTATE, "lb_get_state: no state");
+    HIP_TRY(hipMemcpyAsync(host, s->A, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LB_OK;
+}
+
+int lb_set_state(lb_sim* s, const void* host, size_t bytes) {
+    if (int rc = check_sim(s)) return rc;
+    if (!host || bytes != s->state_bytes) return fail(LB_EINVAL, "lb_set_state: need %zu bytes", s->state_bytes);
+    if (!s->has_grid) return fail(LB_ESTATE, "lb_set_state: call lb_set_grid first");
+    HIP_TRY(hipMemcpyAsync(s->A, host, bytes, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->has_init = true;
+    s->unstable = false;
+    return LB_OK;
+}
+
+int lb_set_timing(lb_sim* s, int enable) {
+    if (int rc = check_sim(s)) return rc;
+    if (s->timing && !enable) {
+        if (int rc = fold_timing(s)) return rc;
+    }
+    s->timing = enable != 0;
+    for (int k = 0; k < 3; ++k) { s->launches[k] = 0; s->ms[k] = 0; }
+    s->n_rec = 0;
+    return LB_OK;
+}
+
+int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
+    if (int rc = check_sim(s)) return rc;
+    if (!launches || !total_ms) return fail(LB_EINVAL, "lb_kernel_times: NULL output");
+    if (int rc = fold_timing(s)) return rc;
+    for (int k = 0; k < 3; ++k) { launches[k] = s->launches[k]; total_ms[k] = s->ms[k]; }
+    return LB_OK;
+}
+
+size_t lb_device_bytes(const lb_sim* s) {
+    if (!s) return 0;
+    return 2 * s->state_bytes + s->metric_bytes + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+           sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
+}
+
+int lb_set_fv_chunk(lb_sim* s, int rows) {
+    if (int rc = check_sim(s)) return rc;
+    if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
+    s->chunk_h = rows;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Device-side building blocks shared by the liblb kernels: the D2Q9 lattice,
+// the storage codec for populations, and the local kinetic model (moments,
+// equilibrium, Guo force) of arXiv:1505.03271 sec. 2.1, 2.2.4 and sec. 5.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbk {
+
+// ---- D2Q9 lattice: index a has velocity (CX[a], CY[a]) ------------------
+// The ordering is the one documented in include/lb.h.
+__host__ __device__ constexpr int cx(int a) {
+    return a == 1 || a == 5 || a == 8 ? 1 : (a == 3 || a == 6 || a == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int a) {
+    return a == 2 || a == 5 || a == 6 ? 1 : (a == 4 || a == 7 || a == 8 ? -1 : 0);
+}
+// lattice weight by speed class: rest 4/9, axis 1/9, diagonal 1/36
+template <class R>
+__host__ __device__ constexpr R wt(int a) {
+    return a == 0 ? R(4) / R(9) : (a <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+// population moving opposite to a
+__host__ __device__ constexpr int opp(int a) {
+    return a == 0 ? 0 : (a <= 4 ? (a + 1) % 4 + 1 : (a + 1) % 4 + 5);
+}
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "D2Q9 opposite (axes)");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "D2Q9 opposite (diagonals)");
+
+// ---- storage codec -------------------------------------------------------
+// F64 is stored as is.  F32/BF16/F16 store the offset p - w_a * ref, which
+// removes the O(1) rest part so the narrow formats keep their precision for
+// the deviation from the reference state.  Conversions round to nearest even.
+struct bf16_t { uint16_t bits; };
+struct f16_t { uint16_t bits; };
+
+template <class S> struct Codec;
+
+template <> struct Codec<double> {
+    static constexpr bool offset = false;
+    template <class R> __device__ static R load(const double* p) { return R(*p); }
+    template <class R> __device__ static void store(double* p, R v) { *p = double(v); }
+};
+
+template <> struct Codec<float> {
+    static constexpr bool offset = true;
+    template <class R> __device__ static R load(const float* p) { return R(*p); }
+    template <class R> __device__ static void store(float* p, R v) { *p = float(v); }
+};
+
+__device__ inline float bf16_bits_to_float(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ inline uint16_t float_to_bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan: keep, quiet the nan
+        return uint16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);       // round to nearest, ties to even
+    return uint16_t(u >> 16);
+}
+
+template <> struct Codec<bf16_t> {
+    static constexpr bool offset = true;
+    template <class R> __device__ static R load(const bf16_t* p) { return R(bf16_bits_to_float(p->bits)); }
+    template <class R> __device__ static void store(bf16_t* p, R v) { p->bits = float_to_bf16_bits(float(v)); }
+};
+
+template <> struct Codec<f16_t> {
+    static constexpr bool offset = true;
+    template <class R> __device__ static R load(const f16_t* p) {
+        return R(__half2float(__ushort_as_half(p->bits)));
+    }
+    template <class R> __device__ static void store(f16_t* p, R v) {
+        p->bits = __half_as_ushort(__float2half_rn(float(v)));
+    }
+};
+
+// ---- local kinetic model -----------------------------------------------
+// Constants of one semi-implicit stage (eq:semi) or of the Euler step
+// (eq:euler), all precomputed on the host:
+//   hdt   velocity shift: u = sum c f / rho + hdt a   (dt/2; 0 for Euler)
+//   k1    relaxation in the advected bracket: dt/(2 tau~)      (0 for Euler)
+//   kh    force in the advected bracket: dt/2                   (0 for Euler)
+//   kc    collision: dt/tau~                                  (dt/tau for Euler)
+//   kf    force in the update: dt (1 - dt/(2 tau~))            (dt for Euler)
+//   k1g, kcg   the same two relaxation constants for g
+template <class R>
+struct StageConst {
+    R hdt, k1, kh, kc, kf, k1g, kcg;
+    R ax, ay, bg, T0;  // a = (ax, ay + bg (T - T0))
+};
+
+template <class R>
+struct Macro {
+    R rho, ux, uy, T, ax, ay;
+};
+
+template <class R, bool TH>
+__device__ inline Macro<R> macro(const R* f, const R* g, const StageConst<R>& k) {
+    Macro<R> m;
+    R rho = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        rho += f[a];
+        if (cx(a) != 0) jx += R(cx(a)) * f[a];
+        if (cy(a) != 0) jy += R(cy(a)) * f[a];
+    }
+    R T = 0;
+    if (TH) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) T += g[a];
+    }
+    m.rho = rho;
+    m.T = T;
+    m.ax = k.ax;
+    m.ay = TH ? k.ay + k.bg * (T - k.T0) : k.ay;
+    R ir = R(1) / rho;
+    m.ux = jx * ir + k.hdt * m.ax;
+    m.uy = jy * ir + k.hdt * m.ay;
+    return m;
+}
+
+// Equilibrium divided by w_a rho:  1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
+// Guo force divided by w_a rho (eq:F2):  3 (c - u).a + 9 (c.u)(c.a)
+template <class R>
+struct EqForce {
+    R poly[9];
+    R frc[9];
+};
+
+template <class R>
+__device__ inline void eq_force(const Macro<R>& m, EqForce<R>& e) {
+    const R uu = R(1.5) * (m.ux * m.ux + m.uy * m.uy);
+    const R ua = m.ux * m.ax + m.uy * m.ay;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const R cu = R(cx(a)) * m.ux + R(cy(a)) * m.uy;
+        const R ca = R(cx(a)) * m.ax + R(cy(a)) * m.ay;
+        e.poly[a] = R(1) + R(3) * cu + R(4.5) * cu * cu - uu;
+        e.frc[a] = R(3) * (ca - ua) + R(9) * cu * ca;
+    }
+}
+
+}  // namespace lbk

@@ -1,0 +1,45 @@
+"""Helpers shared by the GPU tests: run the same seeded case through liblb
+(HIP) and through the FP64 oracle."""
+import numpy as np
+
+import oracle
+import paper_1505_03271_amd as lb
+
+# storage unit roundoff (half an ulp relative to the stored magnitude)
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}
+
+_OKEYS = ("thermal", "wall_x", "wall_y", "dt", "tau", "tau_g", "ax", "ay", "beta_g", "T0", "T_bottom", "T_top")
+
+
+def make_pair(nx, ny, scheme, storage, xf, yf, fields, chunk=None, **kw):
+    """(gpu Sim, oracle Case) initialised from the same fields."""
+    import torch
+    sim = lb.Sim(nx, ny, scheme=scheme, storage=storage, stream=lb.current_stream(), **kw)
+    sim.set_grid(xf, yf)
+    if chunk:
+        sim.set_fv_chunk(chunk)
+    sim.init(*fields)
+    okw = {k: v for k, v in kw.items() if k in _OKEYS}
+    ref = oracle.Case(nx, ny, scheme=scheme, xf=xf, yf=yf, **okw)
+    ref.init(*fields)
+    torch.cuda.synchronize()
+    return sim, ref
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def offsets(p, ref_value):
+    """population minus w_a * ref (what the narrow formats store)."""
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    return p - w * ref_value
+
+
+def random_fields(nx, ny, seed, thermal=True, amp=0.03):
+    r = np.random.default_rng(seed)
+    rho = 1.0 + 0.01 * r.standard_normal((ny, nx))
+    ux = amp * r.standard_normal((ny, nx))
+    uy = amp * r.standard_normal((ny, nx))
+    T = 0.3 * r.uniform(-1, 1, (ny, nx)) if thermal else None
+    return (rho, ux, uy, T) if thermal else (rho, ux, uy)

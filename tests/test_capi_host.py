@@ -1,0 +1,73 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/lb.h declares, and rejects bad arguments before touching the
+device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1505_03271_amd as lb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lb_create", "lb_set_grid", "lb_step", "lb_moments", "lb_nusselt", "lb_init",
+                     "lb_destroy", "lb_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(lb.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, f"liblb.so lacks {missing}"
+
+
+def test_grid_helpers_match_the_paper_formula():
+    x = lb.grid_tanh(512, 512.0, 2.0)
+    assert x[0] == 0.0 and x[-1] == 512.0
+    i = np.arange(513)
+    ref = 256.0 * (1 + np.tanh((2 * i / 512 - 1) * np.arctanh(np.tanh(2.0))) / np.tanh(2.0))
+    np.testing.assert_allclose(x, ref, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(lb.grid_uniform(8, 2.0), np.arange(9) / 4.0, atol=0)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=2), "nx and ny"),
+    (dict(tau=0.0), "tau"),
+    (dict(tau=-1.0), "tau"),
+    (dict(dt=0.0), "dt"),
+    (dict(scheme="heun", stream_only=True), "STREAM_ONLY"),
+])
+def test_create_rejects_bad_parameters(kw, msg):
+    args = dict(nx=16, ny=16, scheme="heun", storage="f32", tau=0.5, dt=1.0)
+    args.update(kw)
+    nx, ny = args.pop("nx"), args.pop("ny")
+    with pytest.raises(lb.LBError) as e:
+        lb.Sim(nx, ny, **args)
+    assert e.value.code == 1 and msg in str(e.value)
+
+
+def test_bad_storage_and_scheme_codes():
+    p = lb.Params(16, 16, 0, 7, 0, 0, 0, 0, 1.0, 0.5, 0.5, 0, 0, 0, 0, 0, 0, 1.0, 0.0, None)
+    h = ctypes.c_void_p()
+    assert lb.lib().lb_create(ctypes.byref(p), ctypes.byref(h)) == 1
+    assert b"storage" in lb.lib().lb_last_error()
+    p.storage, p.scheme = 0, 9
+    assert lb.lib().lb_create(ctypes.byref(p), ctypes.byref(h)) == 1
+    assert lb.lib().lb_create(None, ctypes.byref(h)) == 1
+
+
+def test_null_handle_is_rejected():
+    assert lb.lib().lb_step(None, 1) == 1
+    assert lb.lib().lb_sync(None) == 1
+    lb.lib().lb_destroy(None)  # no-op

@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 storage runs the kernels in double precision and must agree with the
+oracle to 1e-12 relative.  The narrow formats run in FP32 and store offsets
+p - w rho_ref; their bound is derived from the storage rounding (UNIT) and
+FP32 arithmetic, per step.  Streaming alone is a permutation and must move
+tagged words bit for bit."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_03271_amd as lb
+import workloads
+from gpu_common import UNIT, make_pair, offsets, random_fields, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------ FP64 --------
+
+def test_tgv64_fv_heun_fp64_and_decay_rate():
+    cfg = workloads.tgv_config()
+    n, steps = cfg["nx"], int(round(1000 / cfg["dt"]))
+    say(f"tgv64 FV heun f64 dt={cfg['dt']} steps={steps}")
+    sim, ref = make_pair(n, n, "heun", "f64", cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"]),
+                         dt=cfg["dt"], tau=cfg["tau"])
+    E = [sim.diagnostics()["ekin"]]
+    for _ in range(5):
+        sim.step(steps // 5)
+        E.append(sim.diagnostics()["ekin"])
+    ref.step(steps)
+    f, _ = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12
+    k = 2 * math.pi / n
+    t = np.arange(6) * (steps // 5) * cfg["dt"]
+    nu = -np.polyfit(t[1:], np.log(E[1:]), 1)[0] / (4 * k * k)
+    assert abs(nu / cfg["nu"] - 1) < 0.03
+
+
+def test_tgv64_st_fp64():
+    cfg = workloads.tgv_config()
+    n = cfg["nx"]
+    say("tgv64 ST f64 1000 steps")
+    sim, ref = make_pair(n, n, "st", "f64", cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"]),
+                         tau=cfg["tau"])
+    sim.step(1000)
+    ref.step(1000)
+    f, _ = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12
+
+
+FV_CASES = [
+    dict(id="thermal-ywalls-tanh-ragged", nx=300, ny=77, wall_y=True, wall_x=False, thermal=True, chunk=16),
+    dict(id="thermal-allwalls", nx=261, ny=45, wall_y=True, wall_x=True, thermal=True, chunk=8),
+    dict(id="isothermal-periodic-force", nx=253, ny=37, wall_y=False, wall_x=False, thermal=False, chunk=32),
+    dict(id="isothermal-channel-small", nx=5, ny=64, wall_y=True, wall_x=False, thermal=False, chunk=7),
+]
+
+
+@pytest.mark.parametrize("case", FV_CASES, ids=[c["id"] for c in FV_CASES])
+@pytest.mark.parametrize("scheme", ["heun", "semi", "euler"])
+def test_fv_fp64_parity(case, scheme):
+    nx, ny = case["nx"], case["ny"]
+    say(f"FV {scheme} f64 {case['id']} {nx}x{ny}")
+    r = np.random.default_rng(nx + ny)
+    yf = workloads.faces_tanh(ny, 2.5 * ny, 1.5) if case["wall_y"] else workloads.faces_uniform(ny, float(ny))
+    xf = np.concatenate([[0.0], np.cumsum(r.uniform(0.6, 1.4, nx))]) if case["wall_x"] else workloads.faces_uniform(nx, float(nx))
+    dt = {"heun": 0.5, "semi": 0.2, "euler": 0.1}[scheme]
+    kw = dict(thermal=case["thermal"], wall_x=case["wall_x"], wall_y=case["wall_y"], dt=dt, tau=0.3,
+              tau_g=0.25, ax=2e-5, ay=-1e-5, beta_g=1e-3 if case["thermal"] else 0.0, T0=0.05,
+              T_bottom=0.5, T_top=-0.5)
+    fields = random_fields(nx, ny, nx * ny, thermal=case["thermal"])
+    sim, ref = make_pair(nx, ny, scheme, "f64", xf, yf, fields, chunk=case["chunk"], **kw)
+    sim.step(40)
+    ref.step(40)
+    f, g = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12
+    if case["thermal"]:
+        assert rel_max(g, ref.g) < 1e-12
+
+
+@pytest.mark.parametrize("walls", [(False, True), (True, True), (False, False)])
+def test_st_fp64_parity_thermal(walls):
+    nx, ny = 300, 77
+    wx, wy = walls
+    say(f"ST f64 thermal walls={walls}")
+    kw = dict(thermal=True, wall_x=wx, wall_y=wy, tau=0.2, tau_g=0.15, ax=1e-5, beta_g=2e-4,
+              T_bottom=0.5, T_top=-0.5)
+    fields = random_fields(nx, ny, 7)
+    sim, ref = make_pair(nx, ny, "st", "f64", workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny),
+                         fields, **kw)
+    sim.step(50)
+    ref.step(50)
+    f, g = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12 and rel_max(g, ref.g) < 1e-12
+
+
+def test_channel_config_fp64_short_horizon():
+    cfg = workloads.channel_config()
+    say(f"channel 256x512 FV heun f64 dt={cfg['dt']:.4f}")
+    kw = dict(wall_y=True, dt=cfg["dt"], tau=cfg["tau"], ax=cfg["ax"])
+    sim, ref = make_pair(cfg["nx"], cfg["ny"], "heun", "f64", cfg["xf"], cfg["yf"],
+                         (cfg["rho"], cfg["ux"], cfg["uy"]), **kw)
+    sim.step(20)
+    ref.step(20)
+    f, _ = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12
+
+
+def test_rb1024_config_fp64_short_horizon_and_diagnostics():
+    cfg = workloads.rb1024_config()
+    n = cfg["nx"]
+    say(f"rb1024 FV heun f64 dt={cfg['dt']:.3f}")
+    kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
+              T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
+    sim, ref = make_pair(n, n, "heun", "f64", cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"]), **kw)
+    sim.step(3)
+    ref.step(3)
+    f, g = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12 and rel_max(g, ref.g) < 1e-12
+    d, od = sim.diagnostics(), ref.diagnostics()
+    # sums are compared against the size of their terms (sum V T and the
+    # u_y T of the volume Nusselt number cancel almost completely)
+    scale = dict(mass=od["mass"], ekin=od["ekin"], volume=od["volume"],
+                 etherm=od["volume"] * np.abs(cfg["T"]).max(), nu_bottom=1.0, nu_top=1.0, nu_vol=1.0)
+    for key, s in scale.items():
+        assert abs(d[key] - od[key]) <= 1e-11 * s, key
+    # moments are sums of O(1) populations: compare on the scale of those terms
+    m, om = sim.moments(), ref.moments()
+    for key in ("rho", "ux", "uy", "T"):
+        assert np.abs(m[key] - om[key]).max() < 1e-13, key
+
+
+# ------------------------------------------------- narrow storage ---------
+
+def _narrow_bound(storage, ref_f, ref_g, steps):
+    """max abs error allowed after `steps` steps: storage rounding of the
+    initial state, of the predictor and of each result (a few half-ulps of the
+    largest stored offset per step) plus FP32 arithmetic on values of size
+    |f| <= 1."""
+    u = UNIT[storage]
+    so = max(np.abs(offsets(ref_f, 1.0)).max(), np.abs(ref_g).max() if ref_g is not None else 0.0)
+    return steps * (8 * u * so + 64 * 2.0 ** -24)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("scheme", ["heun", "st"])
+def test_narrow_storage_against_oracle(storage, scheme):
+    nx, ny = 300, 77
+    say(f"{scheme} {storage} thermal ragged")
+    if scheme == "st":
+        xf, yf = workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny)
+    else:
+        xf, yf = workloads.faces_uniform(nx, 3.0 * nx), workloads.faces_tanh(ny, 3.0 * ny, 2.0)
+    kw = dict(thermal=True, wall_y=True, dt=0.5, tau=0.3, tau_g=0.25, ax=1e-5, beta_g=1e-3, T_bottom=0.5,
+              T_top=-0.5)
+    fields = random_fields(nx, ny, 11)
+    sim, ref = make_pair(nx, ny, scheme, storage, xf, yf, fields, chunk=16, **kw)
+    for steps in (1, 5):
+        sim.step(1 if steps == 1 else 4)
+        ref.step(1 if steps == 1 else 4)
+        f, g = sim.populations()
+        bound = _narrow_bound(storage, ref.f, ref.g, steps)
+        ef, eg = np.abs(f - ref.f).max(), np.abs(g - ref.g).max()
+        say(f"  steps={steps} err f={ef:.3e} g={eg:.3e} bound={bound:.3e}")
+        assert ef < bound and eg < bound
+
+
+def test_full_size_rb4096_bf16_one_step():
+    """The benchmark's workload and launch shape (4096^2, BF16 storage,
+    default chunking): one full step against the oracle on every cell."""
+    cfg = workloads.rb4096_config()
+    n = cfg["nx"]
+    say(f"rb4096 heun bf16 one step dt={cfg['dt']:.3f}")
+    kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
+              T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
+    sim, ref = make_pair(n, n, "heun", "bf16", cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"]), **kw)
+    sim.step(1)
+    ref.step(1)
+    f, g = sim.populations()
+    bound = _narrow_bound("bf16", ref.f, ref.g, 1)
+    ef, eg = np.abs(f - ref.f).max(), np.abs(g - ref.g).max()
+    say(f"  err f={ef:.3e} g={eg:.3e} bound={bound:.3e}")
+    assert ef < bound and eg < bound
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0.0
+
+
+# ------------------------------------------------ streaming permutation ----
+
+def _tags(storage, count, seed):
+    r = np.random.default_rng(seed)
+    if storage in ("f32", "f64"):
+        vals = r.permutation(count).astype(np.float32 if storage == "f32" else np.float64)
+        return vals.view(np.uint32 if storage == "f32" else np.uint64)
+    bits = np.arange(65536, dtype=np.uint32)
+    if storage == "bf16":
+        finite = bits[(bits & 0x7F80) != 0x7F80]
+    else:
+        finite = bits[(bits & 0x7C00) != 0x7C00]
+    assert count <= finite.size
+    return r.permutation(finite)[:count].astype(np.uint16)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("thermal,walls", [(False, (False, False)), (False, (False, True)), (True, (True, True))])
+def test_st_streaming_permutation_bit_exact(storage, thermal, walls):
+    nx, ny = (64, 64) if not thermal else (48, 40)
+    say(f"ST stream-only {storage} thermal={thermal} walls={walls}")
+    sim = lb.Sim(nx, ny, scheme="st", storage=storage, thermal=thermal, wall_x=walls[0], wall_y=walls[1],
+                 tau=0.5, tau_g=0.5, stream=lb.current_stream(), stream_only=True)
+    sim.set_grid(workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny))
+    nsp = 2 if thermal else 1
+    N = 9 * nx * ny
+    tags = _tags(storage, nsp * N, 5)
+    sim.set_state(tags)
+    ref = oracle.Case(nx, ny, scheme="st", wall_x=walls[0], wall_y=walls[1])
+    src = ref.stream_sources()
+    expect = tags.copy()
+    for step in range(3):
+        sim.step(1)
+        new = np.empty_like(expect)
+        for s in range(nsp):
+            new[s * N:(s + 1) * N] = expect[s * N:(s + 1) * N][src]
+        expect = new
+        got = sim.get_state().view(tags.dtype)
+        assert np.array_equal(got, expect), f"step {step + 1}"
+
+
+# ------------------------------------------------------ lifecycle ----------
+
+def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic():
+    nx, ny = 300, 77
+    say("checkpoint / determinism bf16")
+    kw = dict(thermal=True, wall_y=True, dt=0.5, tau=0.3, tau_g=0.25, beta_g=1e-3, T_bottom=0.5, T_top=-0.5)
+    fields = random_fields(nx, ny, 3)
+    xf, yf = workloads.faces_uniform(nx, 3.0 * nx), workloads.faces_tanh(ny, 3.0 * ny, 2.0)
+    sim, _ = make_pair(nx, ny, "heun", "bf16", xf, yf, fields, **kw)
+    sim.step(10)
+    saved = sim.get_state()
+    sim.step(10)
+    a = sim.get_state()
+    sim.set_state(saved)
+    sim.step(10)
+    b = sim.get_state()
+    assert np.array_equal(a, b)
+    for chunk in (8, 77, 1000):
+        other, _ = make_pair(nx, ny, "heun", "bf16", xf, yf, fields, chunk=chunk, **kw)
+        other.step(20)
+        assert np.array_equal(other.get_state(), a), f"chunk {chunk}"
+
+
+def test_nonfinite_population_is_reported():
+    nx, ny = 64, 32
+    say("non-finite detection")
+    sim, _ = make_pair(nx, ny, "heun", "f32", workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny),
+                       random_fields(nx, ny, 1, thermal=False), dt=0.5, tau=0.3)
+    f, _ = sim.populations()
+    f[3, 10, 20] = np.nan
+    sim.set_populations(f)
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 1.0
+    with pytest.raises(lb.LBError) as e:
+        sim.step(1)
+    assert e.value.code == 5
+
+
+def test_call_order_errors():
+    say("call order")
+    sim = lb.Sim(16, 16, scheme="heun", storage="f32", dt=0.5, tau=0.3, stream=lb.current_stream())
+    with pytest.raises(lb.LBError) as e:
+        sim.step(1)
+    assert e.value.code == 4
+    with pytest.raises(lb.LBError) as e:
+        sim.init(np.ones((16, 16)), np.zeros((16, 16)), np.zeros((16, 16)))
+    assert e.value.code == 4
+    with pytest.raises(lb.LBError) as e:
+        sim.set_grid(np.arange(16.0), np.arange(17.0))
+    assert e.value.code == 1
+    st = lb.Sim(16, 16, scheme="st", storage="f32", tau=0.3, stream=lb.current_stream())
+    with pytest.raises(lb.LBError):
+        st.set_grid(np.arange(17.0) * 0.5, np.arange(17.0))
+    with pytest.raises(lb.LBError):
+        sim.nusselt()
