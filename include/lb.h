@@ -173,8 +173,10 @@ int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
 int lb_set_timing(lb_sim* sim, int enable);
 int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
 
-/* Rows per block of the FV kernels (a launch-shape knob for tuning; the
- * default gives at least ~2048 blocks).  LB_EINVAL if rows < 1. */
+/* Rows per work item of the FV kernels (a launch-shape knob for tuning).
+ * By default the height is chosen at the first step so that every item of a
+ * launch is resident at once.  Any height >= 1 gives identical results.
+ * LB_EINVAL if rows < 1. */
 int lb_set_fv_chunk(lb_sim* sim, int rows);
 
 /* Number of bytes of device memory held by the handle. */

@@ -8,16 +8,19 @@
 
 namespace lbk {
 
+// population a of species sp at cell c, decoded to double
 template <class S>
-__device__ inline double get_pop(const S* base, int64_t plane, int a, int64_t cell, double ref) {
-    double x = Codec<S>::template load<double>(base + a * plane + cell);
+__device__ inline double get_pop(const AuxArgs& A, const S* st, int sp, int a, int64_t c, double ref) {
+    const int nsp = A.thermal ? 2 : 1;
+    double x = Codec<S>::template load<double>(st + pop_index(A.grouped, nsp, A.plane, sp, a, c));
     return Codec<S>::offset ? x + wt<double>(a) * ref : x;
 }
 
 template <class S>
-__device__ inline void put_pop(S* base, int64_t plane, int a, int64_t cell, double ref, double v) {
+__device__ inline void put_pop(const AuxArgs& A, S* st, int sp, int a, int64_t c, double ref, double v) {
+    const int nsp = A.thermal ? 2 : 1;
     double x = Codec<S>::offset ? v - wt<double>(a) * ref : v;
-    Codec<S>::template store<double>(base + a * plane + cell, x);
+    Codec<S>::template store<double>(st + pop_index(A.grouped, nsp, A.plane, sp, a, c), x);
 }
 
 __device__ inline StageConst<double> aux_const(const AuxArgs& a) {
@@ -47,8 +50,8 @@ __global__ void init_kernel(AuxArgs A, const double* rho, const double* ux, cons
     eq_force(m, e);
     for (int a = 0; a < 9; ++a) {
         const double wr = wt<double>(a) * m.rho;
-        put_pop(st, A.plane, a, c, A.ref_f, wr * e.poly[a] - A.hdt * wr * e.frc[a]);
-        if (A.thermal) put_pop(st + 9 * A.plane, A.plane, a, c, A.ref_g, wt<double>(a) * m.T * e.poly[a]);
+        put_pop(A, st, 0, a, c, A.ref_f, wr * e.poly[a] - A.hdt * wr * e.frc[a]);
+        if (A.thermal) put_pop(A, st, 1, a, c, A.ref_g, wt<double>(a) * m.T * e.poly[a]);
     }
 }
 
@@ -57,8 +60,8 @@ __device__ inline Macro<double> cell_macro(const AuxArgs& A, int64_t c) {
     const S* st = static_cast<const S*>(A.state);
     double f[9], g[9];
     for (int a = 0; a < 9; ++a) {
-        f[a] = get_pop(st, A.plane, a, c, A.ref_f);
-        g[a] = A.thermal ? get_pop(st + 9 * A.plane, A.plane, a, c, A.ref_g) : 0.0;
+        f[a] = get_pop(A, st, 0, a, c, A.ref_f);
+        g[a] = A.thermal ? get_pop(A, st, 1, a, c, A.ref_g) : 0.0;
     }
     StageConst<double> k = aux_const(A);
     return A.thermal ? macro<double, true>(f, g, k) : macro<double, false>(f, g, k);
@@ -83,7 +86,7 @@ __global__ void get_pops_kernel(AuxArgs A, double* out) {
     const int ns = A.thermal ? 2 : 1;
     for (int s = 0; s < ns; ++s)
         for (int a = 0; a < 9; ++a)
-            out[(s * 9 + a) * A.plane + c] = get_pop(st + s * 9 * A.plane, A.plane, a, c, s ? A.ref_g : A.ref_f);
+            out[(s * 9 + a) * A.plane + c] = get_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f);
 }
 
 template <class S>
@@ -94,7 +97,7 @@ __global__ void set_pops_kernel(AuxArgs A, const double* in) {
     const int ns = A.thermal ? 2 : 1;
     for (int s = 0; s < ns; ++s)
         for (int a = 0; a < 9; ++a)
-            put_pop(st + s * 9 * A.plane, A.plane, a, c, s ? A.ref_g : A.ref_f, in[(s * 9 + a) * A.plane + c]);
+            put_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f, in[(s * 9 + a) * A.plane + c]);
 }
 
 // ---- diagnostics -------------------------------------------------------
@@ -131,7 +134,7 @@ __global__ void __launch_bounds__(256) diag_kernel(DiagArgs D, double* partial) 
         acc[D_VOL] += v;
         for (int s = 0; s < ns; ++s)
             for (int a = 0; a < 9; ++a) {
-                const double p = get_pop(st + s * 9 * A.plane, A.plane, a, c, 0.0);
+                const double p = get_pop(A, st, s, a, c, 0.0);
                 if (!isfinite(p)) acc[D_BAD] = 1.0;
             }
         if (D.walls && (j == 0 || j == A.ny - 1)) {

@@ -3,6 +3,7 @@
 // failures through its return code and lb_last_error().
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -89,6 +90,33 @@ std::vector<double> quick_weights(const std::vector<double>& xi, bool periodic) 
     return out;
 }
 
+// Four-point flux stencils of every cell of an axis (n cells, face weights fw
+// from quick_weights): D * scale = sum coef * phi, with coef[0..3] on nodes
+// i-2 .. i+1 for c = +1 and coef[4..7] on nodes i-1 .. i+2 for c = -1,
+// scale = factor / width_i.  They combine the two faces of the cell:
+//   c = +1:  D = ([phi]_{i+1/2} - [phi]_{i-1/2}) / dx_i
+//   c = -1:  D = -([phi]_{i+1/2} - [phi]_{i-1/2}) / dx_i
+std::vector<double> flux_stencils(const std::vector<double>& xi, const std::vector<double>& fw, double factor) {
+    const size_t n = xi.size() - 1;
+    std::vector<double> out(n * 8);
+    for (size_t i = 0; i < n; ++i) {
+        const double* L = &fw[i * 6];        // face i     (between i-1 and i)
+        const double* Rr = &fw[(i + 1) * 6]; // face i + 1 (between i and i+1)
+        const double sc = factor / (xi[i + 1] - xi[i]);
+        // c = +1: face value up0 P + up1 E + up2 W
+        out[i * 8 + 0] = sc * (-L[2]);
+        out[i * 8 + 1] = sc * (Rr[2] - L[0]);
+        out[i * 8 + 2] = sc * (Rr[0] - L[1]);
+        out[i * 8 + 3] = sc * (Rr[1]);
+        // c = -1: face value dn0 E + dn1 P + dn2 EE, flux sign -1
+        out[i * 8 + 4] = sc * (L[4]);
+        out[i * 8 + 5] = sc * (L[3] - Rr[4]);
+        out[i * 8 + 6] = sc * (L[5] - Rr[3]);
+        out[i * 8 + 7] = sc * (-Rr[5]);
+    }
+    return out;
+}
+
 // derivative at x0 of the parabola through (x0, x1, x2): weights of the values
 void d_weights(double x0, double x1, double x2, double* w) {
     w[0] = 1.0 / (x0 - x1) + 1.0 / (x0 - x2);
@@ -106,7 +134,8 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     void* A = nullptr;  // current state
     void* B = nullptr;  // predictor / next state
-    void* metric = nullptr;   // xw, yw, idx, idy in the compute precision
+    void* H = nullptr;  // (f~n + C)/2 between the Heun predictor and corrector
+    void* metric = nullptr;   // flux stencils: x pass0, y pass0, x pass1, y pass1 ([n][8] each)
     double* dxy = nullptr;    // dx[nx], dy[ny] in double
     double* partial = nullptr;
     double* dout = nullptr;
@@ -134,6 +163,7 @@ int check_sim(const lb_sim* s) {
 void release(lb_sim* s) {
     if (s->A) (void)hipFree(s->A);
     if (s->B) (void)hipFree(s->B);
+    if (s->H) (void)hipFree(s->H);
     if (s->metric) (void)hipFree(s->metric);
     if (s->dxy) (void)hipFree(s->dxy);
     if (s->partial) (void)hipFree(s->partial);
@@ -159,56 +189,68 @@ AuxArgs aux_args(const lb_sim* s) {
     a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
     a.dx = s->dxy;
     a.dy = s->dxy + s->p.nx;
+    a.grouped = s->p.scheme != LB_ST;
     return a;
 }
 
 template <class R>
-void fill_stage_const(const lb_params& p, StageConst<R>& k) {
+void fill_stage_k(const lb_params& p, StageK<R>& k) {
     const double dt = p.dt;
+    const bool f64 = p.storage == LB_F64;
+    const double rf = f64 ? 0.0 : p.rho_ref, rg = f64 ? 0.0 : p.T_ref;
+    double hdt, k1, kh, kc, kf, k1g, kcg;
     if (p.scheme == LB_FV_EULER) {
-        k.hdt = 0; k.k1 = 0; k.kh = 0;
-        k.kc = R(dt / p.tau); k.kf = R(dt);
-        k.k1g = 0; k.kcg = R(dt / p.tau_g);
+        hdt = 0; k1 = 0; kh = 0; kc = dt / p.tau; kf = dt; k1g = 0; kcg = dt / p.tau_g;
     } else {
         const double tt = p.tau + 0.5 * dt, ttg = p.tau_g + 0.5 * dt;
-        k.hdt = R(0.5 * dt);
-        k.k1 = R(dt / (2.0 * tt));
-        k.kh = R(0.5 * dt);
-        k.kc = R(dt / tt);
-        k.kf = R(dt * (1.0 - dt / (2.0 * tt)));
-        k.k1g = R(dt / (2.0 * ttg));
-        k.kcg = R(dt / ttg);
+        hdt = 0.5 * dt; k1 = dt / (2.0 * tt); kh = 0.5 * dt; kc = dt / tt; kf = dt * (1.0 - dt / (2.0 * tt));
+        k1g = dt / (2.0 * ttg); kcg = dt / ttg;
     }
+    const double w[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    k.hdt = R(hdt);
     k.ax = R(p.ax);
     k.ay = R(p.ay);
     k.bg = R(p.thermal ? p.beta_g : 0.0);
     k.T0 = R(p.T0);
+    k.ref_f = R(rf);
+    k.ref_g = R(rg);
+    k.k1 = R(k1); k.kh = R(kh); k.k1x3 = R(3 * k1); k.khx3 = R(3 * kh); k.omk1 = R(1 - k1);
+    k.k1g = R(k1g); k.omk1g = R(1 - k1g);
+    k.kc = R(kc); k.kf = R(kf); k.kcx3 = R(3 * kc); k.kfx3 = R(3 * kf); k.omkc = R(1 - kc); k.omkcg = R(1 - kcg);
+    for (int c = 0; c < 3; ++c) {
+        k.kcwref[c] = R(kc * w[c] * rf);
+        k.kcgw[c] = R(kcg * w[c]);
+    }
 }
 
 template <class R>
-FvArgs<R> fv_args(const lb_sim* s, const void* src, const void* loc, void* dst, bool corrector) {
+FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool corrector) {
     FvArgs<R> a{};
     a.src = src;
-    a.loc = loc;
     a.dst = dst;
+    a.aux = aux;
+    const size_t es = elem_size(s->p.storage);
+    a.state_bytes = uint32_t(s->state_bytes);
+    a.group_bytes = uint32_t(4 * size_t(s->plane) * es);
+    a.rest_off = uint32_t(8 * size_t(s->nsp) * size_t(s->plane) * es);
     a.nx = s->p.nx;
     a.ny = s->p.ny;
-    a.plane = s->plane;
     a.wall_x = s->p.bc_x == LB_WALL;
     a.wall_y = s->p.bc_y == LB_WALL;
     a.strip_w = FV_LANES - 2 * FV_HALO;
     a.chunk_h = s->chunk_h;
+    a.n_strips = (s->p.nx + a.strip_w - 1) / a.strip_w;
+    a.n_items = a.n_strips * ((s->p.ny + a.chunk_h - 1) / a.chunk_h);
     const R* m = static_cast<const R*>(s->metric);
-    a.m.xw = m;
-    a.m.yw = m + size_t(s->p.nx + 1) * 6;
-    a.m.idx = a.m.yw + size_t(s->p.ny + 1) * 6;
-    a.m.idy = a.m.idx + s->p.nx;
-    fill_stage_const<R>(s->p, a.k);
-    a.dt_update = R(corrector ? 0.5 * s->p.dt : s->p.dt);
-    a.T_bottom = R(s->p.T_bottom);
-    a.T_top = R(s->p.T_top);
-    a.ref_f = R(s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref);
-    a.ref_g = R(s->p.storage == LB_F64 ? 0.0 : s->p.T_ref);
+    const size_t nx8 = size_t(s->p.nx) * 8, ny8 = size_t(s->p.ny) * 8;
+    const R* pass = m + (corrector ? nx8 + ny8 : 0);
+    a.xcoef = pass;
+    a.ycoef = pass + nx8;
+    fill_stage_k<R>(s->p, a.k);
+    const double k1g = s->p.scheme == LB_FV_EULER ? 0.0 : s->p.dt / (2.0 * (s->p.tau_g + 0.5 * s->p.dt));
+    const double rg = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
+    a.Twb = R(s->p.T_bottom - (1.0 - k1g) * rg);
+    a.Twt = R(s->p.T_top - (1.0 - k1g) * rg);
     return a;
 }
 
@@ -241,18 +283,29 @@ int fold_timing(lb_sim* s) {
     return LB_OK;
 }
 
-int fv_launch(lb_sim* s, const void* src, const void* loc, void* dst, bool corrector) {
+// Rows per FV work item: as tall as possible while every item of a launch
+// is resident at once (one item per block), in steps of four rows.
+int auto_chunk(const lb_sim* s) {
     const int n_strips = (s->p.nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
-    const int n_chunks = (s->p.ny + s->chunk_h - 1) / s->chunk_h;
+    int cap = fv_resident_blocks(s->p.storage, s->p.thermal, false);
+    if (cap <= 0) cap = 512;
+    const int chunks = std::max(1, cap / n_strips);
+    int h = (s->p.ny + chunks - 1) / chunks;
+    h = ((h + 3) / 4) * 4;
+    return std::max(8, h);
+}
+
+int fv_launch(lb_sim* s, const void* src, void* dst, void* aux, bool corrector) {
+    if (s->chunk_h <= 0) s->chunk_h = auto_chunk(s);
     int rc = record_event(s, corrector ? 1 : 0);
     if (rc) return rc;
     hipError_t e;
     if (s->p.storage == LB_F64) {
-        FvArgs<double> a = fv_args<double>(s, src, loc, dst, corrector);
-        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, n_strips, n_chunks, s->stream);
+        FvArgs<double> a = fv_args<double>(s, src, dst, aux, corrector);
+        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, s->stream);
     } else {
-        FvArgs<float> a = fv_args<float>(s, src, loc, dst, corrector);
-        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, n_strips, n_chunks, s->stream);
+        FvArgs<float> a = fv_args<float>(s, src, dst, aux, corrector);
+        e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, s->stream);
     }
     if (e != hipSuccess) return fail(LB_EDEVICE, "FV kernel launch failed: %s", hipGetErrorString(e));
     return LB_OK;
@@ -369,6 +422,8 @@ int lb_create(const lb_params* p, lb_sim** out) {
             return fail(LB_EINVAL, "lb_create: bad boundary kind");
         if ((p->flags & LB_FLAG_STREAM_ONLY) && p->scheme != LB_ST)
             return fail(LB_EINVAL, "lb_create: LB_FLAG_STREAM_ONLY needs LB_ST");
+        if ((p->thermal ? 18ull : 9ull) * uint64_t(p->nx) * uint64_t(p->ny) * elem_size(p->storage) >= (1ull << 32))
+            return fail(LB_EINVAL, "lb_create: the population state must be smaller than 4 GiB (nx*ny too large for this storage)");
         lb_sim* s = new (std::nothrow) lb_sim();
         if (!s) return fail(LB_ENOMEM, "lb_create: out of host memory");
         s->p = *p;
@@ -377,13 +432,10 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->plane = int64_t(p->nx) * p->ny;
         s->state_bytes = size_t(s->nsp) * 9 * size_t(s->plane) * elem_size(p->storage);
         s->stream = static_cast<hipStream_t>(p->stream);
-        // chunk height: enough blocks to fill 256 CUs several times over
-        const int n_strips = (p->nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
-        int ch = 128;
-        while (ch > 16 && int64_t(n_strips) * ((p->ny + ch - 1) / ch) < 2048) ch /= 2;
-        s->chunk_h = ch;
+        s->chunk_h = 0;  // chosen at the first FV launch from the occupancy
         hipError_t e;
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
+            (p->scheme == LB_FV_HEUN && fv_heun_h() && (e = hipMalloc(&s->H, s->state_bytes)) != hipSuccess) ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess) {
             release(s);
@@ -426,13 +478,16 @@ int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_
         const int nx = s->p.nx, ny = s->p.ny;
         std::vector<double> xw = quick_weights(s->xf, s->p.bc_x == LB_PERIODIC);
         std::vector<double> yw = quick_weights(s->yf, s->p.bc_y == LB_PERIODIC);
+        // pass 0: predictor / single pass (factor dt); pass 1: Heun corrector (dt/2)
         std::vector<double> m;
-        m.reserve(xw.size() + yw.size() + nx + ny);
-        m.insert(m.end(), xw.begin(), xw.end());
-        m.insert(m.end(), yw.begin(), yw.end());
+        for (double factor : {s->p.dt, 0.5 * s->p.dt}) {
+            std::vector<double> a = flux_stencils(s->xf, xw, factor), b = flux_stencils(s->yf, yw, factor);
+            m.insert(m.end(), a.begin(), a.end());
+            m.insert(m.end(), b.begin(), b.end());
+        }
         std::vector<double> dxy(size_t(nx) + ny);
-        for (int i = 0; i < nx; ++i) { dxy[i] = s->xf[i + 1] - s->xf[i]; m.push_back(1.0 / dxy[i]); }
-        for (int j = 0; j < ny; ++j) { dxy[nx + j] = s->yf[j + 1] - s->yf[j]; m.push_back(1.0 / dxy[nx + j]); }
+        for (int i = 0; i < nx; ++i) dxy[i] = s->xf[i + 1] - s->xf[i];
+        for (int j = 0; j < ny; ++j) dxy[nx + j] = s->yf[j + 1] - s->yf[j];
         if (s->metric) { (void)hipFree(s->metric); s->metric = nullptr; }
         if (s->dxy) { (void)hipFree(s->dxy); s->dxy = nullptr; }
         HIP_TRY(hipStreamSynchronize(s->stream));
@@ -484,12 +539,17 @@ int lb_step(lb_sim* s, int64_t nsteps) {
         int rc;
         switch (s->p.scheme) {
             case LB_FV_HEUN:
-                if ((rc = fv_launch(s, s->A, nullptr, s->B, false))) return rc;  // f~* -> B
-                if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;       // f~n+1 -> A (in place)
+                if (fv_heun_h()) {
+                    if ((rc = fv_launch(s, s->A, s->B, s->H, false))) return rc;  // f~* -> B, H
+                    if ((rc = fv_launch(s, s->B, s->A, s->H, true))) return rc;   // f~n+1 -> A
+                } else {
+                    if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
+                    if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
+                }
                 break;
             case LB_FV_SEMI:
             case LB_FV_EULER:
-                if ((rc = fv_launch(s, s->A, nullptr, s->B, false))) return rc;
+                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;
                 std::swap(s->A, s->B);
                 break;
             default:
@@ -621,7 +681,7 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return 2 * s->state_bytes + s->metric_bytes + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return (s->H ? 3 : 2) * s->state_bytes + s->metric_bytes + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
 }
 

@@ -1,93 +1,337 @@
 // Finite-volume lattice Boltzmann stage kernel (arXiv:1505.03271 sec. 2.2).
 //
-// One launch evaluates, for every cell, one semi-implicit stage fused with
-// the QUICK face fluxes:
-//   phi = f~ + dt/(2 tau~)(f_eq - f~) + dt/2 F         (advected bracket, eq:semi)
-//   C   = dt/tau~ (f_eq - f~) + dt (1 - dt/(2 tau~)) F  (collision + force)
-//   D   = sum_faces (S/V) c.n [phi]_face                (QUICK, sec. 2.2.3)
-// and writes
-//   predictor / single pass:  f~*   = f~n - dt D(phi(f~n)) + C(f~n)          (eq:semi)
-//   corrector:                f~n+1 = (f~n + f~* + C(f~n))/2 - dt/2 D(phi(f~*))
-// The corrector form is eq:semi-heun rewritten with f~* = f~n - dt Dn + Cn,
-// so D(phi(f~n)) never has to be recomputed and f~n+1 can overwrite f~n: each
-// cell reads f~n only at itself, and f~* (with halo) from the other buffer.
+// Two launches make one semi-implicit + Heun step (eq:semi-heun):
+//   predictor:  f~* = f~n - dt D(phi(f~n)) + C(f~n)            (eq:semi)
+//               H   = (f~n + C(f~n)) / 2
+//   corrector:  f~n+1 = H + f~*/2 - dt/2 D(phi(f~*))
+// with, per population (sec. 2.2.2 and the force term of sec. 2.2.4),
+//   phi = f~ + dt/(2 tau~)(f_eq - f~) + dt/2 F          (advected bracket)
+//   C   = dt/tau~ (f_eq - f~) + dt (1 - dt/(2 tau~)) F   (collision + force)
+//   D   = sum_faces (S/V) c.n [phi]_face                 (QUICK, sec. 2.2.3)
+// The corrector is eq:semi-heun rearranged with f~* = f~n - dt Dn + Cn, so
+// D(phi(f~n)) is never needed twice.  The single-pass schemes (eq:semi,
+// eq:euler) use the predictor alone with their own constants.
 //
-// Mapping: a block of FV_LANES lanes owns a strip of up to FV_LANES - 4
-// consecutive columns plus two halo columns on each side (one lane per
-// column) and marches up a chunk of rows.  Each row is loaded once with
-// coalesced accesses (x fastest in every population plane), the stage is
-// evaluated once per cell, x-face neighbours are exchanged through LDS
-// (double buffered, one barrier per row), and y-face neighbours are kept in a
-// rolling register window of the last rows.  The y-face weights and 1/dy are
-// uniform over the block (scalar loads); the x-face weights are per lane and
-// stay in registers for the whole march.
+// Offset arithmetic.  Populations are handled as offsets d = p - w_a ref
+// (ref = rho_ref for f, T_ref for g; ref = 0 for FP64 storage), exactly as
+// they are stored.  Moments are rho = sum d + ref, j = sum c d, T = sum d_g +
+// T_ref.  The advected bracket is carried as phi - (1 - k1) w_a ref: the
+// QUICK weights of a cell sum to zero, so a constant shift per population
+// cancels from D.  Collision outputs are produced directly as offsets.
 //
-// Boundaries ("Boundary conditions" of sec. 2.2): the advected bracket phi of
-// a ghost cell is that of its mirror cell with the opposite population
-// (double reflection); for g on the y walls the anti-reflection
-// -phi_inv(a) + 2 w_a T_w imposes the wall temperature.  Periodic axes wrap.
+// Equilibrium and force are split by population pairs (a, inv(a)): with
+// cu = c.u and ca = c.a,
+//   f_eq / (w rho) = E +- O,   E = 1 + 9/2 cu^2 - 3/2 u.u,   O = 3 cu
+//   F    / (w rho) = Fe +- Fo, Fe = 9 cu ca - 3 u.a,          Fo = 3 ca
+// (Guo force, eq:F2, with cs^2 = 1/3).
+//
+// Flux.  For every cell the x (y) contribution of a population is a
+// four-point stencil of phi along that axis; its weights combine the QUICK
+// coefficients of the two faces, the sign of c, S/V = 1/dx and the update
+// factor (dt, or dt/2 in the corrector) and are precomputed on the host:
+//   c > 0:  nodes i-2 .. i+1,   c < 0:  nodes i-1 .. i+2.
+//
+// Mapping.  A block of FV_LANES lanes owns a strip of up to FV_LANES - 4
+// consecutive columns plus two halo columns on each side, one lane per
+// column, and marches up a chunk of rows.  Each row is read once with
+// coalesced buffer loads (x fastest in every population plane; one scalar
+// offset per plane), the stage is evaluated once per cell, x neighbours come
+// through LDS (double buffered, one barrier per row) and y neighbours from a
+// ring of the last four rows kept in registers (the march is unrolled by four
+// so the ring needs no moves).  y weights are uniform over the block (scalar
+// loads); x weights are per lane and stay in registers.
+//
+// Boundaries ("Boundary conditions" of sec. 2.2): the bracket of a ghost cell
+// is the mirror cell's with the opposite population (double reflection); for
+// g on the y walls it is 2 w_a T_w - phi_inv(a) (isothermal anti-reflection).
+// Periodic axes wrap.
 #include "lb_kernels.h"
 
 namespace lbk {
 
-// populations with c_x != 0, in the order (+1, +1, +1, -1, -1, -1)
+// population pairs (a, inv(a)) with c_a = (PX, PY)
+__device__ constexpr int pa(int p) { return p == 0 ? 1 : p == 1 ? 2 : p == 2 ? 5 : 6; }
+__device__ constexpr int pb(int p) { return p == 0 ? 3 : p == 1 ? 4 : p == 2 ? 7 : 8; }
+// populations with c_x != 0 (LDS slots) and with c_y = +1 / -1 (y ring)
 __device__ constexpr int xpop(int p) { return p == 0 ? 1 : p == 1 ? 5 : p == 2 ? 8 : p == 3 ? 3 : p == 4 ? 6 : 7; }
-// populations with c_y = +1 and c_y = -1
 __device__ constexpr int upop(int p) { return p == 0 ? 2 : p == 1 ? 5 : 6; }
 __device__ constexpr int dpop(int p) { return p == 0 ? 4 : p == 1 ? 7 : 8; }
 
-template <class R, class S>
-__device__ inline void load_pops(const S* base, int64_t plane, int64_t cell, R ref, R* v) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        R x = Codec<S>::template load<R>(base + a * plane + cell);
-        v[a] = Codec<S>::offset ? x + wt<R>(a) * ref : x;
-    }
+template <int N> struct Slot { static constexpr int value = N; };
+
+// Heun corrector input: with HEUN_H the predictor also stores
+// H = (f~n + C(f~n))/2 and the corrector reads it (6 Q b bytes per cell-step);
+// without, the corrector reads f~n at its cell and recomputes C (5 Q b).
+#ifndef LB_HEUN_H
+#define LB_HEUN_H 0
+#endif
+constexpr bool HEUN_H = LB_HEUN_H;
+
+// ---- raw buffer access: 32-bit lane offset, scalar per-plane offset ------
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ inline Buf make_buf(const void* p, uint32_t bytes) {
+    // dword 3 for gfx9-family raw buffers: 32-bit data format, no swizzle
+    return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(bytes), 0x00020000)};
 }
 
-template <class R, class S>
-__device__ inline void store_pops(S* base, int64_t plane, int64_t cell, R ref, const R* v) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        R x = Codec<S>::offset ? v[a] - wt<R>(a) * ref : v[a];
-        Codec<S>::template store<R>(base + a * plane + cell, x);
+// Wide access to the grouped layout (pop_index): one group = the four
+// populations a = 1..4 or a = 5..8 of a species at one cell, contiguous; the
+// rest plane holds a = 0 of every species.  Loads return offsets in R.
+typedef __attribute__((ext_vector_type(2))) unsigned u32x2;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+
+__device__ inline double as_f64(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | uint64_t(lo));
+}
+__device__ inline unsigned f64_lo(double d) { return unsigned(__builtin_bit_cast(uint64_t, d)); }
+__device__ inline unsigned f64_hi(double d) { return unsigned(__builtin_bit_cast(uint64_t, d) >> 32); }
+
+template <class S> struct Io;
+template <> struct Io<double> {
+    template <class R> __device__ static void ld4(Buf b, uint32_t v, uint32_t s, R* d) {
+        u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, 0);
+        u32x4 y = __builtin_amdgcn_raw_buffer_load_b128(b.r, v + 16, s, 0);
+        d[0] = R(as_f64(x[0], x[1]));
+        d[1] = R(as_f64(x[2], x[3]));
+        d[2] = R(as_f64(y[0], y[1]));
+        d[3] = R(as_f64(y[2], y[3]));
     }
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+        const double a0 = d[0], a1 = d[1], a2 = d[2], a3 = d[3];
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, 0);
+    }
+    template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
+        if (N == 2) {
+            u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, 0);
+            d[0] = R(as_f64(x[0], x[1]));
+            d[1] = R(as_f64(x[2], x[3]));
+        } else {
+            u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, 0);
+            d[0] = R(as_f64(x[0], x[1]));
+        }
+    }
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+        const double a0 = d[0];
+        if (N == 2) {
+            const double a1 = d[1];
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, 0);
+        }
+    }
+};
+template <> struct Io<float> {
+    template <class R> __device__ static void ld4(Buf b, uint32_t v, uint32_t s, R* d) {
+        u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = R(__uint_as_float(x[q]));
+    }
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+        u32x4 x{__float_as_uint(float(d[0])), __float_as_uint(float(d[1])), __float_as_uint(float(d[2])),
+                __float_as_uint(float(d[3]))};
+        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, 0);
+    }
+    template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
+        if (N == 2) {
+            u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, 0);
+            d[0] = R(__uint_as_float(x[0]));
+            d[1] = R(__uint_as_float(x[1]));
+        } else {
+            d[0] = R(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, 0)));
+        }
+    }
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+        if (N == 2)
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(d[0])), __float_as_uint(float(d[1]))},
+                                                  b.r, v, s, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(d[0])), b.r, v, s, 0);
+    }
+};
+// 16-bit formats: two elements per dword, element k in bits 16 * (k % 2)
+template <bool BF> struct Io16 {
+    __device__ static float dec(uint32_t w, int hi) {
+        const uint32_t h = hi ? (w >> 16) : (w & 0xffffu);
+        if (BF) return __uint_as_float(h << 16);
+        return float(__builtin_bit_cast(_Float16, uint16_t(h)));
+    }
+    __device__ static uint16_t enc(float x) {
+        if (BF) return __builtin_bit_cast(uint16_t, (__bf16)x);    // v_cvt_pk_bf16_f32: round to nearest even
+        return __builtin_bit_cast(uint16_t, (_Float16)x);          // round to nearest even
+    }
+    __device__ static uint32_t enc2(float lo, float hi) { return uint32_t(enc(lo)) | (uint32_t(enc(hi)) << 16); }
+    template <class R> __device__ static void ld4(Buf b, uint32_t v, uint32_t s, R* d) {
+        u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, 0);
+        d[0] = R(dec(x[0], 0));
+        d[1] = R(dec(x[0], 1));
+        d[2] = R(dec(x[1], 0));
+        d[3] = R(dec(x[1], 1));
+    }
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{enc2(float(d[0]), float(d[1])), enc2(float(d[2]), float(d[3]))},
+                                              b.r, v, s, 0);
+    }
+    template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
+        if (N == 2) {
+            uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, 0);
+            d[0] = R(dec(x, 0));
+            d[1] = R(dec(x, 1));
+        } else {
+            d[0] = R(dec(__builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, 0), 0));
+        }
+    }
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+        if (N == 2) __builtin_amdgcn_raw_buffer_store_b32(enc2(float(d[0]), float(d[1])), b.r, v, s, 0);
+        else __builtin_amdgcn_raw_buffer_store_b16(enc(float(d[0])), b.r, v, s, 0);
+    }
+};
+template <> struct Io<bf16_t> : Io16<true> {};
+template <> struct Io<f16_t> : Io16<false> {};
+
+// All populations of one cell (offsets): f[0..8] and, if TH, g[0..8].
+template <class R, class S, bool TH>
+__device__ inline void load_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t rest_off, R* f, R* g) {
+    constexpr int NSP = TH ? 2 : 1;
+    const uint32_t v4 = cell * uint32_t(4 * sizeof(S));
+    Io<S>::template ld4<R>(b, v4, 0u, f + 1);
+    Io<S>::template ld4<R>(b, v4, gbytes, f + 5);
+    if (TH) {
+        Io<S>::template ld4<R>(b, v4, 2 * gbytes, g + 1);
+        Io<S>::template ld4<R>(b, v4, 3 * gbytes, g + 5);
+    }
+    R r0[2];
+    Io<S>::template ldr<R, NSP>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
+    f[0] = r0[0];
+    if (TH) g[0] = r0[NSP - 1];
 }
 
-// One semi-implicit stage at a cell: the advected brackets phi (and, when
-// WANT_C, the collision increments C) of f and g.
-template <class R, bool TH, bool WANT_C>
-__device__ inline void stage(const R* f, const R* g, const StageConst<R>& k, R (*ph)[9], R (*C)[9]) {
-    Macro<R> m = macro<R, TH>(f, g, k);
-    EqForce<R> e;
-    eq_force(m, e);
+template <class R, class S, bool TH>
+__device__ inline void store_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t rest_off, const R* f, const R* g) {
+    constexpr int NSP = TH ? 2 : 1;
+    const uint32_t v4 = cell * uint32_t(4 * sizeof(S));
+    Io<S>::template st4<R>(b, v4, 0u, f + 1);
+    Io<S>::template st4<R>(b, v4, gbytes, f + 5);
+    if (TH) {
+        Io<S>::template st4<R>(b, v4, 2 * gbytes, g + 1);
+        Io<S>::template st4<R>(b, v4, 3 * gbytes, g + 5);
+    }
+    R r0[2] = {f[0], TH ? g[0] : R(0)};
+    Io<S>::template str<R, NSP>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
+}
+
+template <class R> __device__ inline R recip(R x) { return R(1) / x; }
+template <> __device__ inline float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// One semi-implicit stage at a cell, in offset space.  Writes the advected
+// brackets ph[s][a] (shifted by (1 - k1) w_a ref) of the moving populations
+// and, when BASE, the offsets of f~ + C (all populations).
+template <class R, bool TH, bool BASE>
+__device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, R (*ph)[9], R (*bs)[9]) {
+    constexpr int NSP = TH ? 2 : 1;
+    R rho = df[0], jx = 0, jy = 0;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const R wr = wt<R>(a) * m.rho;
-        const R feq = wr * e.poly[a];
-        const R F = wr * e.frc[a];
-        const R neq = feq - f[a];
-        ph[0][a] = f[a] + k.k1 * neq + k.kh * F;
-        if (WANT_C) C[0][a] = k.kc * neq + k.kf * F;
+    for (int a = 1; a < 9; ++a) {
+        rho += df[a];
+        if (cx(a) > 0) jx += df[a]; else if (cx(a) < 0) jx -= df[a];
+        if (cy(a) > 0) jy += df[a]; else if (cy(a) < 0) jy -= df[a];
+    }
+    rho += k.ref_f;
+    R T = 0, ay = k.ay;
+    if (TH) {
+        T = dg[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) T += dg[a];
+        T += k.ref_g;
+        ay = k.ay + k.bg * (T - k.T0);
+    }
+    const R ax = k.ax;
+    const R ir = recip(rho);
+    const R ux = jx * ir + k.hdt * ax, uy = jy * ir + k.hdt * ay;
+    const R e0 = R(1) - R(1.5) * (ux * ux + uy * uy);
+    const R ua3 = R(3) * (ux * ax + uy * ay);
+    const R wr[3] = {wt<R>(0) * rho, wt<R>(1) * rho, wt<R>(5) * rho};
+    R wt1[3] = {0, 0, 0};  // k1g w T
+    R wt2[3] = {0, 0, 0};  // kcg w
+    if (TH) {
+        wt1[0] = k.k1g * wt<R>(0) * T; wt1[1] = k.k1g * wt<R>(1) * T; wt1[2] = k.k1g * wt<R>(5) * T;
+    }
+    (void)wt2;
+    // rest population: no flux; base only
+    if (BASE) {
+        const R A0 = k.kc * e0 - k.kf * ua3;
+        bs[0][0] = k.omkc * df[0] + (wr[0] * A0 - k.kcwref[0]);
+        if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcgw[0] * (T * e0 - k.ref_g);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int a = pa(p), b = pb(p);
+        const int cl = p < 2 ? 1 : 2;
+        R cu, ca;
+        if (p == 0) { cu = ux; ca = ax; }
+        else if (p == 1) { cu = uy; ca = ay; }
+        else if (p == 2) { cu = ux + uy; ca = ax + ay; }
+        else { cu = uy - ux; ca = ay - ax; }
+        const R E = (R(4.5) * cu) * cu + e0;
+        const R Fe = (R(9) * cu) * ca - ua3;
+        // advected bracket of f
+        const R Pe = k.k1 * E + k.kh * Fe;
+        const R Po = k.k1x3 * cu + k.khx3 * ca;
+        ph[0][a] = k.omk1 * df[a] + wr[cl] * (Pe + Po);
+        ph[0][b] = k.omk1 * df[b] + wr[cl] * (Pe - Po);
         if (TH) {
-            const R geq = wt<R>(a) * m.T * e.poly[a];
-            const R gneq = geq - g[a];
-            ph[1][a] = g[a] + k.k1g * gneq;
-            if (WANT_C) C[1][a] = k.kcg * gneq;
+            const R O = R(3) * cu;
+            ph[NSP - 1][a] = k.omk1g * dg[a] + wt1[cl] * (E + O);
+            ph[NSP - 1][b] = k.omk1g * dg[b] + wt1[cl] * (E - O);
+            if (BASE) {
+                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcgw[cl] * (T * (E + O) - k.ref_g);
+                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcgw[cl] * (T * (E - O) - k.ref_g);
+            }
+        }
+        if (BASE) {
+            const R Ae = k.kc * E + k.kf * Fe;
+            const R Ao = k.kcx3 * cu + k.kfx3 * ca;
+            bs[0][a] = k.omkc * df[a] + (wr[cl] * (Ae + Ao) - k.kcwref[cl]);
+            bs[0][b] = k.omkc * df[b] + (wr[cl] * (Ae - Ao) - k.kcwref[cl]);
         }
     }
 }
 
+// Make this row's LDS writes visible to the other lanes of the block.  A
+// one-wave block only needs the wave's own LDS operations kept in program
+// order (the LDS executes a wave's instructions in order); larger blocks need
+// a workgroup barrier.
+__device__ inline void lanes_sync() {
+    if (FV_LANES == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <class R, class S, bool TH, bool CORR>
-__global__ void __launch_bounds__(FV_LANES) fv_pass(FvArgs<R> A) {
+__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvArgs<R> A) {
     constexpr int NSP = TH ? 2 : 1;
     __shared__ R lds[2][6 * NSP][FV_LANES];
 
     const int t = threadIdx.x;
-    const int x0 = blockIdx.x * A.strip_w;
+    // Work item of this block.  Blocks are dealt to the eight XCDs round
+    // robin, so block b runs on XCD b % 8; items are numbered chunk-major
+    // (adjacent strips of a chunk are consecutive) and each XCD takes a
+    // contiguous range of them, so strips that share halo columns run side by
+    // side on one XCD and meet in its L2.
+    const int per_xcd = (A.n_items + 7) / 8;
+    const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (item >= A.n_items) return;
+    const int strip = item % A.n_strips, chunk = item / A.n_strips;
+    const int x0 = strip * A.strip_w;
     const int own = min(A.strip_w, A.nx - x0);
     const int lanes = own + 2 * FV_HALO;
-    if ((t & ~63) >= lanes) return;  // a wave with no column of this strip leaves (barriers count live waves)
+    if ((t & ~63) >= lanes) return;  // a wave without columns of this strip leaves (barriers count live waves)
 
     // ---- this lane's column (ghost columns mirror or wrap) ----
     const int xg = x0 - FV_HALO + t;
@@ -101,205 +345,225 @@ __global__ void __launch_bounds__(FV_LANES) fv_pass(FvArgs<R> A) {
     if (t >= lanes) { col = 0; mx = false; }  // idle lane of a live wave
     const bool owned = t >= FV_HALO && t < FV_HALO + own;
 
-    R xl[6], xr[6], idx_c = 0;
+    R xc[8];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { xl[q] = 0; xr[q] = 0; }
-    if (owned) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            xl[q] = A.m.xw[col * 6 + q];
-            xr[q] = A.m.xw[(col + 1) * 6 + q];
-        }
-        idx_c = A.m.idx[col];
-    }
+    for (int q = 0; q < 8; ++q) xc[q] = owned ? A.xcoef[col * 8 + q] : R(0);
 
-    const S* src = static_cast<const S*>(A.src);
-    const S* loc = static_cast<const S*>(A.loc);
-    S* dst = static_cast<S*>(A.dst);
-    const int64_t plane = A.plane;
-    const int y0 = blockIdx.y * A.chunk_h;
+    const uint32_t gb = A.group_bytes, ro = A.rest_off;
+    const uint32_t nxu = uint32_t(A.nx), colu = uint32_t(col);
+    const Buf bsrc = make_buf(A.src, A.state_bytes);
+    const Buf bdst = make_buf(A.dst, A.state_bytes);
+    const Buf baux = make_buf(A.aux, A.state_bytes);
+
+    const int y0 = chunk * A.chunk_h;
     const int y1 = min(y0 + A.chunk_h, A.ny);
+    const StageK<R> k = A.k;
+    typedef const __attribute__((address_space(4))) R CR;
 
-    // rolling state of the march
-    R P3[NSP][3], P2[NSP][3], P1[NSP][3];  // phi of c_y=+1 populations at rows r-3, r-2, r-1
-    R M2[NSP][3], M1[NSP][3];              // phi of c_y=-1 populations at rows r-2, r-1
-    R Fp[NSP][6];                          // y-face values of the face below the row being finished
-    R U1[NSP][9], U2[NSP][9];              // partial updates of rows r-1, r-2 (all but the y flux)
+    // rings: phi of c_y=+1 and c_y=-1 populations of the last four rows,
+    // partial updates (all but the y flux) of the last two rows
+    R UP[4][NSP][3], DN[4][NSP][3], U[2][NSP][9];
 #pragma unroll
-    for (int s = 0; s < NSP; ++s) {
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) { P3[s][q] = P2[s][q] = P1[s][q] = M2[s][q] = M1[s][q] = 0; }
+        for (int s = 0; s < NSP; ++s)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) Fp[s][q] = 0;
+            for (int p = 0; p < 3; ++p) UP[q][s][p] = DN[q][s][p] = R(0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) { U1[s][a] = U2[s][a] = 0; }
-    }
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int a = 0; a < 9; ++a) U[q][s][a] = R(0);
 
-    for (int r = y0 - 2; r <= y1 + 1; ++r) {
+    // One row of the march.  The body is free of block-uniform branches (so
+    // the unrolled rings stay in fixed registers): every row is exchanged
+    // through LDS, ghost rows are selected arithmetically, and only the
+    // stores and the owned lanes' flux are masked.
+    // Storage row of march row r (ghost rows mirror or wrap; rows past the
+    // chunk end, the padding of the last unrolled trip, are clamped).
+    auto map_row = [&](const int r) __attribute__((always_inline)) {
         int row = r;
-        bool my = false;
-        R Tw = 0;
-        if (r < 0) {
-            if (A.wall_y) { row = -r - 1; my = true; Tw = A.T_bottom; } else row = r + A.ny;
-        } else if (r >= A.ny) {
-            if (A.wall_y) { row = 2 * A.ny - 1 - r; my = true; Tw = A.T_top; } else row = r - A.ny;
+        if (r < 0) row = A.wall_y ? -r - 1 : r + A.ny;
+        else if (r >= A.ny) row = A.wall_y ? 2 * A.ny - 1 - r : r - A.ny;
+        return min(max(row, 0), A.ny - 1);
+    };
+    // Rows are loaded one row ahead of their use (software pipelining): the
+    // loads of row r+1 are in flight while row r is computed.  The FP64
+    // instance (the parity path) loads each row where it is used: two rows of
+    // f, g and H in double would not fit next to its rings in registers.
+    constexpr bool AHEAD = sizeof(R) == 4;
+    // The corrector's own-cell input goes one row ahead only for 16-bit
+    // storage, whose prefetched words stay packed two to a register.
+    constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2;
+    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
+    auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int Q = decltype(slot_tag)::value & 1;
+        load_cell<R, S, TH>(bsrc, uint32_t(map_row(r)) * nxu + colu, gb, ro, PF[Q], PG[Q]);
+        if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n, or H)
+            load_cell<R, S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, ro, PH[Q], PHG[Q]);
+    };
+
+    auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
+        const bool my = A.wall_y && (r < 0 || r >= A.ny);
+        const R Tw = r < 0 ? A.Twb : A.Twt;
+
+        if (!AHEAD) prefetch(r, Slot<SL>{});
+        R df[9], dg[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            df[a] = PF[SL & 1][a];
+            if (TH) dg[a] = PG[SL & 1][a];
         }
-        const int64_t cell = int64_t(row) * A.nx + col;
-        const bool out_row = r >= y0 && r < y1;
+        if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+        if (CORR && !AHEAD_OWN && owned)  // own-cell input of this row, used after the stage
+            load_cell<R, S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, ro, PH[SL & 1], PHG[SL & 1]);
 
-        R f[9], g[9];
-        load_pops<R, S>(src, plane, cell, A.ref_f, f);
-        if (TH) load_pops<R, S>(src + 9 * plane, plane, cell, A.ref_g, g);
+        R ph[NSP][9], bs[NSP][9];
+        if (CORR) stage<R, TH, false>(df, dg, k, ph, bs);
+        else stage<R, TH, true>(df, dg, k, ph, bs);
 
-        R ph[NSP][9], C[NSP][9];
-        if (CORR)
-            stage<R, TH, false>(f, g, A.k, ph, C);
-        else
-            stage<R, TH, true>(f, g, A.k, ph, C);
-
-        // ghost rows: double reflection (f), anti-reflection about T_w (g)
-        if (my) {
-            R tmp[9];
+        // ghost row (y walls): double reflection of f, anti-reflection of g
+        {
+            R tmp[NSP][9];
 #pragma unroll
-            for (int a = 0; a < 9; ++a) tmp[a] = ph[0][a];
+            for (int s = 0; s < NSP; ++s)
 #pragma unroll
-            for (int a = 0; a < 9; ++a) ph[0][a] = tmp[opp(a)];
-            if (TH) {
+                for (int a = 1; a < 9; ++a) tmp[s][a] = ph[s][a];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) tmp[a] = ph[NSP - 1][a];
-#pragma unroll
-                for (int a = 0; a < 9; ++a) ph[NSP - 1][a] = R(2) * wt<R>(a) * Tw - tmp[opp(a)];
+            for (int a = 1; a < 9; ++a) {
+                ph[0][a] = my ? tmp[0][opp(a)] : tmp[0][a];
+                if (TH) ph[NSP - 1][a] = my ? R(2) * wt<R>(a) * Tw - tmp[NSP - 1][opp(a)] : tmp[NSP - 1][a];
             }
         }
-        // ghost columns: double reflection of both species (x walls are adiabatic)
-        if (mx) {
+        if (mx) {  // ghost column (x walls): double reflection of both species
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
                 R tmp[9];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) tmp[a] = ph[s][a];
+                for (int a = 1; a < 9; ++a) tmp[a] = ph[s][a];
 #pragma unroll
-                for (int a = 0; a < 9; ++a) ph[s][a] = tmp[opp(a)];
+                for (int a = 1; a < 9; ++a) ph[s][a] = tmp[opp(a)];
             }
         }
 
-        // ---- x fluxes and the partial update of an output row ----
-        R U0[NSP][9];
-        if (out_row) {
-            const int b = r & 1;
+        // ---- y flux: finish row j = r - 2 (phi rows j-2 .. j+2) before the
+        //      partial update of row r takes over the U slot of row j ----
+        const int j = r - 2;
+        // y weights of row j: uniform, read as scalar loads (constant address
+        // space) in uniform control flow, so no vector-memory wait is needed
+        R yc[8];
+        {
+            const CR* yw = (const CR*)(A.ycoef) + int64_t(min(max(j, 0), A.ny - 1)) * 8;
 #pragma unroll
-            for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
-            __syncthreads();
-            if (owned) {
-                R base[NSP][9];
-                if (CORR) {
-                    // C(f~n) at this cell; f~* is f here
-                    R fn[9], gn[9], phn[NSP][9], Cn[NSP][9];
-                    const int64_t oc = int64_t(r) * A.nx + col;
-                    load_pops<R, S>(loc, plane, oc, A.ref_f, fn);
-                    if (TH) load_pops<R, S>(loc + 9 * plane, plane, oc, A.ref_g, gn);
-                    stage<R, TH, true>(fn, gn, A.k, phn, Cn);
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        base[0][a] = R(0.5) * (fn[a] + f[a] + Cn[0][a]);
-                        if (TH) base[NSP - 1][a] = R(0.5) * (gn[a] + g[a] + Cn[NSP - 1][a]);
-                    }
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        base[0][a] = f[a] + C[0][a];
-                        if (TH) base[NSP - 1][a] = g[a] + C[NSP - 1][a];
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < NSP; ++s) {
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) U0[s][a] = base[s][a];
-#pragma unroll
-                    for (int p = 0; p < 6; ++p) {
-                        const int a = xpop(p);
-                        const R* L = lds[b][s * 6 + p];
-                        const R v = ph[s][a];
-                        R Fr, Fl;
-                        if (cx(a) > 0) {
-                            const R m1 = L[t - 1], m2 = L[t - 2], p1 = L[t + 1];
-                            Fr = xr[0] * v + xr[1] * p1 + xr[2] * m1;
-                            Fl = xl[0] * m1 + xl[1] * v + xl[2] * m2;
-                        } else {
-                            const R m1 = L[t - 1], p1 = L[t + 1], p2 = L[t + 2];
-                            Fr = xr[3] * p1 + xr[4] * v + xr[5] * p2;
-                            Fl = xl[3] * v + xl[4] * m1 + xl[5] * p1;
-                        }
-                        U0[s][a] -= A.dt_update * R(cx(a)) * (Fr - Fl) * idx_c;
-                    }
-                }
-            }
+            for (int q = 0; q < 8; ++q) yc[q] = yw[q];
         }
-
-        // ---- y faces: face between rows r-2 and r-1 (face index r-1) ----
-        if (r >= y0 + 1) {
-            const R* yw = A.m.yw + int64_t(r - 1) * 6;
-            const R w0 = yw[0], w1 = yw[1], w2 = yw[2], w3 = yw[3], w4 = yw[4], w5 = yw[5];
-            R Fc[NSP][6];
+        if (owned && j >= y0 && j < y1) {
+            R out[NSP][9];
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    Fc[s][q] = w0 * P2[s][q] + w1 * P1[s][q] + w2 * P3[s][q];
-                    Fc[s][3 + q] = w3 * M1[s][q] + w4 * M2[s][q] + w5 * ph[s][dpop(q)];
+                for (int a = 0; a < 9; ++a) out[s][a] = U[SL & 1][s][a];
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    // c_y = +1: rows j-2 .. j+1 = r-4 .. r-1  (ring slots SL, SL+1, SL+2, SL+3)
+                    out[s][upop(p)] -= yc[0] * UP[SL][s][p] + yc[1] * UP[(SL + 1) & 3][s][p] +
+                                       yc[2] * UP[(SL + 2) & 3][s][p] + yc[3] * UP[(SL + 3) & 3][s][p];
+                    // c_y = -1: rows j-1 .. j+2 = r-3 .. r
+                    out[s][dpop(p)] -= yc[4] * DN[(SL + 1) & 3][s][p] + yc[5] * DN[(SL + 2) & 3][s][p] +
+                                       yc[6] * DN[(SL + 3) & 3][s][p] + yc[7] * ph[s][dpop(p)];
                 }
             }
-            if (r >= y0 + 2 && owned) {
-                const int j = r - 2;
-                const R iy = A.m.idy[j];
-                R out[NSP][9];
-#pragma unroll
-                for (int s = 0; s < NSP; ++s) {
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) out[s][a] = U2[s][a];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        out[s][upop(q)] -= A.dt_update * (Fc[s][q] - Fp[s][q]) * iy;
-                        out[s][dpop(q)] += A.dt_update * (Fc[s][3 + q] - Fp[s][3 + q]) * iy;
-                    }
-                }
-                const int64_t oc = int64_t(j) * A.nx + col;
-                store_pops<R, S>(dst, plane, oc, A.ref_f, out[0]);
-                if (TH) store_pops<R, S>(dst + 9 * plane, plane, oc, A.ref_g, out[NSP - 1]);
-            }
-#pragma unroll
-            for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Fp[s][q] = Fc[s][q];
+            store_cell<R, S, TH>(bdst, uint32_t(j) * nxu + colu, gb, ro, out[0], out[NSP - 1]);
         }
 
-        // ---- advance the windows ----
+        // ---- x flux and partial update (all but the y flux) of row r ----
+        const int b = SL & 1;
 #pragma unroll
-        for (int s = 0; s < NSP; ++s) {
+        for (int s = 0; s < NSP; ++s)
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                P3[s][q] = P2[s][q];
-                P2[s][q] = P1[s][q];
-                P1[s][q] = ph[s][upop(q)];
-                M2[s][q] = M1[s][q];
-                M1[s][q] = ph[s][dpop(q)];
+            for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
+        lanes_sync();
+        if (owned) {
+            const bool out_row = r >= y0 && r < y1;
+            const uint32_t ocell = uint32_t(min(r, A.ny - 1)) * nxu + colu;
+            R base[NSP][9];
+            if (CORR && HEUN_H) {
+                // f~n+1 = H + f~*/2 - dt/2 D(phi*): H (offsets) at this cell
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    base[0][a] = PH[SL & 1][a] + R(0.5) * df[a];
+                    if (TH) base[NSP - 1][a] = PHG[SL & 1][a] + R(0.5) * dg[a];
+                }
+            } else if (CORR) {
+                // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
+                R phn[NSP][9], bn[NSP][9];
+                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, phn, bn);
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    base[0][a] = R(0.5) * (bn[0][a] + df[a]);
+                    if (TH) base[NSP - 1][a] = R(0.5) * (bn[NSP - 1][a] + dg[a]);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) base[s][a] = bs[s][a];
+                if (A.aux && out_row) {  // Heun predictor: keep H = (f~ + C)/2 for the corrector
+                    R hf[9], hg[9];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        hf[a] = R(0.5) * bs[0][a];
+                        if (TH) hg[a] = R(0.5) * bs[NSP - 1][a];
+                    }
+                    store_cell<R, S, TH>(baux, ocell, gb, ro, hf, hg);
+                }
             }
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                U2[s][a] = U1[s][a];
-                U1[s][a] = out_row ? U0[s][a] : R(0);
+            for (int s = 0; s < NSP; ++s) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const int a = xpop(p);
+                    const R* L = lds[b][s * 6 + p];
+                    const R v = ph[s][a];
+                    R d;
+                    if (cx(a) > 0)
+                        d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
+                    else
+                        d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
+                    base[s][a] -= d;
+                }
+#pragma unroll
+                for (int a = 0; a < 9; ++a) U[SL & 1][s][a] = base[s][a];
             }
         }
+        // ---- push this row into the rings ----
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                UP[SL][s][p] = ph[s][upop(p)];
+                DN[SL][s][p] = ph[s][dpop(p)];
+            }
+    };
+
+    // Rows y0-2 .. y1+1 in trips of four; the trip may run up to three rows
+    // past y1+1 (their results are never stored).  A chunk of height 4k
+    // needs exactly k+1 trips.
+    if (AHEAD) prefetch(y0 - 2, Slot<0>{});
+    for (int r = y0 - 2; r <= y1 + 1; r += 4) {
+        row_step(r, Slot<0>{});
+        row_step(r + 1, Slot<1>{});
+        row_step(r + 2, Slot<2>{});
+        row_step(r + 3, Slot<3>{});
     }
 }
 
 template <class R, class S>
-static hipError_t launch_typed(bool thermal, bool corrector, const void* args, int n_strips, int n_chunks,
-                               hipStream_t s) {
+static hipError_t launch_typed(bool thermal, bool corrector, const void* args, hipStream_t s) {
     const FvArgs<R>& A = *static_cast<const FvArgs<R>*>(args);
-    dim3 grid(n_strips, n_chunks), block(FV_LANES);
+    dim3 grid(8 * ((A.n_items + 7) / 8)), block(FV_LANES);
     if (thermal) {
         if (corrector)
             hipLaunchKernelGGL((fv_pass<R, S, true, true>), grid, block, 0, s, A);
@@ -314,13 +578,36 @@ static hipError_t launch_typed(bool thermal, bool corrector, const void* args, i
     return hipGetLastError();
 }
 
-hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, int n_strips,
-                          int n_chunks, hipStream_t s) {
+template <class R, class S>
+static int resident_typed(bool thermal, bool corrector) {
+    int per_cu = 0, dev = 0, cus = 0;
+    const void* k;
+    if (thermal) k = corrector ? (const void*)fv_pass<R, S, true, true> : (const void*)fv_pass<R, S, true, false>;
+    else k = corrector ? (const void*)fv_pass<R, S, false, true> : (const void*)fv_pass<R, S, false, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, FV_LANES, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+bool fv_heun_h() { return HEUN_H; }
+
+int fv_resident_blocks(int storage, bool thermal, bool corrector) {
     switch (storage) {
-        case ST_F64: return launch_typed<double, double>(thermal, corrector, args, n_strips, n_chunks, s);
-        case ST_F32: return launch_typed<float, float>(thermal, corrector, args, n_strips, n_chunks, s);
-        case ST_BF16: return launch_typed<float, bf16_t>(thermal, corrector, args, n_strips, n_chunks, s);
-        case ST_F16: return launch_typed<float, f16_t>(thermal, corrector, args, n_strips, n_chunks, s);
+        case ST_F64: return resident_typed<double, double>(thermal, corrector);
+        case ST_F32: return resident_typed<float, float>(thermal, corrector);
+        case ST_BF16: return resident_typed<float, bf16_t>(thermal, corrector);
+        case ST_F16: return resident_typed<float, f16_t>(thermal, corrector);
+    }
+    return 0;
+}
+
+hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s) {
+    switch (storage) {
+        case ST_F64: return launch_typed<double, double>(thermal, corrector, args, s);
+        case ST_F32: return launch_typed<float, float>(thermal, corrector, args, s);
+        case ST_BF16: return launch_typed<float, bf16_t>(thermal, corrector, args, s);
+        case ST_F16: return launch_typed<float, f16_t>(thermal, corrector, args, s);
     }
     return hipErrorInvalidValue;
 }

@@ -75,6 +75,21 @@ template <> struct Codec<f16_t> {
     }
 };
 
+// ---- population layouts in device memory ---------------------------------
+// SoA (ST scheme): element (s, a, c) at (s*9 + a) * plane + c.
+// Grouped (FV schemes): each cell keeps four populations of a species side by
+// side so one lane reads them with one wide load:
+//   group 2s   : a = 1..4 (axis velocities) of species s, 4 elements per cell
+//   group 2s+1 : a = 5..8 (diagonals)
+//   rest plane : a = 0 of every species, nsp elements per cell
+// i.e. element (s, a>0, c) at (2s + (a>4)) * 4 plane + 4c + (a-1)%4 and
+// (s, 0, c) at 8 nsp plane + nsp c + s.
+__host__ __device__ inline int64_t pop_index(bool grouped, int nsp, int64_t plane, int s, int a, int64_t c) {
+    if (!grouped) return (int64_t(s) * 9 + a) * plane + c;
+    if (a == 0) return int64_t(8) * nsp * plane + int64_t(nsp) * c + s;
+    return (int64_t(2 * s + (a > 4 ? 1 : 0)) * 4) * plane + 4 * c + ((a - 1) & 3);
+}
+
 // ---- local kinetic model -----------------------------------------------
 // Constants of one semi-implicit stage (eq:semi) or of the Euler step
 // (eq:euler), all precomputed on the host:

@@ -10,39 +10,47 @@ namespace lbk {
 
 enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
 
-// Width in lanes of the FV strip kernel: 252 owned columns + 2 halo columns
-// on each side.  One lane per column, the block marches up its rows.
-constexpr int FV_LANES = 256;
+// Width in lanes of the FV strip kernel (one lane per column, the block
+// marches up its rows): FV_LANES - 4 owned columns + 2 halo columns on each
+// side.
+#ifndef LB_FV_LANES
+#define LB_FV_LANES 256
+#endif
+constexpr int FV_LANES = LB_FV_LANES;
 constexpr int FV_HALO = 2;
 
-// Per-face QUICK weights (sec. 2.2.3), face k between cells k-1 and k:
-//   c.n > 0 : P = k-1, E = k, W = k-2   ->  up[0] P + up[1] E + up[2] W
-//   c.n < 0 :                EE = k+1   ->  dn[0] E + dn[1] P + dn[2] EE
-// stored as 6 numbers per face: up0 up1 up2 dn0 dn1 dn2, with
-//   up = (1 - g1 + g2, g1, -g2), dn = (1 - g3 + g4, g3, -g4).
+// Stage constants of the FV kernel in offset arithmetic (see fv.hip):
+//   bracket   phi' = omk1 d + w rho (k1 poly + kh frc)          (f)
+//             phi' = omk1g d + k1g w T poly                     (g)
+//   f~ + C    b'   = omkc d + w rho (kc poly + kf frc) - kc w ref
+//             b'   = omkcg d + kcg w (T poly - T_ref)
+// with poly = f_eq/(w rho), frc = F/(w rho); k1x3 = 3 k1 etc.
 template <class R>
-struct Metric {
-    const R* xw;   // [(nx+1)*6]
-    const R* yw;   // [(ny+1)*6]
-    const R* idx;  // [nx]  1/dx (S/V of the x faces)
-    const R* idy;  // [ny]
+struct StageK {
+    R hdt, ax, ay, bg, T0, ref_f, ref_g;
+    R k1, kh, k1x3, khx3, omk1, k1g, omk1g;
+    R kc, kf, kcx3, kfx3, omkc, omkcg;
+    R kcwref[3];  // kc w_class ref_f  (classes: rest, axis, diagonal)
+    R kcgw[3];    // kcg w_class
 };
 
 template <class R>
 struct FvArgs {
-    const void* src;  // state read with halo: f~n (predictor, single pass) or f~* (corrector)
-    const void* loc;  // corrector only: f~n, read at the cell itself
-    void* dst;        // output state
+    const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector)
+    void* dst;         // output state
+    void* aux;         // corrector: its own-cell input (f~n, or H); predictor: H output or NULL
+    uint32_t state_bytes;  // whole state (grouped layout, see pop_index)
+    uint32_t group_bytes;  // one group plane: 4 elements per cell
+    uint32_t rest_off;     // byte offset of the rest plane
     int nx, ny;
-    int64_t plane;    // nx * ny
     int wall_x, wall_y;
-    int strip_w;      // owned columns per strip (<= FV_LANES - 4)
-    int chunk_h;      // rows per chunk
-    Metric<R> m;
-    StageConst<R> k;
-    R dt_update;      // dt (predictor / single pass) or dt/2 (corrector)
-    R T_bottom, T_top;
-    R ref_f, ref_g;   // storage offsets (rho_ref, T_ref)
+    int strip_w;       // owned columns per strip (<= FV_LANES - 4)
+    int chunk_h;       // rows per chunk
+    int n_strips, n_items;  // work items: n_strips * n_chunks, chunk-major
+    const R* xcoef;    // [nx][8] four-point flux weights (c>0: i-2..i+1, c<0: i-1..i+2), times dt or dt/2
+    const R* ycoef;    // [ny][8]
+    StageK<R> k;
+    R Twb, Twt;        // wall temperatures for the g anti-reflection, shifted: T_w - (1 - k1g) T_ref
 };
 
 struct StArgs {
@@ -58,15 +66,19 @@ struct StArgs {
 
 // Host launchers (defined in the .hip files).  `storage` selects the
 // template instance; every launcher returns the hipError_t of the launch.
-hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args,
-                          int n_strips, int n_chunks, hipStream_t s);
+hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
+// True when the Heun predictor stores H = (f~n + C)/2 for the corrector.
+bool fv_heun_h();
+// Largest number of FV blocks of one launch that are resident at once.
+int fv_resident_blocks(int storage, bool thermal, bool corrector);
 hipError_t launch_st(int storage, bool thermal, bool stream_only, const StArgs& a, hipStream_t s);
 
 struct AuxArgs {
-    void* state;       // populations (f planes then g planes)
+    void* state;       // populations (layout: pop_index)
     int nx, ny;
     int64_t plane;
     int thermal;
+    int grouped;       // 1: grouped layout (FV schemes), 0: SoA (ST)
     double hdt;        // velocity shift dt/2 (0 for Euler)
     double ax, ay, bg, T0;
     double ref_f, ref_g;
