@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--storage", default="bf16")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the serving trace to replay (0: skip serving)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 512 MiB device to device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -180,11 +182,11 @@ def main():
     (np_, tp), (nc, tc) = head["kernels"]["fv_first_pass"], head["kernels"]["fv_corrector"]
     avg_p, avg_c = tp / np_ / 1e3, tc / nc / 1e3
     # compulsory traffic per cell of each launch: the predictor reads f~n and
-    # writes f~* and H = (f~n + C)/2; the corrector reads f~* and H and writes f~n+1
+    # writes f~* (2 Q b); the corrector reads f~* and f~n and writes f~n+1 (3 Q b)
     if tc >= tp:
         name, avg, per_cell = "fv_pass<corrector>", avg_c, 3 * Q * b
     else:
-        name, avg, per_cell = "fv_pass<predictor>", avg_p, 3 * Q * b
+        name, avg, per_cell = "fv_pass<predictor>", avg_p, 2 * Q * b
     achieved = per_cell * cells / avg / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells, name),
@@ -193,7 +195,7 @@ def main():
     extra = {"storage": args.storage, "predictor_avg_ms": round(avg_p * 1e3, 4),
              "corrector_avg_ms": round(avg_c * 1e3, 4),
              "step_effective_GBps_2Qb": round(2 * Q * b * cells * K / head["seconds"] / 1e9, 1),
-             "step_compulsory_GBps_6Qb": round(6 * Q * b * cells * K / head["seconds"] / 1e9, 1),
+             "step_compulsory_GBps_5Qb": round(5 * Q * b * cells * K / head["seconds"] / 1e9, 1),
              "nusselt_bottom_top_vol_last": head["nusselt"][-1] if head["nusselt"] else None,
              "nonfinite": head["diag"]["nonfinite"]}
     if not args.no_variants:
@@ -214,6 +216,20 @@ def main():
                                   f"FV semi-implicit+Heun, D2Q9 f+g, {args.storage} storage, FP32 arithmetic",
                       "cells": cells, "storage": args.storage, "dt": cfg["dt"]},
            "roofline": roof}
+    if args.serve_requests > 0:
+        from paper_1505_03271_amd.serve import Server
+        trace = workloads.serving_trace()[:args.serve_requests]
+        log(f"serving {len(trace)} requests ...")
+        server = Server(storage="bf16", hbm_budget=16e9, max_sims=128, graph_steps=100)
+        st = server.run(trace)
+        server.close()
+        out["serving"] = {"requests": st["n_requests"], "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                          "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
+                          "graph_steps": st["graph_steps"], "graph_launches": st["graph_launches"],
+                          "hbm_budget_bytes": 16e9, "storage": "bf16",
+                          "trace": "Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
+                                   "steps U{2000..20000}, seed 150503275"}
+        log(f"serving: p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, {st['aggregate_mlups']:.0f} MLUPS")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

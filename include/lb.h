@@ -182,6 +182,34 @@ int lb_set_fv_chunk(lb_sim* sim, int rows);
 /* Number of bytes of device memory held by the handle. */
 size_t lb_device_bytes(const lb_sim* sim);
 
+/* ---- Serving: many simulations advanced by shared launches ------------
+ *
+ * A group holds up to max_sims FV semi-implicit + Heun simulations (same
+ * storage format and thermal flag, any sizes, grids and parameters) and
+ * advances all of them with one predictor and one corrector launch per
+ * step over the work items of every member, captured with the group's
+ * counter updates in a HIP graph of nsteps steps (re-captured only when the
+ * membership or nsteps changes).  Each member carries its own remaining
+ * step count and stops exactly there, so a member's state after its steps
+ * is bit-identical to running it alone with lb_step.  Members stay owned by
+ * the caller and must not be stepped, reset or destroyed while in a group.
+ * stream: hipStream_t to use, or NULL to create one. */
+typedef struct lb_group lb_group;
+int lb_group_create(int32_t max_sims, void* stream, lb_group** out);
+void lb_group_destroy(lb_group* group);
+/* Join with `steps` steps to do; *slot receives the member's slot.
+ * LB_EINVAL for a non-Heun member or a storage/thermal mismatch, LB_ESTATE
+ * without a state, LB_ENOMEM when all slots are taken.  Synchronises. */
+int lb_group_add(lb_group* group, lb_sim* sim, int64_t steps, int32_t* slot);
+/* Leave (finished or not); the slot becomes free.  Synchronises. */
+int lb_group_remove(lb_group* group, int32_t slot);
+/* Enqueue nsteps group steps (asynchronous). */
+int lb_group_step(lb_group* group, int64_t nsteps);
+int lb_group_sync(lb_group* group);
+/* Remaining steps of every slot (array of max_sims; 0 for free slots).
+ * Synchronises. */
+int lb_group_remaining(lb_group* group, int64_t* left);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lb_last_error(void);
 

@@ -77,6 +77,13 @@ def lib():
             "lb_set_fv_chunk": ([h, ctypes.c_int], ctypes.c_int),
             "lb_device_bytes": ([h], ctypes.c_size_t),
             "lb_last_error": ([], ctypes.c_char_p),
+            "lb_group_create": ([ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(h)], ctypes.c_int),
+            "lb_group_destroy": ([h], None),
+            "lb_group_add": ([h, h, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "lb_group_remove": ([h, ctypes.c_int32], ctypes.c_int),
+            "lb_group_step": ([h, ctypes.c_int64], ctypes.c_int),
+            "lb_group_sync": ([h], ctypes.c_int),
+            "lb_group_remaining": ([h, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -221,3 +228,47 @@ class Sim:
 
     def device_bytes(self):
         return lib().lb_device_bytes(self.h)
+
+
+class Group:
+    """Serving group (lb_group_*): members advance together in shared
+    launches, each stopping exactly at its own step count."""
+
+    def __init__(self, max_sims, stream=None):
+        self.max_sims = int(max_sims)
+        self.h = ctypes.c_void_p()
+        st = stream.value if isinstance(stream, ctypes.c_void_p) else stream
+        _check(lib().lb_group_create(self.max_sims, st, ctypes.byref(self.h)))
+        self.members = {}
+
+    def close(self):
+        if self.h:
+            lib().lb_group_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, sim, steps):
+        slot = ctypes.c_int32()
+        _check(lib().lb_group_add(self.h, sim.h, int(steps), ctypes.byref(slot)))
+        self.members[slot.value] = sim
+        return slot.value
+
+    def remove(self, slot):
+        _check(lib().lb_group_remove(self.h, int(slot)))
+        self.members.pop(slot, None)
+
+    def step(self, n):
+        _check(lib().lb_group_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().lb_group_sync(self.h))
+
+    def remaining(self):
+        out = (ctypes.c_int64 * self.max_sims)()
+        _check(lib().lb_group_remaining(self.h, out))
+        return list(out)

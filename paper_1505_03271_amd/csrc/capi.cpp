@@ -693,3 +693,211 @@ int lb_set_fv_chunk(lb_sim* s, int rows) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- groups --
+
+struct lb_group {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int max_sims = 0;
+    std::vector<lb_sim*> sims;  // slot -> member (nullptr if free)
+    int storage = -1, thermal = -1;
+    void* d_args = nullptr;     // 2 FvArgs per slot
+    int2* d_items = nullptr;
+    size_t items_cap = 0;
+    int n_items = 0;
+    int64_t* d_left = nullptr;
+    bool dirty = true;
+    hipGraphExec_t exec = nullptr;
+    int64_t exec_steps = 0;
+};
+
+namespace {
+
+constexpr int GROUP_CHUNK = 64;  // rows per work item of group members (balanced items)
+
+void group_drop_graph(lb_group* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    g->exec = nullptr;
+    g->exec_steps = 0;
+}
+
+template <class R>
+void group_fill_args(lb_group* g, std::vector<char>& host) {
+    for (int k = 0; k < g->max_sims; ++k) {
+        lb_sim* s = g->sims[k];
+        if (!s) continue;
+        FvArgs<R> pa = fv_args<R>(s, s->A, s->B, nullptr, false);
+        FvArgs<R> ca = fv_args<R>(s, s->B, s->A, s->A, true);
+        std::memcpy(&host[(2 * size_t(k)) * sizeof(FvArgs<R>)], &pa, sizeof pa);
+        std::memcpy(&host[(2 * size_t(k) + 1) * sizeof(FvArgs<R>)], &ca, sizeof ca);
+    }
+}
+
+int group_rebuild(lb_group* g) {
+    const size_t ab = fv_args_bytes(g->storage);
+    std::vector<char> host(2 * size_t(g->max_sims) * ab, 0);
+    if (g->storage == LB_F64) group_fill_args<double>(g, host);
+    else group_fill_args<float>(g, host);
+    std::vector<int2> items;
+    for (int k = 0; k < g->max_sims; ++k) {
+        lb_sim* s = g->sims[k];
+        if (!s) continue;
+        const int n_strips = (s->p.nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
+        const int n = n_strips * ((s->p.ny + s->chunk_h - 1) / s->chunk_h);
+        for (int q = 0; q < n; ++q) items.push_back(int2{k, q});
+    }
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    HIP_TRY(hipMemcpy(g->d_args, host.data(), host.size(), hipMemcpyHostToDevice));
+    if (items.size() > g->items_cap) {
+        if (g->d_items) (void)hipFree(g->d_items);
+        g->d_items = nullptr;
+        g->items_cap = std::max<size_t>(items.size(), 2 * g->items_cap);
+        HIP_TRY(hipMalloc(&g->d_items, g->items_cap * sizeof(int2)));
+    }
+    if (!items.empty()) HIP_TRY(hipMemcpy(g->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+    g->n_items = int(items.size());
+    group_drop_graph(g);
+    g->dirty = false;
+    return LB_OK;
+}
+
+// Enqueue nsteps group steps on the group's stream (one predictor, one
+// corrector and one counter tick per step).
+hipError_t group_enqueue(lb_group* g, int64_t nsteps) {
+    for (int64_t n = 0; n < nsteps; ++n) {
+        hipError_t e = launch_fv_multi(g->storage, g->thermal, false, g->d_args, g->d_items, g->n_items, g->d_left, g->stream);
+        if (e == hipSuccess)
+            e = launch_fv_multi(g->storage, g->thermal, true, g->d_args, g->d_items, g->n_items, g->d_left, g->stream);
+        if (e == hipSuccess) e = launch_tick(g->d_left, g->max_sims, g->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_group_create(int32_t max_sims, void* stream, lb_group** out) {
+    if (!out || max_sims < 1 || max_sims > 65536) return fail(LB_EINVAL, "lb_group_create: 1 <= max_sims <= 65536");
+    *out = nullptr;
+    lb_group* g = new (std::nothrow) lb_group();
+    if (!g) return fail(LB_ENOMEM, "lb_group_create: out of host memory");
+    g->max_sims = max_sims;
+    g->sims.assign(max_sims, nullptr);
+    hipError_t e = hipSuccess;
+    if (stream) {
+        g->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);  // default priority
+        g->own_stream = e == hipSuccess;
+    }
+    const size_t ab = std::max(fv_args_bytes(LB_F64), fv_args_bytes(LB_F32));
+    if (e == hipSuccess) e = hipMalloc(&g->d_args, 2 * size_t(max_sims) * ab);
+    if (e == hipSuccess) e = hipMalloc(&g->d_left, sizeof(int64_t) * max_sims);
+    if (e == hipSuccess) {
+        std::vector<int64_t> z(max_sims, 0);
+        e = hipMemcpy(g->d_left, z.data(), sizeof(int64_t) * max_sims, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        lb_group_destroy(g);
+        return fail(LB_EDEVICE, "lb_group_create: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return LB_OK;
+}
+
+void lb_group_destroy(lb_group* g) {
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    group_drop_graph(g);
+    if (g->d_args) (void)hipFree(g->d_args);
+    if (g->d_items) (void)hipFree(g->d_items);
+    if (g->d_left) (void)hipFree(g->d_left);
+    if (g->own_stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
+    if (!g || !s || !slot) return fail(LB_EINVAL, "lb_group_add: NULL argument");
+    if (steps < 0) return fail(LB_EINVAL, "lb_group_add: negative step count");
+    if (s->p.scheme != LB_FV_HEUN) return fail(LB_EINVAL, "lb_group_add: members must use LB_FV_HEUN");
+    if (!s->has_init) return fail(LB_ESTATE, "lb_group_add: the simulation has no state yet");
+    if (g->storage >= 0 && (s->p.storage != g->storage || s->p.thermal != g->thermal))
+        return fail(LB_EINVAL, "lb_group_add: members must share storage format and thermal flag");
+    for (lb_sim* m : g->sims)
+        if (m == s) return fail(LB_EINVAL, "lb_group_add: already a member");
+    int k = 0;
+    while (k < g->max_sims && g->sims[k]) ++k;
+    if (k == g->max_sims) return fail(LB_ENOMEM, "lb_group_add: all %d slots are taken", g->max_sims);
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(g->d_left + k, &steps, sizeof(int64_t), hipMemcpyHostToDevice));
+    g->storage = s->p.storage;
+    g->thermal = s->p.thermal;
+    s->chunk_h = GROUP_CHUNK;
+    g->sims[k] = s;
+    g->dirty = true;
+    *slot = k;
+    return LB_OK;
+}
+
+int lb_group_remove(lb_group* g, int32_t slot) {
+    if (!g || slot < 0 || slot >= g->max_sims || !g->sims[slot]) return fail(LB_EINVAL, "lb_group_remove: bad slot");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    const int64_t zero = 0;
+    HIP_TRY(hipMemcpy(g->d_left + slot, &zero, sizeof zero, hipMemcpyHostToDevice));
+    g->sims[slot] = nullptr;
+    g->dirty = true;
+    bool any = false;
+    for (lb_sim* m : g->sims) any = any || m;
+    if (!any) { g->storage = -1; g->thermal = -1; }
+    return LB_OK;
+}
+
+int lb_group_step(lb_group* g, int64_t nsteps) {
+    if (!g) return fail(LB_EINVAL, "lb_group_step: NULL group");
+    if (nsteps < 0) return fail(LB_EINVAL, "lb_group_step: negative step count");
+    if (nsteps == 0) return LB_OK;
+    if (g->dirty) {
+        if (int rc = group_rebuild(g)) return rc;
+    }
+    if (g->n_items == 0) return LB_OK;
+    if (!g->exec || g->exec_steps != nsteps) {
+        group_drop_graph(g);
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = group_enqueue(g, nsteps);
+        hipError_t e2 = hipStreamEndCapture(g->stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(LB_EDEVICE, "lb_group_step: graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g->exec = nullptr;
+            return fail(LB_EDEVICE, "lb_group_step: graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        g->exec_steps = nsteps;
+    }
+    HIP_TRY(hipGraphLaunch(g->exec, g->stream));
+    return LB_OK;
+}
+
+int lb_group_sync(lb_group* g) {
+    if (!g) return fail(LB_EINVAL, "lb_group_sync: NULL group");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return LB_OK;
+}
+
+int lb_group_remaining(lb_group* g, int64_t* left) {
+    if (!g || !left) return fail(LB_EINVAL, "lb_group_remaining: NULL argument");
+    HIP_TRY(hipMemcpyAsync(left, g->d_left, sizeof(int64_t) * g->max_sims, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return LB_OK;
+}
+
+}  // extern "C"

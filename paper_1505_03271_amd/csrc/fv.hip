@@ -313,20 +313,24 @@ __device__ inline void lanes_sync() {
     }
 }
 
+// Work item of block b.  Blocks are dealt to the eight XCDs round robin, so
+// block b runs on XCD b % 8; items are numbered chunk-major (adjacent strips
+// of a chunk are consecutive) and each XCD takes a contiguous range of them,
+// so strips that share halo columns run side by side on one XCD and meet in
+// its L2.
+__device__ inline int xcd_item(int b, int n_items) {
+    const int per_xcd = (n_items + 7) / 8;
+    return (b % 8) * per_xcd + b / 8;
+}
+
+// One FV stage over work item `item` (strip item % n_strips, chunk
+// item / n_strips) of the simulation described by A.
 template <class R, class S, bool TH, bool CORR>
-__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvArgs<R> A) {
+__device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     constexpr int NSP = TH ? 2 : 1;
     __shared__ R lds[2][6 * NSP][FV_LANES];
 
     const int t = threadIdx.x;
-    // Work item of this block.  Blocks are dealt to the eight XCDs round
-    // robin, so block b runs on XCD b % 8; items are numbered chunk-major
-    // (adjacent strips of a chunk are consecutive) and each XCD takes a
-    // contiguous range of them, so strips that share halo columns run side by
-    // side on one XCD and meet in its L2.
-    const int per_xcd = (A.n_items + 7) / 8;
-    const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (item >= A.n_items) return;
     const int strip = item % A.n_strips, chunk = item / A.n_strips;
     const int x0 = strip * A.strip_w;
     const int own = min(A.strip_w, A.nx - x0);
@@ -559,6 +563,83 @@ __global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvAr
         row_step(r + 3, Slot<3>{});
     }
 }
+
+// One simulation: arguments by value.
+template <class R, class S, bool TH, bool CORR>
+__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvArgs<R> A) {
+    const int item = xcd_item(blockIdx.x, A.n_items);
+    if (item >= A.n_items) return;
+    fv_item<R, S, TH, CORR>(A, item);
+}
+
+// Many simulations in one launch (serving): a table of per-simulation
+// arguments (predictor and corrector entry per simulation), a work list of
+// (simulation, local item) pairs, and per-simulation remaining steps; the
+// items of a simulation that has finished are skipped.  Every item runs the
+// same code as in fv_pass, so a simulation's result does not depend on what
+// else shares the launch.
+template <class R, class S, bool TH, bool CORR>
+__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1)
+    fv_pass_multi(const FvArgs<R>* args, const int2* items, int n_items, const int64_t* left) {
+    const int w = xcd_item(blockIdx.x, n_items);
+    if (w >= n_items) return;
+    const int2 it = items[w];
+    if (left[it.x] <= 0) return;
+    // the argument block is uniform: copy it word by word with scalar loads
+    static_assert(sizeof(FvArgs<R>) % 4 == 0, "argument block in words");
+    typedef const __attribute__((address_space(4))) uint32_t CW;
+    CW* src = (CW*)(args + 2 * it.x + (CORR ? 1 : 0));
+    uint32_t words[sizeof(FvArgs<R>) / 4];
+#pragma unroll
+    for (int q = 0; q < int(sizeof(FvArgs<R>) / 4); ++q) words[q] = src[q];
+    FvArgs<R> A;
+    __builtin_memcpy(&A, words, sizeof(FvArgs<R>));
+    fv_item<R, S, TH, CORR>(A, it.y);
+}
+
+__global__ void tick_kernel(int64_t* left, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && left[i] > 0) left[i] -= 1;
+}
+
+template <class R, class S>
+static hipError_t launch_multi_typed(bool thermal, bool corrector, const void* args, const int2* items, int n_items,
+                                     const int64_t* left, hipStream_t s) {
+    const FvArgs<R>* a = static_cast<const FvArgs<R>*>(args);
+    dim3 grid(8 * ((n_items + 7) / 8)), block(FV_LANES);
+    if (thermal) {
+        if (corrector)
+            hipLaunchKernelGGL((fv_pass_multi<R, S, true, true>), grid, block, 0, s, a, items, n_items, left);
+        else
+            hipLaunchKernelGGL((fv_pass_multi<R, S, true, false>), grid, block, 0, s, a, items, n_items, left);
+    } else {
+        if (corrector)
+            hipLaunchKernelGGL((fv_pass_multi<R, S, false, true>), grid, block, 0, s, a, items, n_items, left);
+        else
+            hipLaunchKernelGGL((fv_pass_multi<R, S, false, false>), grid, block, 0, s, a, items, n_items, left);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void* args, const int2* items,
+                           int n_items, const int64_t* left, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (storage) {
+        case ST_F64: return launch_multi_typed<double, double>(thermal, corrector, args, items, n_items, left, s);
+        case ST_F32: return launch_multi_typed<float, float>(thermal, corrector, args, items, n_items, left, s);
+        case ST_BF16: return launch_multi_typed<float, bf16_t>(thermal, corrector, args, items, n_items, left, s);
+        case ST_F16: return launch_multi_typed<float, f16_t>(thermal, corrector, args, items, n_items, left, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tick(int64_t* left, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tick_kernel, dim3((n + 255) / 256), dim3(256), 0, s, left, n);
+    return hipGetLastError();
+}
+
+size_t fv_args_bytes(int storage) { return storage == ST_F64 ? sizeof(FvArgs<double>) : sizeof(FvArgs<float>); }
 
 template <class R, class S>
 static hipError_t launch_typed(bool thermal, bool corrector, const void* args, hipStream_t s) {

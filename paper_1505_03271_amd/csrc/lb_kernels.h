@@ -67,6 +67,14 @@ struct StArgs {
 // Host launchers (defined in the .hip files).  `storage` selects the
 // template instance; every launcher returns the hipError_t of the launch.
 hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
+// Serving: one launch over the work items of many simulations.  args holds
+// 2 FvArgs per simulation (predictor, corrector); items are (simulation,
+// local item); left[s] is the number of steps simulation s still has to do.
+hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void* args, const int2* items,
+                           int n_items, const int64_t* left, hipStream_t s);
+hipError_t launch_tick(int64_t* left, int n, hipStream_t s);
+size_t fv_args_bytes(int storage);
+
 // True when the Heun predictor stores H = (f~n + C)/2 for the corrector.
 bool fv_heun_h();
 // Largest number of FV blocks of one launch that are resident at once.

@@ -1,0 +1,118 @@
+"""Continuous-batching service of Rayleigh-Benard FV-LB runs on one GPU.
+
+Requests (grid side n, Ra, Pr, steps) arrive over time.  A request is
+admitted as soon as a group slot is free and its device memory fits the HBM
+budget; admission and completion happen only between group launches (graph
+boundaries), so requests that arrive while others run join them in the next
+launch and their work overlaps on the device.  Every admitted simulation
+keeps its state resident in HBM until it has done exactly its steps; then
+its Nusselt numbers are read (FP64 device reductions) and its memory is
+released.
+
+    from paper_1505_03271_amd.serve import Server
+    stats = Server(storage="bf16", hbm_budget=16e9).run(trace)
+
+The physical set-up of a request follows the paper's recipe for its
+Rayleigh-Benard runs (sec. 5): tau = tau_g = 1/2 for the smaller relaxation
+time, free-fall velocity about 0.1, tanh wall refinement, periodic sides;
+see workloads.rb_params.
+"""
+import time
+from collections import deque
+
+import numpy as np
+
+from . import Group, Sim, current_stream, STORAGE_BYTES
+
+
+def request_bytes(n, storage, thermal=True):
+    """Device memory of one request: two population buffers plus metric."""
+    q = 18 if thermal else 9
+    return 2 * q * n * n * STORAGE_BYTES[storage] + 64 * n + 4096
+
+
+class Server:
+    def __init__(self, storage="bf16", hbm_budget=16e9, max_sims=128, graph_steps=100, stream=None,
+                 stretch=2.0):
+        self.storage = storage
+        self.hbm_budget = float(hbm_budget)
+        self.graph_steps = int(graph_steps)
+        self.stretch = stretch
+        self.stream = stream if stream is not None else current_stream()
+        self.group = Group(max_sims, self.stream)
+        self.max_sims = max_sims
+
+    def _make(self, req):
+        import workloads
+        n = req["n"]
+        P = workloads.rb_params(req["Ra"], req["Pr"], n, n, aspect=1.0, stretch=self.stretch)
+        rho, ux, uy, T = workloads.rb_fields(n, P["yf"], P["dT"], P["T0"], P["beta_g"],
+                                            seed_index=1000 + req["id"])
+        sim = Sim(n, n, scheme="heun", storage=self.storage, thermal=True, wall_y=True, dt=P["dt"], tau=P["tau"],
+                  tau_g=P["tau_g"], beta_g=P["beta_g"], T0=P["T0"], T_bottom=P["T_bottom"], T_top=P["T_top"],
+                  stream=self.stream)
+        sim.set_grid(P["xf"], P["yf"])
+        sim.init(rho, ux, uy, T)
+        return sim
+
+    def run(self, trace, time_scale=1.0, log=None):
+        """Serve `trace` (list of dicts with id, arrival [s], n, Ra, Pr, steps).
+        Arrival times are replayed on the wall clock (scaled by time_scale).
+        Returns per-request records and summary statistics."""
+        pending = deque(sorted(trace, key=lambda r: r["arrival"]))
+        queue = deque()
+        active = {}    # slot -> (request, sim, admit time)
+        done = []
+        used = 0.0
+        cell_steps = 0
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        launches = 0
+        while pending or queue or active:
+            now = clock()
+            while pending and pending[0]["arrival"] * time_scale <= now:
+                queue.append(pending.popleft())
+            # admission at the graph boundary, first come first served
+            while queue and len(active) < self.max_sims:
+                req = queue[0]
+                need = request_bytes(req["n"], self.storage)
+                if need > self.hbm_budget:
+                    raise ValueError(f"request {req['id']} needs {need:.3e} B, more than the whole budget")
+                if used + need > self.hbm_budget:
+                    break
+                queue.popleft()
+                sim = self._make(req)
+                slot = self.group.add(sim, req["steps"])
+                active[slot] = (req, sim, clock(), need)
+                used += need
+            if not active:
+                if pending:  # idle until the next arrival
+                    time.sleep(max(0.0, pending[0]["arrival"] * time_scale - clock()))
+                continue
+            self.group.step(self.graph_steps)
+            launches += 1
+            left = self.group.remaining()   # synchronises
+            for slot in [s for s in active if left[s] == 0]:
+                req, sim, t_admit, need = active.pop(slot)
+                nu = sim.nusselt()
+                t_done = clock()
+                self.group.remove(slot)
+                sim.close()
+                used -= need
+                cell_steps += req["n"] ** 2 * req["steps"]
+                done.append(dict(id=req["id"], n=req["n"], steps=req["steps"], arrival=req["arrival"] * time_scale,
+                                 admitted=t_admit, finished=t_done, latency=t_done - req["arrival"] * time_scale,
+                                 queue_wait=t_admit - req["arrival"] * time_scale, nu=nu))
+                if log:
+                    log(f"req {req['id']:4d} n={req['n']:5d} steps={req['steps']:6d} "
+                        f"latency {done[-1]['latency']:.2f}s nu_vol={nu[2]:.3f}")
+        makespan = clock()
+        lat = np.array([d["latency"] for d in done])
+        return dict(requests=done, n_requests=len(done), makespan_s=makespan,
+                    p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+                    p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
+                    aggregate_mlups=cell_steps / makespan / 1e6 if makespan > 0 else None,
+                    graph_launches=launches, graph_steps=self.graph_steps)
+
+    def close(self):
+        self.group.close()

@@ -1,0 +1,111 @@
+"""Serving: many simulations in shared launches (lb_group_*) and the
+continuous-batching server.  A member's result must be bit-identical to the
+same simulation run alone, whatever else shares its launches and whenever it
+joins."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1505_03271_amd as lb
+import workloads
+from paper_1505_03271_amd.serve import Server
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
+    P = workloads.rb_params(Ra, Pr, n_x, n_y, aspect=n_x / n_y, stretch=stretch)
+    rho, ux, uy, T = workloads.rb_fields(n_x, P["yf"], P["dT"], P["T0"], P["beta_g"], seed_index=seed)
+    sim = lb.Sim(n_x, n_y, scheme="heun", storage=storage, thermal=True, wall_y=True, dt=P["dt"], tau=P["tau"],
+                 tau_g=P["tau_g"], beta_g=P["beta_g"], T0=P["T0"], T_bottom=P["T_bottom"], T_top=P["T_top"],
+                 stream=lb.current_stream())
+    sim.set_grid(P["xf"], P["yf"])
+    sim.init(rho, ux, uy, T)
+    return sim
+
+
+CASES = [(300, 77, 1e7, 1.0, 31), (128, 128, 1e6, 0.7, 45), (200, 150, 1e8, 7.0, 60), (97, 64, 3e6, 1.0, 0)]
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f32", "f64"])
+def test_group_members_match_alone_bit_exact(storage):
+    say(f"group vs alone {storage}")
+    alone = []
+    for k, (nx, ny, Ra, Pr, steps) in enumerate(CASES):
+        s = _rb_sim(nx, ny, Ra, Pr, storage, 100 + k)
+        s.step(steps)
+        alone.append(s.get_state())
+        s.close()
+    sims = [_rb_sim(nx, ny, Ra, Pr, storage, 100 + k) for k, (nx, ny, Ra, Pr, _) in enumerate(CASES)]
+    g = lb.Group(8, lb.current_stream())
+    slots = {}
+    for k in (0, 1, 3):
+        slots[k] = g.add(sims[k], CASES[k][4])
+    g.step(7)
+    slots[2] = g.add(sims[2], CASES[2][4])   # joins later: continuous batching
+    for _ in range(20):
+        g.step(7)
+    left = g.remaining()
+    assert all(left[slots[k]] == 0 for k in slots)
+    for k in range(len(CASES)):
+        assert np.array_equal(sims[k].get_state(), alone[k]), f"member {k}"
+    for k in slots:
+        g.remove(slots[k])
+    assert g.remaining() == [0] * 8
+    g.close()
+
+
+def test_group_membership_rules():
+    say("group rules")
+    g = lb.Group(2, lb.current_stream())
+    a = _rb_sim(64, 64, 1e6, 1.0, "bf16", 1)
+    b = _rb_sim(64, 64, 1e6, 1.0, "f32", 2)
+    st = lb.Sim(64, 64, scheme="st", storage="bf16", thermal=True, wall_y=True, tau=0.5, tau_g=0.5,
+                stream=lb.current_stream())
+    st.set_grid(workloads.faces_uniform(64, 64), workloads.faces_uniform(64, 64))
+    st.init(np.ones((64, 64)), np.zeros((64, 64)), np.zeros((64, 64)), np.zeros((64, 64)))
+    with pytest.raises(lb.LBError) as e:
+        g.add(st, 10)
+    assert e.value.code == 1
+    s0 = g.add(a, 5)
+    with pytest.raises(lb.LBError) as e:
+        g.add(b, 5)          # different storage format
+    assert e.value.code == 1
+    with pytest.raises(lb.LBError):
+        g.add(a, 5)          # already a member
+    c = _rb_sim(64, 64, 1e6, 1.0, "bf16", 3)
+    d = _rb_sim(64, 64, 1e6, 1.0, "bf16", 4)
+    g.add(c, 0)              # zero steps: never changes
+    before = c.get_state()
+    with pytest.raises(lb.LBError) as e:
+        g.add(d, 5)
+    assert e.value.code == 2  # slots full
+    g.step(10)
+    assert g.remaining()[s0] == 0
+    assert np.array_equal(c.get_state(), before)
+    g.close()
+
+
+def test_server_serves_a_trace_and_results_equal_alone():
+    say("server small trace")
+    trace = workloads.serving_trace(n_requests=8, rate=50.0, side=(64, 160), ra=(1e6, 1e8), steps=(40, 160))
+    server = Server(storage="bf16", hbm_budget=2e8, max_sims=4, graph_steps=25)
+    stats = server.run(trace)
+    server.close()
+    assert stats["n_requests"] == 8
+    assert stats["p50_s"] > 0 and stats["p99_s"] >= stats["p50_s"]
+    by_id = {r["id"]: r for r in stats["requests"]}
+    for req in trace:
+        solo = Server(storage="bf16", max_sims=1)
+        sim = solo._make(req)
+        sim.step(req["steps"])
+        nu = sim.nusselt()
+        sim.close()
+        solo.close()
+        assert by_id[req["id"]]["nu"] == nu, req["id"]
