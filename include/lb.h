@@ -173,6 +173,17 @@ int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
 int lb_set_timing(lb_sim* sim, int enable);
 int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
 
+/* Thermal reference rows (non-F64 storage of a thermal run): the stored g
+ * are offsets from w_a T_ref(row), T_ref(row) starting as the row means of
+ * the initial temperature (lb_init).  lb_rebase sets T_ref(row) to the
+ * current row means and re-encodes the stored g (one rounding); with
+ * lb_set_rebase(every > 0) lb_step does this after every `every` steps
+ * (0, the default, never).  Narrow formats then resolve temperature
+ * differences relative to the local mean profile, which keeps wall heat
+ * fluxes accurate.  No-ops for FP64 storage or isothermal runs. */
+int lb_rebase(lb_sim* sim);
+int lb_set_rebase(lb_sim* sim, int64_t every);
+
 /* Rows per work item of the FV kernels (a launch-shape knob for tuning).
  * By default the height is chosen at the first step so that every item of a
  * launch is resident at once.  Any height >= 1 gives identical results.

@@ -75,6 +75,8 @@ def lib():
             "lb_set_timing": ([h, ctypes.c_int], ctypes.c_int),
             "lb_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
             "lb_set_fv_chunk": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_rebase": ([h], ctypes.c_int),
+            "lb_set_rebase": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_device_bytes": ([h], ctypes.c_size_t),
             "lb_last_error": ([], ctypes.c_char_p),
             "lb_group_create": ([ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(h)], ctypes.c_int),
@@ -222,6 +224,12 @@ class Sim:
         _check(lib().lb_kernel_times(self.h, n, ms))
         names = ["fv_first_pass", "fv_corrector", "st"]
         return {names[k]: (int(n[k]), float(ms[k])) for k in range(3)}
+
+    def rebase(self):
+        _check(lib().lb_rebase(self.h))
+
+    def set_rebase(self, every):
+        _check(lib().lb_set_rebase(self.h, int(every)))
 
     def set_fv_chunk(self, rows):
         _check(lib().lb_set_fv_chunk(self.h, int(rows)))

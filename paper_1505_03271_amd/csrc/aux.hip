@@ -9,9 +9,15 @@
 namespace lbk {
 
 // population a of species sp at cell c, decoded to double
+// reference of species sp at cell c: ref, or the row's thermal reference
+__device__ inline double ref_at(const AuxArgs& A, int sp, int64_t c, double ref) {
+    return (sp == 1 && A.tref) ? double(A.tref[c / A.nx]) : ref;
+}
+
 template <class S>
 __device__ inline double get_pop(const AuxArgs& A, const S* st, int sp, int a, int64_t c, double ref) {
     const int nsp = A.thermal ? 2 : 1;
+    ref = ref_at(A, sp, c, ref);
     double x = Codec<S>::template load<double>(st + pop_index(A.grouped, nsp, A.plane, sp, a, c));
     return Codec<S>::offset ? x + wt<double>(a) * ref : x;
 }
@@ -19,6 +25,7 @@ __device__ inline double get_pop(const AuxArgs& A, const S* st, int sp, int a, i
 template <class S>
 __device__ inline void put_pop(const AuxArgs& A, S* st, int sp, int a, int64_t c, double ref, double v) {
     const int nsp = A.thermal ? 2 : 1;
+    ref = ref_at(A, sp, c, ref);
     double x = Codec<S>::offset ? v - wt<double>(a) * ref : v;
     Codec<S>::template store<double>(st + pop_index(A.grouped, nsp, A.plane, sp, a, c), x);
 }
@@ -98,6 +105,56 @@ __global__ void set_pops_kernel(AuxArgs A, const double* in) {
     for (int s = 0; s < ns; ++s)
         for (int a = 0; a < 9; ++a)
             put_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f, in[(s * 9 + a) * A.plane + c]);
+}
+
+// ---- per-row thermal reference update ----------------------------------
+// One block per row: the row mean of T becomes the row's new reference and
+// every stored g of the row is re-encoded, d_new = d_old + w_a (old - new).
+template <class S>
+__global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
+    __shared__ double red[4];
+    __shared__ float newref;
+    const int j = blockIdx.x;
+    S* st = static_cast<S*>(A.state);
+    double sum = 0.0;
+    for (int i = threadIdx.x; i < A.nx; i += 256) {
+        const int64_t c = int64_t(j) * A.nx + i;
+        for (int a = 0; a < 9; ++a) sum += get_pop(A, st, 1, a, c, A.ref_g);
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) newref = float((red[0] + red[1] + red[2] + red[3]) / A.nx);
+    __syncthreads();
+    const float oldref = A.tref[j];
+    const float nr = newref;
+    for (int i = threadIdx.x; i < A.nx; i += 256) {
+        const int64_t c = int64_t(j) * A.nx + i;
+        const int nsp = 2;
+        for (int a = 0; a < 9; ++a) {
+            S* p = st + pop_index(A.grouped, nsp, A.plane, 1, a, c);
+            const double d = Codec<S>::template load<double>(p);
+            Codec<S>::template store<double>(p, d + wt<double>(a) * (double(oldref) - double(nr)));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) const_cast<float*>(A.tref)[j] = nr;
+}
+
+template <class S>
+static hipError_t rebase_typed(const AuxArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(rebase_kernel<S>, dim3(a.ny), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s) {
+    if (!a.tref || !a.thermal) return hipSuccess;
+    switch (storage) {
+        case ST_F32: return rebase_typed<float>(a, s);
+        case ST_BF16: return rebase_typed<bf16_t>(a, s);
+        case ST_F16: return rebase_typed<f16_t>(a, s);
+    }
+    return hipSuccess;
 }
 
 // ---- diagnostics -------------------------------------------------------

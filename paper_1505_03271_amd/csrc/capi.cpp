@@ -139,6 +139,8 @@ struct lb_sim {
     double* dxy = nullptr;    // dx[nx], dy[ny] in double
     double* partial = nullptr;
     double* dout = nullptr;
+    float* tref = nullptr;    // per-row thermal reference of the stored g (thermal, non-F64 storage)
+    int64_t rebase_every = 0, since_rebase = 0;
     size_t metric_bytes = 0;
     bool has_grid = false, has_init = false, unstable = false;
     std::vector<double> xf, yf;
@@ -168,6 +170,7 @@ void release(lb_sim* s) {
     if (s->dxy) (void)hipFree(s->dxy);
     if (s->partial) (void)hipFree(s->partial);
     if (s->dout) (void)hipFree(s->dout);
+    if (s->tref) (void)hipFree(s->tref);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     s->events.clear();
 }
@@ -190,6 +193,7 @@ AuxArgs aux_args(const lb_sim* s) {
     a.dx = s->dxy;
     a.dy = s->dxy + s->p.nx;
     a.grouped = s->p.scheme != LB_ST;
+    a.tref = s->tref;
     return a;
 }
 
@@ -249,8 +253,9 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     fill_stage_k<R>(s->p, a.k);
     const double k1g = s->p.scheme == LB_FV_EULER ? 0.0 : s->p.dt / (2.0 * (s->p.tau_g + 0.5 * s->p.dt));
     const double rg = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
-    a.Twb = R(s->p.T_bottom - (1.0 - k1g) * rg);
-    a.Twt = R(s->p.T_top - (1.0 - k1g) * rg);
+    a.Tb = R(s->p.T_bottom);
+    a.Tt = R(s->p.T_top);
+    a.tref = reinterpret_cast<const R*>(s->tref);  // float rows for FP32 arithmetic, NULL for FP64
     return a;
 }
 
@@ -330,6 +335,7 @@ int st_launch(lb_sim* s) {
     a.T_top = s->p.T_top;
     a.ref_f = s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref;
     a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
+    a.tref = s->tref;
     int rc = record_event(s, 2);
     if (rc) return rc;
     hipError_t e = launch_st(s->p.storage, s->p.thermal, (s->p.flags & LB_FLAG_STREAM_ONLY) != 0, a, s->stream);
@@ -437,7 +443,8 @@ int lb_create(const lb_params* p, lb_sim** out) {
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
             (p->scheme == LB_FV_HEUN && fv_heun_h() && (e = hipMalloc(&s->H, s->state_bytes)) != hipSuccess) ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
-            (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess) {
+            (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess ||
+            (p->thermal && p->storage != LB_F64 && (e = hipMalloc(&s->tref, sizeof(float) * p->ny)) != hipSuccess)) {
             release(s);
             delete s;
             return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "lb_create: device allocation failed: %s",
@@ -515,6 +522,16 @@ int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, co
     if (!s->has_grid) return fail(LB_ESTATE, "lb_init: call lb_set_grid first");
     if (!rho || !ux || !uy || (s->p.thermal && !T)) return fail(LB_EINVAL, "lb_init: NULL field");
     const size_t n = size_t(s->plane);
+    if (s->tref) {
+        // the stored g are offsets from w_a times the row mean of the initial T
+        std::vector<float> tr(s->p.ny);
+        for (int j = 0; j < s->p.ny; ++j) {
+            double m = 0.0;
+            for (int i = 0; i < s->p.nx; ++i) m += T[size_t(j) * s->p.nx + i];
+            tr[j] = float(m / s->p.nx);
+        }
+        HIP_TRY(hipMemcpy(s->tref, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice));
+    }
     double *d[4] = {nullptr, nullptr, nullptr, nullptr};
     const double* h[4] = {rho, ux, uy, s->p.thermal ? T : rho};
     int rc = LB_OK;
@@ -556,7 +573,15 @@ int lb_step(lb_sim* s, int64_t nsteps) {
                 if ((rc = st_launch(s))) return rc;
         }
     }
-    if (nsteps > 0) return record_event(s, -1);
+    if (nsteps > 0) {
+        if (int rc = record_event(s, -1)) return rc;
+        s->since_rebase += nsteps;
+        if (s->tref && s->rebase_every > 0 && s->since_rebase >= s->rebase_every) {
+            hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
+            s->since_rebase = 0;
+        }
+    }
     return LB_OK;
 }
 
@@ -681,8 +706,26 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return (s->H ? 3 : 2) * s->state_bytes + s->metric_bytes + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return (s->H ? 3 : 2) * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
+}
+
+int lb_rebase(lb_sim* s) {
+    if (int rc = check_sim(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb_rebase: no state");
+    if (!s->tref) return LB_OK;
+    hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
+    s->since_rebase = 0;
+    return LB_OK;
+}
+
+int lb_set_rebase(lb_sim* s, int64_t every) {
+    if (int rc = check_sim(s)) return rc;
+    if (every < 0) return fail(LB_EINVAL, "lb_set_rebase: negative interval");
+    s->rebase_every = every;
+    s->since_rebase = 0;
+    return LB_OK;
 }
 
 int lb_set_fv_chunk(lb_sim* s, int rows) {

@@ -227,9 +227,10 @@ template <> __device__ inline float recip<float>(float x) { return __builtin_amd
 
 // One semi-implicit stage at a cell, in offset space.  Writes the advected
 // brackets ph[s][a] (shifted by (1 - k1) w_a ref) of the moving populations
-// and, when BASE, the offsets of f~ + C (all populations).
+// and, when BASE, the offsets of f~ + C (all populations).  Tr is the
+// thermal reference of the cell's row (g is stored as g - w_a Tr).
 template <class R, bool TH, bool BASE>
-__device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, R (*ph)[9], R (*bs)[9]) {
+__device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
     constexpr int NSP = TH ? 2 : 1;
     R rho = df[0], jx = 0, jy = 0;
 #pragma unroll
@@ -244,7 +245,7 @@ __device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, R (*p
         T = dg[0];
 #pragma unroll
         for (int a = 1; a < 9; ++a) T += dg[a];
-        T += k.ref_g;
+        T += Tr;
         ay = k.ay + k.bg * (T - k.T0);
     }
     const R ax = k.ax;
@@ -263,7 +264,7 @@ __device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, R (*p
     if (BASE) {
         const R A0 = k.kc * e0 - k.kf * ua3;
         bs[0][0] = k.omkc * df[0] + (wr[0] * A0 - k.kcwref[0]);
-        if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcgw[0] * (T * e0 - k.ref_g);
+        if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcgw[0] * (T * e0 - Tr);
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -286,8 +287,8 @@ __device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, R (*p
             ph[NSP - 1][a] = k.omk1g * dg[a] + wt1[cl] * (E + O);
             ph[NSP - 1][b] = k.omk1g * dg[b] + wt1[cl] * (E - O);
             if (BASE) {
-                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcgw[cl] * (T * (E + O) - k.ref_g);
-                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcgw[cl] * (T * (E - O) - k.ref_g);
+                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcgw[cl] * (T * (E + O) - Tr);
+                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcgw[cl] * (T * (E - O) - Tr);
             }
         }
         if (BASE) {
@@ -367,6 +368,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // rings: phi of c_y=+1 and c_y=-1 populations of the last four rows,
     // partial updates (all but the y flux) of the last two rows
     R UP[4][NSP][3], DN[4][NSP][3], U[2][NSP][9];
+    R TRg[4] = {0, 0, 0, 0};  // thermal reference of the rows in the UP/DN rings
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -411,7 +413,11 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
         const bool my = A.wall_y && (r < 0 || r >= A.ny);
-        const R Tw = r < 0 ? A.Twb : A.Twt;
+        // thermal reference of this row (uniform; ghost rows use their mirror's)
+        R Tr = k.ref_g;
+        if (TH && A.tref) Tr = ((const CR*)A.tref)[map_row(r)];
+        // wall temperature for the anti-reflection of the shifted brackets
+        const R Tw = (r < 0 ? A.Tb : A.Tt) - k.omk1g * Tr;
 
         if (!AHEAD) prefetch(r, Slot<SL>{});
         R df[9], dg[9];
@@ -425,8 +431,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             load_cell<R, S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, ro, PH[SL & 1], PHG[SL & 1]);
 
         R ph[NSP][9], bs[NSP][9];
-        if (CORR) stage<R, TH, false>(df, dg, k, ph, bs);
-        else stage<R, TH, true>(df, dg, k, ph, bs);
+        if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
+        else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
 
         // ghost row (y walls): double reflection of f, anti-reflection of g
         {
@@ -463,6 +469,16 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) yc[q] = yw[q];
         }
+        // A per-row thermal reference shifts the stored brackets of g by
+        // (1 - k1g) w_a Tr(row); across rows the shift does not cancel from
+        // the y stencil, so its contribution is added back (uniform per row).
+        R sU = 0, sD = 0;
+        if (TH && A.tref) {
+            sU = k.omk1g * (yc[0] * TRg[SL] + yc[1] * TRg[(SL + 1) & 3] + yc[2] * TRg[(SL + 2) & 3] +
+                            yc[3] * TRg[(SL + 3) & 3]);
+            sD = k.omk1g * (yc[4] * TRg[(SL + 1) & 3] + yc[5] * TRg[(SL + 2) & 3] + yc[6] * TRg[(SL + 3) & 3] +
+                            yc[7] * Tr);
+        }
         if (owned && j >= y0 && j < y1) {
             R out[NSP][9];
 #pragma unroll
@@ -477,6 +493,10 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                     // c_y = -1: rows j-1 .. j+2 = r-3 .. r
                     out[s][dpop(p)] -= yc[4] * DN[(SL + 1) & 3][s][p] + yc[5] * DN[(SL + 2) & 3][s][p] +
                                        yc[6] * DN[(SL + 3) & 3][s][p] + yc[7] * ph[s][dpop(p)];
+                    if (TH && s == NSP - 1) {
+                        out[s][upop(p)] -= wt<R>(upop(p)) * sU;
+                        out[s][dpop(p)] -= wt<R>(dpop(p)) * sD;
+                    }
                 }
             }
             store_cell<R, S, TH>(bdst, uint32_t(j) * nxu + colu, gb, ro, out[0], out[NSP - 1]);
@@ -503,7 +523,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             } else if (CORR) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
                 R phn[NSP][9], bn[NSP][9];
-                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, phn, bn);
+                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
                     base[0][a] = R(0.5) * (bn[0][a] + df[a]);
@@ -543,6 +563,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             }
         }
         // ---- push this row into the rings ----
+        TRg[SL] = Tr;
 #pragma unroll
         for (int s = 0; s < NSP; ++s)
 #pragma unroll

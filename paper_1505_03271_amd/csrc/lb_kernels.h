@@ -50,7 +50,8 @@ struct FvArgs {
     const R* xcoef;    // [nx][8] four-point flux weights (c>0: i-2..i+1, c<0: i-1..i+2), times dt or dt/2
     const R* ycoef;    // [ny][8]
     StageK<R> k;
-    R Twb, Twt;        // wall temperatures for the g anti-reflection, shifted: T_w - (1 - k1g) T_ref
+    R Tb, Tt;          // wall temperatures (bottom, top) for the isothermal anti-reflection of g
+    const R* tref;     // per-row thermal reference (g stored as g - w_a tref[row]), or NULL: k.ref_g
 };
 
 struct StArgs {
@@ -62,6 +63,7 @@ struct StArgs {
     double tau, tau_g;   // paper's tau; tau~ = tau + 1/2
     double ax, ay, bg, T0, T_bottom, T_top;
     double ref_f, ref_g;
+    const float* tref;   // per-row thermal reference of the stored g, or NULL
 };
 
 // Host launchers (defined in the .hip files).  `storage` selects the
@@ -87,6 +89,7 @@ struct AuxArgs {
     int64_t plane;
     int thermal;
     int grouped;       // 1: grouped layout (FV schemes), 0: SoA (ST)
+    const float* tref; // per-row thermal reference of the stored g, or NULL: ref_g
     double hdt;        // velocity shift dt/2 (0 for Euler)
     double ax, ay, bg, T0;
     double ref_f, ref_g;
@@ -100,6 +103,8 @@ hipError_t launch_moments(int storage, const AuxArgs& a, double* rho, double* ux
                           double* T, hipStream_t s);
 hipError_t launch_get_pops(int storage, const AuxArgs& a, double* out, hipStream_t s);
 hipError_t launch_set_pops(int storage, const AuxArgs& a, const double* in, hipStream_t s);
+// New per-row thermal references = row means of T; stored g re-encoded.
+hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s);
 
 // Diagnostics: per-block FP64 partial sums, then one block folds them in a
 // fixed order (bit-reproducible).  Output slots:

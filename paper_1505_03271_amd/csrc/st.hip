@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
 
     // destination slot of each population
     int64_t slot[9];
-    int yhit[9];
+    int yhit[9], drow[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int ti = i + cx(a), tj = j + cy(a);
@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
             if (A.wall_x) hit = true; else ti = ti < 0 ? ti + A.nx : ti - A.nx;
         }
         slot[a] = hit ? int64_t(opp(a)) * plane + cell : int64_t(a) * plane + int64_t(tj) * A.nx + ti;
+        drow[a] = hit ? j : tj;
     }
 
     if (RAW) {
@@ -49,7 +50,8 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
         return;
     }
 
-    const R rf = R(A.ref_f), rg = R(A.ref_g);
+    // g is stored relative to the row's thermal reference when one is kept
+    const R rf = R(A.ref_f), rg = A.tref ? R(A.tref[j]) : R(A.ref_g);
     R f[9], g[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -82,7 +84,8 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
         if (TH) {
             R gp = g[a] + kcg * (wt<R>(a) * m.T * e.poly[a] - g[a]);
             if (yhit[a] != 0) gp = R(2) * wt<R>(a) * (yhit[a] < 0 ? Tb : Tt) - gp;
-            R y = Codec<S>::offset ? gp - wt<R>(a) * rg : gp;
+            const R rgd = A.tref ? R(A.tref[drow[a]]) : rg;
+            R y = Codec<S>::offset ? gp - wt<R>(a) * rgd : gp;
             Codec<S>::template store<R>(dst + 9 * plane + slot[a], y);
         }
     }
