@@ -62,7 +62,15 @@ enum lb_storage {
     LB_F64 = 0,   /* double populations, double arithmetic (parity path) */
     LB_F32 = 1,   /* float offsets f - w rho_ref, float arithmetic */
     LB_BF16 = 2,  /* bfloat16 offsets (round to nearest even), float arithmetic */
-    LB_F16 = 3    /* IEEE half offsets (round to nearest even), float arithmetic */
+    LB_F16 = 3,   /* IEEE half offsets (round to nearest even), float arithmetic */
+    /* Moment-split storage, FV schemes only: per cell the conserved moments
+     * (rho - rho_ref, j = sum c f~, T - T_row) in float and the residuals
+     * f~ - (f_eq - dt/2 F) and g - g_eq of 6 + 8 populations in 16 bits (the
+     * other residuals follow from zero mass and momentum), 44 bytes per
+     * thermal cell.  Small per-step increments of the moments are kept at
+     * float resolution where plain 16-bit offsets would round them away. */
+    LB_BF16S = 4, /* residuals in bfloat16 */
+    LB_F16S = 5   /* residuals in IEEE half, scaled by 2^10 */
 };
 
 enum lb_boundary {

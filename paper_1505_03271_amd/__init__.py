@@ -20,8 +20,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblb.so")
 
 SCHEMES = {"heun": 0, "semi": 1, "euler": 2, "st": 3}
-STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16s": 4, "f16s": 5}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def cell_bytes(storage, thermal=True):
+    """Bytes of one cell of one population state in `storage`."""
+    if storage in ("bf16s", "f16s"):   # float moments + 16-bit residuals
+        return 44 if thermal else 24
+    return (18 if thermal else 9) * STORAGE_BYTES[storage]
 FLAG_STREAM_ONLY = 1
 STATUS = {0: "LB_OK", 1: "LB_EINVAL", 2: "LB_ENOMEM", 3: "LB_EDEVICE", 4: "LB_ESTATE", 5: "LB_EUNSTABLE"}
 

@@ -4,6 +4,8 @@
 // exactly (every storage format widens exactly to double) and the moments
 // follow the relations of arXiv:1505.03271 sec. 2.1 and "Force term"
 // (rho = sum f~, u = sum c f~ / rho + dt/2 a) and sec. 5 (T = sum g~).
+#include <type_traits>
+
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -30,6 +32,97 @@ __device__ inline void put_pop(const AuxArgs& A, S* st, int sp, int a, int64_t c
     Codec<S>::template store<double>(st + pop_index(A.grouped, nsp, A.plane, sp, a, c), x);
 }
 
+// ---- moment-split cells (SplitLayout), decoded and encoded in double ----
+template <class S> __device__ inline double split_get(const char* st, int64_t off) {
+    const uint16_t b = *reinterpret_cast<const uint16_t*>(st + off);
+    double x;
+    if constexpr (std::is_same<S, bf16s_t>::value) x = double(bf16_bits_to_float(b));
+    else x = double(__half2float(__ushort_as_half(b)));
+    return x / double(split_scale<S>::value);
+}
+template <class S> __device__ inline void split_put(char* st, int64_t off, double r) {
+    const float x = float(r * double(split_scale<S>::value));
+    uint16_t b;
+    if constexpr (std::is_same<S, bf16s_t>::value) b = float_to_bf16_bits(x);
+    else b = __half_as_ushort(__float2half_rn(x));
+    *reinterpret_cast<uint16_t*>(st + off) = b;
+}
+
+// Offsets e_a = E_a - w_a ref of the forced equilibrium at moments m (f:
+// E = f_eq - dt/2 F, g: E = g_eq), with the row reference Tr of g.
+__device__ inline void split_eq_d(const AuxArgs& A, const double* m, double Tr, double (*e)[9]) {
+    const double rho = m[0] + A.ref_f, T = A.thermal ? m[3] + Tr : 0.0;
+    const double ay = A.thermal ? A.ay + A.bg * (T - A.T0) : A.ay;
+    const double ux = m[1] / rho + A.hdt * A.ax, uy = m[2] / rho + A.hdt * ay;
+    const double uu = 1.5 * (ux * ux + uy * uy), ua = ux * A.ax + uy * ay;
+    for (int a = 0; a < 9; ++a) {
+        const double cu = cx(a) * ux + cy(a) * uy, ca = cx(a) * A.ax + cy(a) * ay;
+        const double pm1 = 3.0 * cu + 4.5 * cu * cu - uu;          // f_eq / (w rho) - 1
+        const double fr = 3.0 * (ca - ua) + 9.0 * cu * ca;         // F / (w rho)
+        e[0][a] = wt<double>(a) * (m[0] + rho * (pm1 - A.hdt * fr));
+        e[1][a] = A.thermal ? wt<double>(a) * (m[3] + T * pm1) : 0.0;
+    }
+}
+
+__device__ inline SplitLayout split_layout(const AuxArgs& A) { return SplitLayout{A.thermal != 0, A.plane}; }
+__device__ inline double row_ref(const AuxArgs& A, int64_t c) { return A.tref ? double(A.tref[c / A.nx]) : A.ref_g; }
+
+template <class S> __device__ inline void split_moments(const AuxArgs& A, int64_t c, double* m) {
+    const SplitLayout L = split_layout(A);
+    const char* st = static_cast<const char*>(A.state);
+    for (int q = 0; q < 4; ++q)
+        m[q] = (q < 3 || A.thermal) ? double(*reinterpret_cast<const float*>(st + L.mom(q, c))) : 0.0;
+}
+
+// populations p[s][a] of cell c
+template <class S> __device__ inline void split_decode_d(const AuxArgs& A, int64_t c, double (*p)[9]) {
+    const SplitLayout L = split_layout(A);
+    const char* st = static_cast<const char*>(A.state);
+    double m[4], e[2][9], r[2][9];
+    split_moments<S>(A, c, m);
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 9; ++a) {
+            const int k = split_slot(s, a);
+            r[s][a] = (k >= 0 && (s == 0 || A.thermal)) ? split_get<S>(st, L.res(k, c)) : 0.0;
+        }
+    r[0][1] = r[0][3] - r[0][5] + r[0][6] + r[0][7] - r[0][8];
+    r[0][2] = r[0][4] - r[0][5] - r[0][6] + r[0][7] + r[0][8];
+    for (int s = 0; s < 2; ++s) {
+        double t = 0.0;
+        for (int a = 1; a < 9; ++a) t += r[s][a];
+        r[s][0] = -t;
+    }
+    const double Tr = row_ref(A, c);
+    split_eq_d(A, m, Tr, e);
+    for (int a = 0; a < 9; ++a) {
+        p[0][a] = e[0][a] + r[0][a] + wt<double>(a) * A.ref_f;
+        p[1][a] = A.thermal ? e[1][a] + r[1][a] + wt<double>(a) * Tr : 0.0;
+    }
+}
+
+template <class S> __device__ inline void split_encode_d(const AuxArgs& A, int64_t c, const double (*p)[9]) {
+    const SplitLayout L = split_layout(A);
+    char* st = static_cast<char*>(A.state);
+    const double Tr = row_ref(A, c);
+    double d[2][9], m[4] = {0.0, 0.0, 0.0, 0.0}, e[2][9];
+    for (int a = 0; a < 9; ++a) {
+        d[0][a] = p[0][a] - wt<double>(a) * A.ref_f;
+        d[1][a] = A.thermal ? p[1][a] - wt<double>(a) * Tr : 0.0;
+        m[0] += d[0][a];
+        m[1] += cx(a) * d[0][a];
+        m[2] += cy(a) * d[0][a];
+        m[3] += d[1][a];
+    }
+    for (int q = 0; q < 4; ++q) m[q] = double(float(m[q]));  // the stored moments
+    for (int q = 0; q < (A.thermal ? 4 : 3); ++q) *reinterpret_cast<float*>(st + L.mom(q, c)) = float(m[q]);
+    split_eq_d(A, m, Tr, e);
+    for (int s = 0; s < (A.thermal ? 2 : 1); ++s)
+        for (int a = 0; a < 9; ++a) {
+            const int k = split_slot(s, a);
+            if (k >= 0) split_put<S>(st, L.res(k, c), d[s][a] - e[s][a]);
+        }
+}
+
 __device__ inline StageConst<double> aux_const(const AuxArgs& a) {
     StageConst<double> k{};
     k.hdt = a.hdt;
@@ -45,7 +138,6 @@ template <class S>
 __global__ void init_kernel(AuxArgs A, const double* rho, const double* ux, const double* uy, const double* T) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= A.plane) return;
-    S* st = static_cast<S*>(A.state);
     Macro<double> m;
     m.rho = rho[c];
     m.ux = ux[c];
@@ -55,23 +147,47 @@ __global__ void init_kernel(AuxArgs A, const double* rho, const double* ux, cons
     m.ay = A.thermal ? A.ay + A.bg * (m.T - A.T0) : A.ay;
     EqForce<double> e;
     eq_force(m, e);
-    for (int a = 0; a < 9; ++a) {
-        const double wr = wt<double>(a) * m.rho;
-        put_pop(A, st, 0, a, c, A.ref_f, wr * e.poly[a] - A.hdt * wr * e.frc[a]);
-        if (A.thermal) put_pop(A, st, 1, a, c, A.ref_g, wt<double>(a) * m.T * e.poly[a]);
+    if constexpr (is_split<S>::value) {
+        double p[2][9];
+        for (int a = 0; a < 9; ++a) {
+            const double wr = wt<double>(a) * m.rho;
+            p[0][a] = wr * e.poly[a] - A.hdt * wr * e.frc[a];
+            p[1][a] = wt<double>(a) * m.T * e.poly[a];
+        }
+        split_encode_d<S>(A, c, p);
+    } else {
+        S* st = static_cast<S*>(A.state);
+        for (int a = 0; a < 9; ++a) {
+            const double wr = wt<double>(a) * m.rho;
+            put_pop(A, st, 0, a, c, A.ref_f, wr * e.poly[a] - A.hdt * wr * e.frc[a]);
+            if (A.thermal) put_pop(A, st, 1, a, c, A.ref_g, wt<double>(a) * m.T * e.poly[a]);
+        }
     }
 }
 
 template <class S>
 __device__ inline Macro<double> cell_macro(const AuxArgs& A, int64_t c) {
-    const S* st = static_cast<const S*>(A.state);
-    double f[9], g[9];
-    for (int a = 0; a < 9; ++a) {
-        f[a] = get_pop(A, st, 0, a, c, A.ref_f);
-        g[a] = A.thermal ? get_pop(A, st, 1, a, c, A.ref_g) : 0.0;
+    if constexpr (is_split<S>::value) {  // the stored moments
+        double mm[4];
+        split_moments<S>(A, c, mm);
+        Macro<double> m;
+        m.rho = mm[0] + A.ref_f;
+        m.T = A.thermal ? mm[3] + row_ref(A, c) : 0.0;
+        m.ax = A.ax;
+        m.ay = A.thermal ? A.ay + A.bg * (m.T - A.T0) : A.ay;
+        m.ux = mm[1] / m.rho + A.hdt * m.ax;
+        m.uy = mm[2] / m.rho + A.hdt * m.ay;
+        return m;
+    } else {
+        const S* st = static_cast<const S*>(A.state);
+        double f[9], g[9];
+        for (int a = 0; a < 9; ++a) {
+            f[a] = get_pop(A, st, 0, a, c, A.ref_f);
+            g[a] = A.thermal ? get_pop(A, st, 1, a, c, A.ref_g) : 0.0;
+        }
+        StageConst<double> k = aux_const(A);
+        return A.thermal ? macro<double, true>(f, g, k) : macro<double, false>(f, g, k);
     }
-    StageConst<double> k = aux_const(A);
-    return A.thermal ? macro<double, true>(f, g, k) : macro<double, false>(f, g, k);
 }
 
 template <class S>
@@ -89,22 +205,36 @@ template <class S>
 __global__ void get_pops_kernel(AuxArgs A, double* out) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= A.plane) return;
-    const S* st = static_cast<const S*>(A.state);
     const int ns = A.thermal ? 2 : 1;
-    for (int s = 0; s < ns; ++s)
-        for (int a = 0; a < 9; ++a)
-            out[(s * 9 + a) * A.plane + c] = get_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f);
+    if constexpr (is_split<S>::value) {
+        double p[2][9];
+        split_decode_d<S>(A, c, p);
+        for (int s = 0; s < ns; ++s)
+            for (int a = 0; a < 9; ++a) out[(s * 9 + a) * A.plane + c] = p[s][a];
+    } else {
+        const S* st = static_cast<const S*>(A.state);
+        for (int s = 0; s < ns; ++s)
+            for (int a = 0; a < 9; ++a)
+                out[(s * 9 + a) * A.plane + c] = get_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f);
+    }
 }
 
 template <class S>
 __global__ void set_pops_kernel(AuxArgs A, const double* in) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= A.plane) return;
-    S* st = static_cast<S*>(A.state);
     const int ns = A.thermal ? 2 : 1;
-    for (int s = 0; s < ns; ++s)
-        for (int a = 0; a < 9; ++a)
-            put_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f, in[(s * 9 + a) * A.plane + c]);
+    if constexpr (is_split<S>::value) {
+        double p[2][9];
+        for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < 9; ++a) p[s][a] = s < ns ? in[(s * 9 + a) * A.plane + c] : 0.0;
+        split_encode_d<S>(A, c, p);
+    } else {
+        S* st = static_cast<S*>(A.state);
+        for (int s = 0; s < ns; ++s)
+            for (int a = 0; a < 9; ++a)
+                put_pop(A, st, s, a, c, s ? A.ref_g : A.ref_f, in[(s * 9 + a) * A.plane + c]);
+    }
 }
 
 // ---- per-row thermal reference update ----------------------------------
@@ -119,7 +249,9 @@ __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
     double sum = 0.0;
     for (int i = threadIdx.x; i < A.nx; i += 256) {
         const int64_t c = int64_t(j) * A.nx + i;
-        for (int a = 0; a < 9; ++a) sum += get_pop(A, st, 1, a, c, A.ref_g);
+        if constexpr (is_split<S>::value) sum += cell_macro<S>(A, c).T;
+        else
+            for (int a = 0; a < 9; ++a) sum += get_pop(A, st, 1, a, c, A.ref_g);
     }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
@@ -130,11 +262,16 @@ __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
     const float nr = newref;
     for (int i = threadIdx.x; i < A.nx; i += 256) {
         const int64_t c = int64_t(j) * A.nx + i;
-        const int nsp = 2;
-        for (int a = 0; a < 9; ++a) {
-            S* p = st + pop_index(A.grouped, nsp, A.plane, 1, a, c);
-            const double d = Codec<S>::template load<double>(p);
-            Codec<S>::template store<double>(p, d + wt<double>(a) * (double(oldref) - double(nr)));
+        if constexpr (is_split<S>::value) {  // only the moment T - Tr changes
+            float* m3 = reinterpret_cast<float*>(static_cast<char*>(A.state) + split_layout(A).mom(3, c));
+            *m3 = float(double(*m3) + (double(oldref) - double(nr)));
+        } else {
+            const int nsp = 2;
+            for (int a = 0; a < 9; ++a) {
+                S* p = st + pop_index(A.grouped, nsp, A.plane, 1, a, c);
+                const double d = Codec<S>::template load<double>(p);
+                Codec<S>::template store<double>(p, d + wt<double>(a) * (double(oldref) - double(nr)));
+            }
         }
     }
     __syncthreads();
@@ -153,6 +290,8 @@ hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s) {
         case ST_F32: return rebase_typed<float>(a, s);
         case ST_BF16: return rebase_typed<bf16_t>(a, s);
         case ST_F16: return rebase_typed<f16_t>(a, s);
+        case ST_BF16S: return rebase_typed<bf16s_t>(a, s);
+        case ST_F16S: return rebase_typed<f16s_t>(a, s);
     }
     return hipSuccess;
 }
@@ -189,11 +328,19 @@ __global__ void __launch_bounds__(256) diag_kernel(DiagArgs D, double* partial) 
         acc[D_ETH] += v * m.T;
         acc[D_UT] += v * m.uy * m.T;
         acc[D_VOL] += v;
-        for (int s = 0; s < ns; ++s)
-            for (int a = 0; a < 9; ++a) {
-                const double p = get_pop(A, st, s, a, c, 0.0);
-                if (!isfinite(p)) acc[D_BAD] = 1.0;
-            }
+        if constexpr (is_split<S>::value) {
+            double p[2][9];
+            split_decode_d<S>(A, c, p);
+            for (int s = 0; s < ns; ++s)
+                for (int a = 0; a < 9; ++a)
+                    if (!isfinite(p[s][a])) acc[D_BAD] = 1.0;
+        } else {
+            for (int s = 0; s < ns; ++s)
+                for (int a = 0; a < 9; ++a) {
+                    const double p = get_pop(A, st, s, a, c, 0.0);
+                    if (!isfinite(p)) acc[D_BAD] = 1.0;
+                }
+        }
         if (D.walls && (j == 0 || j == A.ny - 1)) {
             const int j2 = j == 0 ? 1 : A.ny - 2;
             const double T2 = cell_macro<S>(A, int64_t(j2) * A.nx + i).T;
@@ -251,6 +398,8 @@ static hipError_t aux_dispatch(int storage, int what, const AuxArgs& a, const do
         case ST_F32: return aux_typed<float>(what, a, p0, p1, p2, p3, o0, o1, o2, o3, s);
         case ST_BF16: return aux_typed<bf16_t>(what, a, p0, p1, p2, p3, o0, o1, o2, o3, s);
         case ST_F16: return aux_typed<f16_t>(what, a, p0, p1, p2, p3, o0, o1, o2, o3, s);
+        case ST_BF16S: return aux_typed<bf16s_t>(what, a, p0, p1, p2, p3, o0, o1, o2, o3, s);
+        case ST_F16S: return aux_typed<f16s_t>(what, a, p0, p1, p2, p3, o0, o1, o2, o3, s);
     }
     return hipErrorInvalidValue;
 }
@@ -278,6 +427,8 @@ hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, d
         case ST_F32: hipLaunchKernelGGL(diag_kernel<float>, dim3(nb), dim3(256), 0, s, d, partial); break;
         case ST_BF16: hipLaunchKernelGGL(diag_kernel<bf16_t>, dim3(nb), dim3(256), 0, s, d, partial); break;
         case ST_F16: hipLaunchKernelGGL(diag_kernel<f16_t>, dim3(nb), dim3(256), 0, s, d, partial); break;
+        case ST_BF16S: hipLaunchKernelGGL(diag_kernel<bf16s_t>, dim3(nb), dim3(256), 0, s, d, partial); break;
+        case ST_F16S: hipLaunchKernelGGL(diag_kernel<f16s_t>, dim3(nb), dim3(256), 0, s, d, partial); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -46,6 +46,15 @@ size_t elem_size(int storage) {
     }
 }
 
+bool is_split_storage(int storage) { return storage == LB_BF16S || storage == LB_F16S; }
+
+// Bytes of one population state: 9 or 18 planes of populations, or the
+// moment-split layout (FP32 moments + 16-bit residuals).
+uint64_t state_size(int storage, bool thermal, uint64_t cells) {
+    if (is_split_storage(storage)) return uint64_t(SplitLayout{thermal, int64_t(cells)}.bytes());
+    return (thermal ? 18ull : 9ull) * cells * elem_size(storage);
+}
+
 // Centre of node k (ghosts included) on an axis with faces xi[0..n].
 double node_pos(const std::vector<double>& xi, bool periodic, long k) {
     const long n = long(xi.size()) - 1;
@@ -210,7 +219,6 @@ void fill_stage_k(const lb_params& p, StageK<R>& k) {
         hdt = 0.5 * dt; k1 = dt / (2.0 * tt); kh = 0.5 * dt; kc = dt / tt; kf = dt * (1.0 - dt / (2.0 * tt));
         k1g = dt / (2.0 * ttg); kcg = dt / ttg;
     }
-    const double w[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
     k.hdt = R(hdt);
     k.ax = R(p.ax);
     k.ay = R(p.ay);
@@ -221,10 +229,7 @@ void fill_stage_k(const lb_params& p, StageK<R>& k) {
     k.k1 = R(k1); k.kh = R(kh); k.k1x3 = R(3 * k1); k.khx3 = R(3 * kh); k.omk1 = R(1 - k1);
     k.k1g = R(k1g); k.omk1g = R(1 - k1g);
     k.kc = R(kc); k.kf = R(kf); k.kcx3 = R(3 * kc); k.kfx3 = R(3 * kf); k.omkc = R(1 - kc); k.omkcg = R(1 - kcg);
-    for (int c = 0; c < 3; ++c) {
-        k.kcwref[c] = R(kc * w[c] * rf);
-        k.kcgw[c] = R(kcg * w[c]);
-    }
+    k.kcg = R(kcg);
 }
 
 template <class R>
@@ -251,8 +256,6 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     a.xcoef = pass;
     a.ycoef = pass + nx8;
     fill_stage_k<R>(s->p, a.k);
-    const double k1g = s->p.scheme == LB_FV_EULER ? 0.0 : s->p.dt / (2.0 * (s->p.tau_g + 0.5 * s->p.dt));
-    const double rg = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
     a.Tb = R(s->p.T_bottom);
     a.Tt = R(s->p.T_top);
     a.tref = reinterpret_cast<const R*>(s->tref);  // float rows for FP32 arithmetic, NULL for FP64
@@ -421,14 +424,16 @@ int lb_create(const lb_params* p, lb_sim** out) {
         *out = nullptr;
         if (p->nx < 4 || p->ny < 4) return fail(LB_EINVAL, "lb_create: nx and ny must be >= 4 (got %d, %d)", p->nx, p->ny);
         if (p->scheme < LB_FV_HEUN || p->scheme > LB_ST) return fail(LB_EINVAL, "lb_create: unknown scheme %d", p->scheme);
-        if (p->storage < LB_F64 || p->storage > LB_F16) return fail(LB_EINVAL, "lb_create: unknown storage %d", p->storage);
+        if (p->storage < LB_F64 || p->storage > LB_F16S) return fail(LB_EINVAL, "lb_create: unknown storage %d", p->storage);
+        if (is_split_storage(p->storage) && p->scheme == LB_ST)
+            return fail(LB_EINVAL, "lb_create: moment-split storage (LB_BF16S, LB_F16S) is for the FV schemes only");
         if (!(p->tau > 0) || (p->thermal && !(p->tau_g > 0))) return fail(LB_EINVAL, "lb_create: tau and tau_g must be > 0");
         if (p->scheme != LB_ST && !(p->dt > 0)) return fail(LB_EINVAL, "lb_create: dt must be > 0");
         if ((p->bc_x != LB_PERIODIC && p->bc_x != LB_WALL) || (p->bc_y != LB_PERIODIC && p->bc_y != LB_WALL))
             return fail(LB_EINVAL, "lb_create: bad boundary kind");
         if ((p->flags & LB_FLAG_STREAM_ONLY) && p->scheme != LB_ST)
             return fail(LB_EINVAL, "lb_create: LB_FLAG_STREAM_ONLY needs LB_ST");
-        if ((p->thermal ? 18ull : 9ull) * uint64_t(p->nx) * uint64_t(p->ny) * elem_size(p->storage) >= (1ull << 32))
+        if (state_size(p->storage, p->thermal != 0, uint64_t(p->nx) * uint64_t(p->ny)) >= (1ull << 32))
             return fail(LB_EINVAL, "lb_create: the population state must be smaller than 4 GiB (nx*ny too large for this storage)");
         lb_sim* s = new (std::nothrow) lb_sim();
         if (!s) return fail(LB_ENOMEM, "lb_create: out of host memory");
@@ -436,7 +441,7 @@ int lb_create(const lb_params* p, lb_sim** out) {
         if (s->p.scheme == LB_ST) s->p.dt = 1.0;
         s->nsp = p->thermal ? 2 : 1;
         s->plane = int64_t(p->nx) * p->ny;
-        s->state_bytes = size_t(s->nsp) * 9 * size_t(s->plane) * elem_size(p->storage);
+        s->state_bytes = size_t(state_size(p->storage, p->thermal != 0, uint64_t(s->plane)));
         s->stream = static_cast<hipStream_t>(p->stream);
         s->chunk_h = 0;  // chosen at the first FV launch from the occupancy
         hipError_t e;

@@ -13,11 +13,14 @@
 // eq:euler) use the predictor alone with their own constants.
 //
 // Offset arithmetic.  Populations are handled as offsets d = p - w_a ref
-// (ref = rho_ref for f, T_ref for g; ref = 0 for FP64 storage), exactly as
-// they are stored.  Moments are rho = sum d + ref, j = sum c d, T = sum d_g +
-// T_ref.  The advected bracket is carried as phi - (1 - k1) w_a ref: the
-// QUICK weights of a cell sum to zero, so a constant shift per population
-// cancels from D.  Collision outputs are produced directly as offsets.
+// (ref = rho_ref for f, the row's thermal reference Tr for g; ref = 0 for
+// FP64 storage), exactly as they are stored.  Moments are rho = sum d + ref,
+// j = sum c d, T = sum d_g + Tr.  The advected bracket is carried as
+// phi - w_a ref, built from rho - ref and T - Tr so that no O(1) constant
+// enters it: the four-point weights of a cell sum to zero, so a constant
+// shift cancels from D, and leaving it out keeps the FP32 rounding of the
+// weights (whose sum is zero only up to that rounding) from acting on it.
+// Collision outputs are produced directly as offsets.
 //
 // Equilibrium and force are split by population pairs (a, inv(a)): with
 // cu = c.u and ca = c.a,
@@ -229,74 +232,218 @@ template <> __device__ inline float recip<float>(float x) { return __builtin_amd
 // brackets ph[s][a] (shifted by (1 - k1) w_a ref) of the moving populations
 // and, when BASE, the offsets of f~ + C (all populations).  Tr is the
 // thermal reference of the cell's row (g is stored as g - w_a Tr).
+// stage_core takes the cell's macroscopic state (rho, T, u, a_y); stage
+// computes it from the offsets.
 template <class R, bool TH, bool BASE>
-__device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
+__device__ inline void stage_core(const R* df, const R* dg, const R rho_p, const R rho, const R T_p, const R T,
+                                  const R ux, const R uy, const R ay, const StageK<R>& k, R (*ph)[9], R (*bs)[9]) {
     constexpr int NSP = TH ? 2 : 1;
-    R rho = df[0], jx = 0, jy = 0;
-#pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        rho += df[a];
-        if (cx(a) > 0) jx += df[a]; else if (cx(a) < 0) jx -= df[a];
-        if (cy(a) > 0) jy += df[a]; else if (cy(a) < 0) jy -= df[a];
-    }
-    rho += k.ref_f;
-    R T = 0, ay = k.ay;
-    if (TH) {
-        T = dg[0];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) T += dg[a];
-        T += Tr;
-        ay = k.ay + k.bg * (T - k.T0);
-    }
     const R ax = k.ax;
-    const R ir = recip(rho);
-    const R ux = jx * ir + k.hdt * ax, uy = jy * ir + k.hdt * ay;
-    const R e0 = R(1) - R(1.5) * (ux * ux + uy * uy);
+    const R uu = R(1.5) * (ux * ux + uy * uy);
     const R ua3 = R(3) * (ux * ax + uy * ay);
-    const R wr[3] = {wt<R>(0) * rho, wt<R>(1) * rho, wt<R>(5) * rho};
-    R wt1[3] = {0, 0, 0};  // k1g w T
-    R wt2[3] = {0, 0, 0};  // kcg w
-    if (TH) {
-        wt1[0] = k.k1g * wt<R>(0) * T; wt1[1] = k.k1g * wt<R>(1) * T; wt1[2] = k.k1g * wt<R>(5) * T;
-    }
-    (void)wt2;
     // rest population: no flux; base only
     if (BASE) {
-        const R A0 = k.kc * e0 - k.kf * ua3;
-        bs[0][0] = k.omkc * df[0] + (wr[0] * A0 - k.kcwref[0]);
-        if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcgw[0] * (T * e0 - Tr);
+        bs[0][0] = k.omkc * df[0] + wt<R>(0) * (k.kc * rho_p - rho * (k.kc * uu + k.kf * ua3));
+        if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcg * wt<R>(0) * (T_p - T * uu);
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int a = pa(p), b = pb(p);
-        const int cl = p < 2 ? 1 : 2;
+        const R w = wt<R>(a);
         R cu, ca;
         if (p == 0) { cu = ux; ca = ax; }
         else if (p == 1) { cu = uy; ca = ay; }
         else if (p == 2) { cu = ux + uy; ca = ax + ay; }
         else { cu = uy - ux; ca = ay - ax; }
-        const R E = (R(4.5) * cu) * cu + e0;
-        const R Fe = (R(9) * cu) * ca - ua3;
-        // advected bracket of f
-        const R Pe = k.k1 * E + k.kh * Fe;
-        const R Po = k.k1x3 * cu + k.khx3 * ca;
-        ph[0][a] = k.omk1 * df[a] + wr[cl] * (Pe + Po);
-        ph[0][b] = k.omk1 * df[b] + wr[cl] * (Pe - Po);
+        const R Em = (R(4.5) * cu) * cu - uu;     // even part of f_eq / (w rho), minus 1
+        const R Fe = (R(9) * cu) * ca - ua3;      // even part of F / (w rho)
+        // advected bracket of f, minus w ref
+        const R Pe = k.k1 * rho_p + rho * (k.k1 * Em + k.kh * Fe);
+        const R Po = rho * (k.k1x3 * cu + k.khx3 * ca);
+        ph[0][a] = k.omk1 * df[a] + w * (Pe + Po);
+        ph[0][b] = k.omk1 * df[b] + w * (Pe - Po);
         if (TH) {
+            // bracket of g, minus w Tr
             const R O = R(3) * cu;
-            ph[NSP - 1][a] = k.omk1g * dg[a] + wt1[cl] * (E + O);
-            ph[NSP - 1][b] = k.omk1g * dg[b] + wt1[cl] * (E - O);
+            const R Ge = T_p + T * Em, Go = T * O;
+            ph[NSP - 1][a] = k.omk1g * dg[a] + k.k1g * w * (Ge + Go);
+            ph[NSP - 1][b] = k.omk1g * dg[b] + k.k1g * w * (Ge - Go);
             if (BASE) {
-                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcgw[cl] * (T * (E + O) - Tr);
-                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcgw[cl] * (T * (E - O) - Tr);
+                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcg * w * (Ge + Go);
+                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcg * w * (Ge - Go);
             }
         }
         if (BASE) {
-            const R Ae = k.kc * E + k.kf * Fe;
-            const R Ao = k.kcx3 * cu + k.kfx3 * ca;
-            bs[0][a] = k.omkc * df[a] + (wr[cl] * (Ae + Ao) - k.kcwref[cl]);
-            bs[0][b] = k.omkc * df[b] + (wr[cl] * (Ae - Ao) - k.kcwref[cl]);
+            const R Ae = k.kc * rho_p + rho * (k.kc * Em + k.kf * Fe);
+            const R Ao = rho * (k.kcx3 * cu + k.kfx3 * ca);
+            bs[0][a] = k.omkc * df[a] + w * (Ae + Ao);
+            bs[0][b] = k.omkc * df[b] + w * (Ae - Ao);
         }
+    }
+}
+
+template <class R, bool TH, bool BASE>
+__device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
+    R rho_p = df[0], jx = 0, jy = 0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        rho_p += df[a];
+        if (cx(a) > 0) jx += df[a]; else if (cx(a) < 0) jx -= df[a];
+        if (cy(a) > 0) jy += df[a]; else if (cy(a) < 0) jy -= df[a];
+    }
+    const R rho = rho_p + k.ref_f;
+    R T_p = 0, T = 0, ay = k.ay;
+    if (TH) {
+        T_p = dg[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) T_p += dg[a];
+        T = T_p + Tr;
+        ay = k.ay + k.bg * (T - k.T0);
+    }
+    const R ir = recip(rho);
+    const R ux = jx * ir + k.hdt * k.ax, uy = jy * ir + k.hdt * ay;
+    stage_core<R, TH, BASE>(df, dg, rho_p, rho, T_p, T, ux, uy, ay, k, ph, bs);
+}
+
+// ---- moment-split cells (storage BF16S / F16S) ---------------------------
+// Layout (SplitLayout, with G = 8 bytes x cells = group_bytes): thermal
+// cells keep m as one float4 at 16 c, residual planes at 2G, 3G, 4G and the
+// tail at 5G; other cells keep (m0, m1) at 8 c, m2 at G + 4 c, the residual
+// plane at 1.5 G and the tail at 2.5 G.
+template <class S> struct Narrow;
+template <> struct Narrow<bf16s_t> : Io16<true> {};
+template <> struct Narrow<f16s_t> : Io16<false> {};
+
+template <class R, class S, bool TH>
+__device__ inline void load_split(Buf b, uint32_t cell, uint32_t G, R* m, R* rf, R* rg) {
+    using IO = Narrow<S>;
+    constexpr float irs = 1.0f / split_scale<S>::value;
+    auto d = [&](uint32_t w, int hi) __attribute__((always_inline)) { return R(IO::dec(w, hi) * irs); };
+    const uint32_t v8 = cell * 8u, v4 = cell * 4u;
+    if (TH) {
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, cell * 16u, 0u, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[q] = R(__uint_as_float(x[q]));
+        const u32x2 p0 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 2 * G, 0);
+        const u32x2 p1 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 3 * G, 0);
+        const u32x2 p2 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 4 * G, 0);
+        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(b.r, v4, 5 * G, 0);
+        rf[3] = d(p0[0], 0); rf[4] = d(p0[0], 1); rf[5] = d(p0[1], 0); rf[6] = d(p0[1], 1);
+        rf[7] = d(p1[0], 0); rf[8] = d(p1[0], 1); rg[1] = d(p1[1], 0); rg[2] = d(p1[1], 1);
+        rg[3] = d(p2[0], 0); rg[4] = d(p2[0], 1); rg[5] = d(p2[1], 0); rg[6] = d(p2[1], 1);
+        rg[7] = d(t, 0); rg[8] = d(t, 1);
+    } else {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 0u, 0);
+        m[0] = R(__uint_as_float(x[0]));
+        m[1] = R(__uint_as_float(x[1]));
+        m[2] = R(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, v4, G, 0)));
+        m[3] = R(0);
+        const u32x2 p0 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, G + G / 2, 0);
+        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(b.r, v4, 2 * G + G / 2, 0);
+        rf[3] = d(p0[0], 0); rf[4] = d(p0[0], 1); rf[5] = d(p0[1], 0); rf[6] = d(p0[1], 1);
+        rf[7] = d(t, 0); rf[8] = d(t, 1);
+    }
+}
+
+// Macroscopic state of a split cell from its moments.
+template <class R, bool TH>
+__device__ inline void split_macro(const R* m, const StageK<R>& k, const R Tr, R& rho, R& T, R& ux, R& uy, R& ay) {
+    rho = m[0] + k.ref_f;
+    T = TH ? m[3] + Tr : R(0);
+    ay = TH ? k.ay + k.bg * (T - k.T0) : k.ay;
+    const R ir = recip(rho);
+    ux = m[1] * ir + k.hdt * k.ax;
+    uy = m[2] * ir + k.hdt * ay;
+}
+
+// Offsets of the forced equilibrium, e_a = E_a - w_a ref: for f
+// w (m0 + rho (P_a - 1 - hdt F_a / (w rho))), for g w (m3 + T (P_a - 1)),
+// with P = f_eq / (w rho).  Small terms only, so FP32 keeps them exact to
+// its own resolution.
+template <class R, bool TH, class Fn>
+__device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, const R uy, const R ay,
+                                const StageK<R>& k, Fn&& put) {
+    const R uu = R(1.5) * (ux * ux + uy * uy);
+    const R ua3 = R(3) * (ux * k.ax + uy * ay);
+    put(0, 0, wt<R>(0) * (m[0] + rho * (k.hdt * ua3 - uu)));
+    if (TH) put(1, 0, wt<R>(0) * (m[3] - T * uu));
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int a = pa(p), b = pb(p);
+        R cu, ca;
+        if (p == 0) { cu = ux; ca = k.ax; }
+        else if (p == 1) { cu = uy; ca = ay; }
+        else if (p == 2) { cu = ux + uy; ca = k.ax + ay; }
+        else { cu = uy - ux; ca = ay - k.ax; }
+        const R Em = (R(4.5) * cu) * cu - uu;
+        const R O = R(3) * cu;
+        const R Qe = Em - k.hdt * ((R(9) * cu) * ca - ua3);
+        const R Qo = O - k.hdt * (R(3) * ca);
+        const R w = wt<R>(a);
+        put(0, a, w * (m[0] + rho * (Qe + Qo)));
+        put(0, b, w * (m[0] + rho * (Qe - Qo)));
+        if (TH) {
+            put(1, a, w * (m[3] + T * (Em + O)));
+            put(1, b, w * (m[3] + T * (Em - O)));
+        }
+    }
+}
+
+// Residuals (stored entries in rf, rg) -> offsets d of all populations, in
+// place, plus the cell's macroscopic state.
+template <class R, bool TH>
+__device__ inline void split_decode(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R& rho, R& T, R& ux,
+                                    R& uy, R& ay) {
+    df[1] = df[3] - df[5] + df[6] + df[7] - df[8];
+    df[2] = df[4] - df[5] - df[6] + df[7] + df[8];
+    df[0] = -(((df[1] + df[2]) + (df[3] + df[4])) + ((df[5] + df[6]) + (df[7] + df[8])));
+    if (TH) dg[0] = -(((dg[1] + dg[2]) + (dg[3] + dg[4])) + ((dg[5] + dg[6]) + (dg[7] + dg[8])));
+    split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
+    split_eq<R, TH>(m, rho, T, ux, uy, ay, k, [&](int s, int a, R e) __attribute__((always_inline)) {
+        if (s == 0) df[a] += e; else dg[a] += e;
+    });
+}
+
+template <class R, bool TH, bool BASE>
+__device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
+    R rho, T, ux, uy, ay;
+    split_decode<R, TH>(m, df, dg, k, Tr, rho, T, ux, uy, ay);
+    stage_core<R, TH, BASE>(df, dg, m[0], rho, TH ? m[3] : R(0), T, ux, uy, ay, k, ph, bs);
+}
+
+// Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
+template <class R, class S, bool TH>
+__device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
+                                   const R Tr) {
+    using IO = Narrow<S>;
+    constexpr float rs = split_scale<S>::value;
+    R m[4];
+    m[0] = ((df[0] + (df[1] + df[2])) + (df[3] + df[4])) + ((df[5] + df[6]) + (df[7] + df[8]));
+    m[1] = ((df[1] - df[3]) + (df[5] - df[6])) + (df[8] - df[7]);
+    m[2] = ((df[2] - df[4]) + (df[5] + df[6])) - (df[7] + df[8]);
+    m[3] = TH ? ((dg[0] + (dg[1] + dg[2])) + (dg[3] + dg[4])) + ((dg[5] + dg[6]) + (dg[7] + dg[8])) : R(0);
+    R rho, T, ux, uy, ay;
+    split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
+    R rf[9], rg[9];
+    split_eq<R, TH>(m, rho, T, ux, uy, ay, k, [&](int s, int a, R e) __attribute__((always_inline)) {
+        if (s == 0) rf[a] = df[a] - e; else rg[a] = dg[a] - e;
+    });
+    auto e2 = [&](R lo, R hi) __attribute__((always_inline)) { return IO::enc2(float(lo) * rs, float(hi) * rs); };
+    const uint32_t v8 = cell * 8u, v4 = cell * 4u;
+    if (TH) {
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
+                                                     __float_as_uint(float(m[2])), __float_as_uint(float(m[3]))},
+                                               b.r, cell * 16u, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, 2 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[7], rf[8]), e2(rg[1], rg[2])}, b.r, v8, 3 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rg[3], rg[4]), e2(rg[5], rg[6])}, b.r, v8, 4 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(e2(rg[7], rg[8]), b.r, v4, 5 * G, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(m[0])), __float_as_uint(float(m[1]))}, b.r,
+                                              v8, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(m[2])), b.r, v4, G, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, G + G / 2, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(e2(rf[7], rf[8]), b.r, v4, 2 * G + G / 2, 0);
     }
 }
 
@@ -402,12 +549,24 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // The corrector's own-cell input goes one row ahead only for 16-bit
     // storage, whose prefetched words stay packed two to a register.
     constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2;
-    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
+    // moment-split storage: PF/PG hold the stored residuals, PM the moments
+    constexpr bool SPLIT = is_split<S>::value;
+    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9], PM[2][4], PHM[2][4];
+    auto load_any = [&](const Buf& b, uint32_t cell, R* m, R* f, R* g) __attribute__((always_inline)) {
+        if constexpr (SPLIT) load_split<R, S, TH>(b, cell, gb, m, f, g);
+        else load_cell<R, S, TH>(b, cell, gb, ro, f, g);
+    };
     auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
-        load_cell<R, S, TH>(bsrc, uint32_t(map_row(r)) * nxu + colu, gb, ro, PF[Q], PG[Q]);
+        load_any(bsrc, uint32_t(map_row(r)) * nxu + colu, PM[Q], PF[Q], PG[Q]);
         if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n, or H)
-            load_cell<R, S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, ro, PH[Q], PHG[Q]);
+            load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PHM[Q], PH[Q], PHG[Q]);
+    };
+    // store the offsets of a cell of a row whose thermal reference is trow
+    auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
+                         __attribute__((always_inline)) {
+        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow);
+        else store_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
@@ -417,7 +576,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         R Tr = k.ref_g;
         if (TH && A.tref) Tr = ((const CR*)A.tref)[map_row(r)];
         // wall temperature for the anti-reflection of the shifted brackets
-        const R Tw = (r < 0 ? A.Tb : A.Tt) - k.omk1g * Tr;
+        const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
 
         if (!AHEAD) prefetch(r, Slot<SL>{});
         R df[9], dg[9];
@@ -428,11 +587,16 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         }
         if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
         if (CORR && !AHEAD_OWN && owned)  // own-cell input of this row, used after the stage
-            load_cell<R, S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, ro, PH[SL & 1], PHG[SL & 1]);
+            load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PHM[SL & 1], PH[SL & 1], PHG[SL & 1]);
 
         R ph[NSP][9], bs[NSP][9];
-        if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
-        else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
+        if constexpr (SPLIT) {  // decodes df, dg to offsets in place
+            if (CORR) stage_split<R, TH, false>(PM[SL & 1], df, dg, k, Tr, ph, bs);
+            else stage_split<R, TH, true>(PM[SL & 1], df, dg, k, Tr, ph, bs);
+        } else {
+            if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
+            else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
+        }
 
         // ghost row (y walls): double reflection of f, anti-reflection of g
         {
@@ -469,15 +633,16 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) yc[q] = yw[q];
         }
-        // A per-row thermal reference shifts the stored brackets of g by
-        // (1 - k1g) w_a Tr(row); across rows the shift does not cancel from
-        // the y stencil, so its contribution is added back (uniform per row).
+        // A per-row thermal reference shifts the brackets of g by
+        // w_a Tr(row); across rows the shift does not cancel from the y
+        // stencil, so its flux is added back (uniform per row).  The weights
+        // sum to zero, so the flux is taken of Tr(row) - Tr(j), which keeps
+        // it free of the rounding of that sum.
         R sU = 0, sD = 0;
         if (TH && A.tref) {
-            sU = k.omk1g * (yc[0] * TRg[SL] + yc[1] * TRg[(SL + 1) & 3] + yc[2] * TRg[(SL + 2) & 3] +
-                            yc[3] * TRg[(SL + 3) & 3]);
-            sD = k.omk1g * (yc[4] * TRg[(SL + 1) & 3] + yc[5] * TRg[(SL + 2) & 3] + yc[6] * TRg[(SL + 3) & 3] +
-                            yc[7] * Tr);
+            const R tj = TRg[(SL + 2) & 3];
+            sU = yc[0] * (TRg[SL] - tj) + yc[1] * (TRg[(SL + 1) & 3] - tj) + yc[3] * (TRg[(SL + 3) & 3] - tj);
+            sD = yc[4] * (TRg[(SL + 1) & 3] - tj) + yc[6] * (TRg[(SL + 3) & 3] - tj) + yc[7] * (Tr - tj);
         }
         if (owned && j >= y0 && j < y1) {
             R out[NSP][9];
@@ -499,7 +664,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                     }
                 }
             }
-            store_cell<R, S, TH>(bdst, uint32_t(j) * nxu + colu, gb, ro, out[0], out[NSP - 1]);
+            store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3]);
         }
 
         // ---- x flux and partial update (all but the y flux) of row r ----
@@ -515,15 +680,35 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             R base[NSP][9];
             if (CORR && HEUN_H) {
                 // f~n+1 = H + f~*/2 - dt/2 D(phi*): H (offsets) at this cell
+                R hf[9], hg[9];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
-                    base[0][a] = PH[SL & 1][a] + R(0.5) * df[a];
-                    if (TH) base[NSP - 1][a] = PHG[SL & 1][a] + R(0.5) * dg[a];
+                    hf[a] = PH[SL & 1][a];
+                    hg[a] = PHG[SL & 1][a];
+                }
+                if constexpr (SPLIT) {
+                    R q0, q1, q2, q3, q4;
+                    split_decode<R, TH>(PHM[SL & 1], hf, hg, k, Tr, q0, q1, q2, q3, q4);
+                }
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    base[0][a] = hf[a] + R(0.5) * df[a];
+                    if (TH) base[NSP - 1][a] = hg[a] + R(0.5) * dg[a];
                 }
             } else if (CORR) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
                 R phn[NSP][9], bn[NSP][9];
-                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
+                if constexpr (SPLIT) {
+                    R hf[9], hg[9];
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        hf[a] = PH[SL & 1][a];
+                        hg[a] = PHG[SL & 1][a];
+                    }
+                    stage_split<R, TH, true>(PHM[SL & 1], hf, hg, k, Tr, phn, bn);
+                } else {
+                    stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
+                }
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
                     base[0][a] = R(0.5) * (bn[0][a] + df[a]);
@@ -541,7 +726,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                         hf[a] = R(0.5) * bs[0][a];
                         if (TH) hg[a] = R(0.5) * bs[NSP - 1][a];
                     }
-                    store_cell<R, S, TH>(baux, ocell, gb, ro, hf, hg);
+                    store_any(baux, ocell, hf, hg, Tr);
                 }
             }
 #pragma unroll
@@ -650,6 +835,8 @@ hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void
         case ST_F32: return launch_multi_typed<float, float>(thermal, corrector, args, items, n_items, left, s);
         case ST_BF16: return launch_multi_typed<float, bf16_t>(thermal, corrector, args, items, n_items, left, s);
         case ST_F16: return launch_multi_typed<float, f16_t>(thermal, corrector, args, items, n_items, left, s);
+        case ST_BF16S: return launch_multi_typed<float, bf16s_t>(thermal, corrector, args, items, n_items, left, s);
+        case ST_F16S: return launch_multi_typed<float, f16s_t>(thermal, corrector, args, items, n_items, left, s);
     }
     return hipErrorInvalidValue;
 }
@@ -700,6 +887,8 @@ int fv_resident_blocks(int storage, bool thermal, bool corrector) {
         case ST_F32: return resident_typed<float, float>(thermal, corrector);
         case ST_BF16: return resident_typed<float, bf16_t>(thermal, corrector);
         case ST_F16: return resident_typed<float, f16_t>(thermal, corrector);
+        case ST_BF16S: return resident_typed<float, bf16s_t>(thermal, corrector);
+        case ST_F16S: return resident_typed<float, f16s_t>(thermal, corrector);
     }
     return 0;
 }
@@ -710,6 +899,8 @@ hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void*
         case ST_F32: return launch_typed<float, float>(thermal, corrector, args, s);
         case ST_BF16: return launch_typed<float, bf16_t>(thermal, corrector, args, s);
         case ST_F16: return launch_typed<float, f16_t>(thermal, corrector, args, s);
+        case ST_BF16S: return launch_typed<float, bf16s_t>(thermal, corrector, args, s);
+        case ST_F16S: return launch_typed<float, f16s_t>(thermal, corrector, args, s);
     }
     return hipErrorInvalidValue;
 }

@@ -75,6 +75,58 @@ template <> struct Codec<f16_t> {
     }
 };
 
+// ---- moment-split storage ------------------------------------------------
+// A cell keeps the conserved moments of its populations in FP32,
+//   m = (rho - rho_ref, j_x, j_y, T - T_r),   j = sum c f~,
+// and, in a 16-bit format, the residual r_a = f~_a - E_a(m) of each
+// population from the forced equilibrium E = f_eq - dt/2 F (Guo) at the
+// velocity u = j / rho + dt/2 a; for g, E = g_eq = w T (f_eq / (w rho)).  E
+// carries the moments m exactly, so the residuals have zero mass and
+// momentum: r0, r1 and r2 of f and r0 of g follow from the stored ones,
+//   r1 = r3 - r5 + r6 + r7 - r8,  r2 = r4 - r5 - r6 + r7 + r8,  r0 = -sum r,
+// and the 16-bit words never carry a conserved quantity.  Only the non-
+// equilibrium part, which relaxes every step, is rounded to 16 bits; the
+// slowly changing moments keep FP32 resolution, so increments far below a
+// 16-bit ulp of the populations are not lost.  The 16-bit values hold
+// r * RSCALE (2^10 for IEEE half, whose range is narrow; 1 for bfloat16).
+template <class N> struct Split { uint16_t bits; };
+using bf16s_t = Split<bf16_t>;
+using f16s_t = Split<f16_t>;
+template <class S> struct is_split { static constexpr bool value = false; };
+template <class N> struct is_split<Split<N>> { static constexpr bool value = true; };
+template <class S> struct split_scale { static constexpr float value = 1.0f; };
+template <> struct split_scale<f16s_t> { static constexpr float value = 1024.0f; };
+
+// Residual slot of (species s, population a), -1 when it is derived:
+// slots 0..5 hold f r3..r8, slots 6..13 hold g r1..r8.
+__host__ __device__ constexpr int split_slot(int s, int a) {
+    return s == 0 ? (a >= 3 ? a - 3 : -1) : (a >= 1 ? 5 + a : -1);
+}
+// Byte layout of a split state with `cells` cells:
+//   thermal:      [float4 m per cell][3 planes of 4 residuals (8 B per cell)][plane of 2 residuals]
+//   not thermal:  [float2 (m0, m1) per cell][float m2 per cell][1 plane of 4 residuals][plane of 2]
+// Residual slot k lives in plane k / 4 (element k % 4) for k < 4 K4, else in
+// the 2-element tail plane (element k - 4 K4), K4 = 3 (thermal) or 1.
+struct SplitLayout {
+    bool thermal;
+    int64_t cells;
+    __host__ __device__ int k4() const { return thermal ? 3 : 1; }
+    __host__ __device__ int64_t mom2_off() const { return 8 * cells; }   // not thermal: float m2 plane
+    __host__ __device__ int64_t res_off() const { return (thermal ? 16 : 12) * cells; }
+    __host__ __device__ int64_t tail_off() const { return res_off() + 8 * k4() * cells; }
+    __host__ __device__ int64_t bytes() const { return tail_off() + 4 * cells; }
+    // byte offset of moment q (0..3) of cell c
+    __host__ __device__ int64_t mom(int q, int64_t c) const {
+        if (thermal) return 16 * c + 4 * q;
+        return q < 2 ? 8 * c + 4 * q : mom2_off() + 4 * c;
+    }
+    // byte offset of residual slot k of cell c
+    __host__ __device__ int64_t res(int k, int64_t c) const {
+        if (k < 4 * k4()) return res_off() + int64_t(k / 4) * 8 * cells + 8 * c + 2 * (k % 4);
+        return tail_off() + 4 * c + 2 * (k - 4 * k4());
+    }
+};
+
 // ---- population layouts in device memory ---------------------------------
 // SoA (ST scheme): element (s, a, c) at (s*9 + a) * plane + c.
 // Grouped (FV schemes): each cell keeps four populations of a species side by

@@ -8,7 +8,7 @@
 
 namespace lbk {
 
-enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3, ST_BF16S = 4, ST_F16S = 5 };
 
 // Width in lanes of the FV strip kernel (one lane per column, the block
 // marches up its rows): FV_LANES - 4 owned columns + 2 halo columns on each
@@ -19,19 +19,18 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
 constexpr int FV_LANES = LB_FV_LANES;
 constexpr int FV_HALO = 2;
 
-// Stage constants of the FV kernel in offset arithmetic (see fv.hip):
-//   bracket   phi' = omk1 d + w rho (k1 poly + kh frc)          (f)
-//             phi' = omk1g d + k1g w T poly                     (g)
-//   f~ + C    b'   = omkc d + w rho (kc poly + kf frc) - kc w ref
-//             b'   = omkcg d + kcg w (T poly - T_ref)
-// with poly = f_eq/(w rho), frc = F/(w rho); k1x3 = 3 k1 etc.
+// Stage constants of the FV kernel in offset arithmetic (see fv.hip), with
+// d = p - w ref, poly = f_eq/(w rho), frc = F/(w rho):
+//   bracket   phi - w ref = omk1 d + w (k1 (rho - ref) + rho (k1 (poly - 1) + kh frc))   (f)
+//             phi - w Tr  = omk1g d + k1g w ((T - Tr) + T (poly - 1))                       (g)
+//   f~ + C    b           = omkc d + w (kc (rho - ref) + rho (kc (poly - 1) + kf frc))
+//             b           = omkcg d + kcg w ((T - Tr) + T (poly - 1))
+// k1x3 = 3 k1 etc.
 template <class R>
 struct StageK {
     R hdt, ax, ay, bg, T0, ref_f, ref_g;
     R k1, kh, k1x3, khx3, omk1, k1g, omk1g;
-    R kc, kf, kcx3, kfx3, omkc, omkcg;
-    R kcwref[3];  // kc w_class ref_f  (classes: rest, axis, diagonal)
-    R kcgw[3];    // kcg w_class
+    R kc, kf, kcx3, kfx3, omkc, omkcg, kcg;
 };
 
 template <class R>
@@ -39,9 +38,9 @@ struct FvArgs {
     const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector)
     void* dst;         // output state
     void* aux;         // corrector: its own-cell input (f~n, or H); predictor: H output or NULL
-    uint32_t state_bytes;  // whole state (grouped layout, see pop_index)
-    uint32_t group_bytes;  // one group plane: 4 elements per cell
-    uint32_t rest_off;     // byte offset of the rest plane
+    uint32_t state_bytes;  // whole state (grouped layout, see pop_index; or SplitLayout)
+    uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
+    uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
     int nx, ny;
     int wall_x, wall_y;
     int strip_w;       // owned columns per strip (<= FV_LANES - 4)

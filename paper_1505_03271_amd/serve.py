@@ -22,13 +22,12 @@ from collections import deque
 
 import numpy as np
 
-from . import Group, Sim, current_stream, STORAGE_BYTES
+from . import Group, Sim, current_stream, cell_bytes
 
 
 def request_bytes(n, storage, thermal=True):
     """Device memory of one request: two population buffers plus metric."""
-    q = 18 if thermal else 9
-    return 2 * q * n * n * STORAGE_BYTES[storage] + 64 * n + 4096
+    return 2 * n * n * cell_bytes(storage, thermal) + 64 * n + 4096
 
 
 class Server:

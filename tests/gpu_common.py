@@ -6,7 +6,8 @@ import oracle
 import paper_1505_03271_amd as lb
 
 # storage unit roundoff (half an ulp relative to the stored magnitude)
-UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -9, "f16": 2.0 ** -11, "bf16s": 2.0 ** -9,
+        "f16s": 2.0 ** -11}
 
 _OKEYS = ("thermal", "wall_x", "wall_y", "dt", "tau", "tau_g", "ax", "ay", "beta_g", "T0", "T_bottom", "T_top")
 

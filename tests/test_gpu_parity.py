@@ -2,8 +2,9 @@
 
 FP64 storage runs the kernels in double precision and must agree with the
 oracle to 1e-12 relative.  The narrow formats run in FP32 and store offsets
-p - w rho_ref; their bound is derived from the storage rounding (UNIT) and
-FP32 arithmetic, per step.  Streaming alone is a permutation and must move
+p - w rho_ref, or (moment-split formats) FP32 moments plus 16-bit residuals
+from the forced equilibrium; their bound is derived from the storage
+rounding (UNIT) and FP32 arithmetic, per step.  Streaming alone is a permutation and must move
 tagged words bit for bit."""
 import math
 import sys
@@ -177,6 +178,74 @@ def test_narrow_storage_against_oracle(storage, scheme):
         assert ef < bound and eg < bound
 
 
+def _residual_scale(f, g, dt, ax, ay, beta_g, T0):
+    """max |f~ - (f_eq - dt/2 F)| and |g - g_eq| of an FP64 state: the size
+    of what moment-split storage rounds to 16 bits."""
+    c = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    cx, cy = c[:, 0, None, None], c[:, 1, None, None]
+    rho = f.sum(0)
+    T = g.sum(0) if g is not None else 0.0
+    Ay = ay + beta_g * (T - T0)
+    ux = (cx * f).sum(0) / rho + 0.5 * dt * ax
+    uy = (cy * f).sum(0) / rho + 0.5 * dt * Ay
+    cu = cx * ux + cy * uy
+    ca = cx * ax + cy * Ay
+    poly = 1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy)
+    frc = 3 * (ca - (ux * ax + uy * Ay)) + 9 * cu * ca
+    r = np.abs(f - w * rho * (poly - 0.5 * dt * frc)).max()
+    if g is not None:
+        r = max(r, np.abs(g - w * T * poly).max())
+    return r
+
+
+SPLIT_CASES = [
+    dict(id="thermal-ywalls-tanh", nx=300, ny=77, wall_x=False, thermal=True),
+    dict(id="thermal-allwalls", nx=261, ny=45, wall_x=True, thermal=True),
+    dict(id="isothermal-channel", nx=253, ny=37, wall_x=False, thermal=False),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[c["id"] for c in SPLIT_CASES])
+@pytest.mark.parametrize("scheme", ["heun", "semi", "euler"])
+@pytest.mark.parametrize("storage", ["bf16s", "f16s"])
+def test_split_storage_against_oracle(storage, scheme, case):
+    """Moment-split storage: moments in FP32, residuals from the forced
+    equilibrium in 16 bits.  The error per step is bounded by FP32 rounding
+    of the moments and arithmetic plus a few half-ulps of the largest
+    residual; mass is conserved to FP32 rounding."""
+    nx, ny, thermal = case["nx"], case["ny"], case["thermal"]
+    say(f"split {storage} {scheme} {case['id']}")
+    xf = (np.concatenate([[0.0], np.cumsum(np.random.default_rng(5).uniform(0.6, 1.4, nx))]) * 3.0
+          if case["wall_x"] else workloads.faces_uniform(nx, 3.0 * nx))
+    yf = workloads.faces_tanh(ny, 3.0 * ny, 2.0)
+    dt = {"heun": 0.5, "semi": 0.2, "euler": 0.1}[scheme]
+    kw = dict(thermal=thermal, wall_x=case["wall_x"], wall_y=True, dt=dt, tau=0.3, tau_g=0.25, ax=1e-5, ay=-2e-5,
+              beta_g=1e-3 if thermal else 0.0, T0=0.05, T_bottom=0.5, T_top=-0.5)
+    fields = random_fields(nx, ny, 13, thermal=thermal)
+    sim, ref = make_pair(nx, ny, scheme, storage, xf, yf, fields, chunk=16, **kw)
+    # the initial state is the equilibrium: residuals vanish, moments are FP32
+    f0, g0 = sim.populations()
+    assert np.abs(f0 - ref.f).max() < 4 * 2.0 ** -24
+    if thermal:
+        assert np.abs(g0 - ref.g).max() < 4 * 2.0 ** -24
+    m0 = sim.diagnostics()["mass"]
+    u = UNIT[storage]
+    for steps in (1, 5):
+        sim.step(1 if steps == 1 else 4)
+        ref.step(1 if steps == 1 else 4)
+        f, g = sim.populations()
+        R = _residual_scale(ref.f, ref.g, dt, kw["ax"], kw["ay"], kw["beta_g"], kw["T0"])
+        bound = steps * (8 * u * R + 64 * 2.0 ** -24)
+        ef = np.abs(f - ref.f).max()
+        eg = np.abs(g - ref.g).max() if thermal else 0.0
+        say(f"  steps={steps} err f={ef:.3e} g={eg:.3e} residual={R:.3e} bound={bound:.3e}")
+        assert ef < bound and eg < bound
+    d = sim.diagnostics()
+    assert abs(d["mass"] - m0) <= 1e-6 * abs(m0)
+    assert d["nonfinite"] == 0.0
+
+
 def test_full_size_rb4096_bf16_one_step():
     """The benchmark's workload and launch shape (4096^2, BF16 storage,
     default chunking): one full step against the oracle on every cell."""
@@ -240,13 +309,14 @@ def test_st_streaming_permutation_bit_exact(storage, thermal, walls):
 
 # ------------------------------------------------------ lifecycle ----------
 
-def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic():
+@pytest.mark.parametrize("storage", ["bf16", "bf16s"])
+def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic(storage):
     nx, ny = 300, 77
-    say("checkpoint / determinism bf16")
+    say(f"checkpoint / determinism {storage}")
     kw = dict(thermal=True, wall_y=True, dt=0.5, tau=0.3, tau_g=0.25, beta_g=1e-3, T_bottom=0.5, T_top=-0.5)
     fields = random_fields(nx, ny, 3)
     xf, yf = workloads.faces_uniform(nx, 3.0 * nx), workloads.faces_tanh(ny, 3.0 * ny, 2.0)
-    sim, _ = make_pair(nx, ny, "heun", "bf16", xf, yf, fields, **kw)
+    sim, _ = make_pair(nx, ny, "heun", storage, xf, yf, fields, **kw)
     sim.step(10)
     saved = sim.get_state()
     sim.step(10)
@@ -256,7 +326,7 @@ def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic():
     b = sim.get_state()
     assert np.array_equal(a, b)
     for chunk in (8, 77, 1000):
-        other, _ = make_pair(nx, ny, "heun", "bf16", xf, yf, fields, chunk=chunk, **kw)
+        other, _ = make_pair(nx, ny, "heun", storage, xf, yf, fields, chunk=chunk, **kw)
         other.step(20)
         assert np.array_equal(other.get_state(), a), f"chunk {chunk}"
 

@@ -33,7 +33,7 @@ def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
 CASES = [(300, 77, 1e7, 1.0, 31), (128, 128, 1e6, 0.7, 45), (200, 150, 1e8, 7.0, 60), (97, 64, 3e6, 1.0, 0)]
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f32", "f64"])
+@pytest.mark.parametrize("storage", ["bf16", "bf16s", "f32", "f64"])
 def test_group_members_match_alone_bit_exact(storage):
     say(f"group vs alone {storage}")
     alone = []
