@@ -3,20 +3,23 @@
 Workload (headline): 2D Rayleigh-Benard convection, Ra = 1e10, Pr = 1,
 4096 x 4096 cells, tanh(2.5) wall refinement in y, periodic in x, D2Q9 flow
 + thermal populations, semi-implicit + Heun FV step, FP32 arithmetic with
-BF16 storage of the offsets p - w_a ref; FP64 Nusselt/energy reductions every
-1000 steps inside the timed region.  Inputs are synthetic and seeded
-(conductive profile, hydrostatic density, +-1e-3 dT noise) and resident in
-HBM before timing starts.
+16-bit storage (BF16S: FP32 moments + bfloat16 residuals from the forced
+equilibrium, 44 B per cell); FP64 Nusselt/energy reductions every 1000 steps
+inside the timed region.  Inputs are synthetic and seeded (conductive
+profile, hydrostatic density, +-1e-3 dT noise) and resident in HBM before
+timing starts.
 
 One "step" is one full FV time step (predictor + corrector kernels) of the
 whole grid.  value = cells * steps / time in MLUPS.
 
-Also reported: the same grid with FP32 and FP16 storage, the ST step on a
-uniform grid of the same size, per-kernel durations (HIP events on the
-library's stream), the roofline of the dominant kernel and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Also reported: the same grid with FP32, FP16S and plain BF16 storage, the ST
+step on a uniform grid of the same size, per-kernel durations (HIP events on
+the library's stream), the roofline of the dominant kernel, the accuracy of
+every storage format against the FP64 oracle at a steady convective state,
+the serving loop (p50/p99 latency) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants] [--no-accuracy]
 """
 import argparse
 import hashlib
@@ -33,8 +36,12 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "FV-LB MLUPS & % HBM roofline (FP32 vs BF16 storage); serving p50/p99 latency"
 KERNEL_SOURCES = ["paper_1505_03271_amd/csrc/fv.hip", "paper_1505_03271_amd/csrc/lb_device.h",
                   "paper_1505_03271_amd/csrc/lb_kernels.h"]
-COUNTERS = os.path.join(ROOT, "profiles", "fv_rb4096_bf16_counters.json")
-STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+GOLDEN_RB64 = os.path.join(ROOT, "tests", "golden", "rb64_ra1e4_steady.json")
+ACC_STORAGES = ("f64", "f32", "bf16s", "f16s", "bf16")
+
+
+def counters_path(storage):
+    return os.path.join(ROOT, "profiles", f"fv_rb4096_{storage}_counters.json")
 
 
 def kernel_hash():
@@ -123,13 +130,76 @@ def cpu_baseline(cfg, steps=2):
                        f"{oracle.threads()} OpenMP threads, {dt:.1f} s")
 
 
-def traffic_from_counters(launch_cells, kernel):
+def accuracy_report(lb, torch, storages=ACC_STORAGES, chunk=10000):
+    """Every storage format against the FP64 oracle at the steady convective
+    roll of Rayleigh-Benard Ra = 1e4, Pr = 1, 64 x 64, tanh(1.5) (the
+    oracle's run is stored in tests/golden/rb64_ra1e4_steady.json).  All
+    formats run at once, one stream each.  Reported per format: relative
+    error of the wall and volume Nusselt numbers and the relative L2 error of
+    the x-averaged temperature and rms-speed profiles (against the oracle),
+    the relative mass change, and the relative L2 error of the T and u fields
+    against the FP64 path (which equals the oracle to 1e-12 per step in the
+    parity tests; the steady roll may sit at another x, so the profiles are
+    the translation-free measure)."""
+    import numpy as np
+    import workloads
+    with open(GOLDEN_RB64) as fh:
+        gold = json.load(fh)
+    c = gold["config"]
+    n = c["n"]
+    cfg = workloads.rb_config(n, c["Ra"], c["stretch"], seed_index=c["seed_index"])
+    kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
+              T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
+    streams, sims = {}, {}
+    for st in storages:
+        streams[st] = torch.cuda.Stream()
+        sims[st] = lb.Sim(n, n, scheme="heun", storage=st, stream=streams[st].cuda_stream, **kw)
+        sims[st].set_grid(cfg["xf"], cfg["yf"])
+        sims[st].init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"])
+    t0 = time.perf_counter()
+    for k in range(c["steps"] // chunk):
+        for sim in sims.values():
+            sim.step(chunk)
+        if (k + 1) % 10 == 0:
+            for sim in sims.values():
+                sim.sync()
+            log(f"accuracy: {(k + 1) * chunk} of {c['steps']} steps, {time.perf_counter() - t0:.0f} s")
+    res = {}
+    for st, sim in sims.items():
+        res[st] = dict(m=sim.moments(), nu=sim.nusselt(), d=sim.diagnostics())
+        sim.close()
+    ref = res["f64"]["m"] if "f64" in res else None
+    gnu = [gold["nu_bottom"], gold["nu_top"], gold["nu_vol"]]
+    gT, gU = np.array(gold["T_profile"]), np.array(gold["speed_rms_profile"])
+    out = {"case": f"steady roll, RB Ra=1e4 Pr=1 {n}x{n} tanh(1.5), {c['steps']} steps, "
+                   f"against the FP64 oracle (golden file)",
+           "seconds": round(time.perf_counter() - t0, 1)}
+    for st, r in res.items():
+        m = r["m"]
+        Tp = m["T"].mean(axis=1)
+        Up = np.sqrt((m["ux"] ** 2 + m["uy"] ** 2).mean(axis=1))
+        e = {"nu_rel_err": [float(abs(a - b) / abs(b)) for a, b in zip(r["nu"], gnu)],
+             "T_profile_L2": float(np.sqrt(np.mean((Tp - gT) ** 2) / np.mean(gT ** 2))),
+             "speed_profile_L2": float(np.sqrt(np.mean((Up - gU) ** 2) / np.mean(gU ** 2))),
+             "mass_rel_change": float((r["d"]["mass"] - gold["mass"]) / gold["mass"]),
+             "nonfinite": r["d"]["nonfinite"]}
+        if ref is not None and st != "f64":
+            e["T_L2_vs_f64"] = float(np.sqrt(np.mean((m["T"] - ref["T"]) ** 2) / np.mean(ref["T"] ** 2)))
+            du2 = (m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2
+            e["u_L2_vs_f64"] = float(np.sqrt(np.mean(du2) / np.mean(ref["ux"] ** 2 + ref["uy"] ** 2)))
+        e["nu_within_1pct"] = bool(max(e["nu_rel_err"]) <= 0.01)
+        out[st] = e
+    return out
+
+
+def traffic_from_counters(launch_cells, kernel, storage):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size),
     if it was taken on the current kernel source."""
-    if not os.path.exists(COUNTERS):
+    path = counters_path(storage)
+    if not os.path.exists(path):
         return None
-    with open(COUNTERS) as fh:
+    with open(path) as fh:
         c = json.load(fh)
     if c.get("kernel_hash") != kernel_hash() or c.get("cells") != launch_cells:
         return None
@@ -143,7 +213,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--storage", default="bf16")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--storage", default="bf16s")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the serving trace to replay (0: skip serving)")
     ap.add_argument("--calibrate", action="store_true",
@@ -177,33 +248,38 @@ def main():
     log(f"FV {args.storage}: {mlups:.0f} MLUPS ({head['seconds']:.3f} s for {K} steps)")
 
     # roofline of the dominant kernel (per launch: one pass over all cells)
-    Q = 18
-    b = STORE_BYTES[args.storage]
+    b = lb.cell_bytes(args.storage, thermal=True)   # one state, one cell
     (np_, tp), (nc, tc) = head["kernels"]["fv_first_pass"], head["kernels"]["fv_corrector"]
     avg_p, avg_c = tp / np_ / 1e3, tc / nc / 1e3
     # compulsory traffic per cell of each launch: the predictor reads f~n and
-    # writes f~* (2 Q b); the corrector reads f~* and f~n and writes f~n+1 (3 Q b)
+    # writes f~* (2 states); the corrector reads f~* and f~n and writes f~n+1 (3)
     if tc >= tp:
-        name, avg, per_cell = "fv_pass<corrector>", avg_c, 3 * Q * b
+        name, avg, per_cell = "fv_pass<corrector>", avg_c, 3 * b
     else:
-        name, avg, per_cell = "fv_pass<predictor>", avg_p, 2 * Q * b
+        name, avg, per_cell = "fv_pass<predictor>", avg_p, 2 * b
     achieved = per_cell * cells / avg / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells, name),
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells, name, args.storage),
             "kernel": name, "avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_cell": per_cell}
 
-    extra = {"storage": args.storage, "predictor_avg_ms": round(avg_p * 1e3, 4),
+    extra = {"storage": args.storage, "state_bytes_per_cell": b, "predictor_avg_ms": round(avg_p * 1e3, 4),
              "corrector_avg_ms": round(avg_c * 1e3, 4),
-             "step_effective_GBps_2Qb": round(2 * Q * b * cells * K / head["seconds"] / 1e9, 1),
-             "step_compulsory_GBps_5Qb": round(5 * Q * b * cells * K / head["seconds"] / 1e9, 1),
+             "predictor_GBps_2states": round(2 * b * cells / avg_p / 1e9, 1),
+             "corrector_GBps_3states": round(3 * b * cells / avg_c / 1e9, 1),
+             "step_effective_GBps_2states": round(2 * b * cells * K / head["seconds"] / 1e9, 1),
+             "step_compulsory_GBps_5states": round(5 * b * cells * K / head["seconds"] / 1e9, 1),
              "nusselt_bottom_top_vol_last": head["nusselt"][-1] if head["nusselt"] else None,
              "nonfinite": head["diag"]["nonfinite"]}
     if not args.no_variants:
         vsteps = max(args.steps // 4, 50)
-        for st in ("f32", "f16"):
+        for st in ("f32", "f16s", "bf16"):
+            if st == args.storage:
+                continue
             r = run_fv(lb, torch, cfg, st, vsteps, 20)
             extra[f"fv_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
             log(f"FV {st}: {extra[f'fv_{st}_mlups']} MLUPS")
+        if "fv_f32_mlups" in extra:
+            extra["fv_speedup_vs_f32"] = round(mlups / extra["fv_f32_mlups"], 3)
         for st in ("bf16", "f32"):
             r = run_st(lb, torch, n, st, vsteps, 20)
             extra[f"st_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
@@ -220,16 +296,19 @@ def main():
         from paper_1505_03271_amd.serve import Server
         trace = workloads.serving_trace()[:args.serve_requests]
         log(f"serving {len(trace)} requests ...")
-        server = Server(storage="bf16", hbm_budget=16e9, max_sims=128, graph_steps=100)
+        server = Server(storage=args.storage, hbm_budget=16e9, max_sims=128, graph_steps=100)
         st = server.run(trace)
         server.close()
         out["serving"] = {"requests": st["n_requests"], "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                           "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
                           "graph_steps": st["graph_steps"], "graph_launches": st["graph_launches"],
-                          "hbm_budget_bytes": 16e9, "storage": "bf16",
+                          "hbm_budget_bytes": 16e9, "storage": args.storage,
                           "trace": "Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
                                    "steps U{2000..20000}, seed 150503275"}
         log(f"serving: p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, {st['aggregate_mlups']:.0f} MLUPS")
+    if not args.no_accuracy:
+        log("accuracy against the oracle (steady roll) ...")
+        out["accuracy"] = accuracy_report(lb, torch)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

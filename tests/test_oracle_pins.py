@@ -508,3 +508,22 @@ def test_stability_statements_of_the_paper():
     for tau in (0.15, 0.5):
         assert not _kolmogorov_blows_up("heun", tau, 1.3)
     assert _kolmogorov_blows_up("heun", 0.5, 1.9)
+
+
+def test_golden_steady_roll_is_steady_and_balanced():
+    """The oracle's stored steady Rayleigh-Benard roll (Ra = 1e4): at a
+    steady state the heat entering at the bottom leaves at the top (equal
+    wall Nusselt numbers), the volume estimate agrees with them to the
+    discretisation error, and the run had stopped changing."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "rb64_ra1e4_steady.json")
+    with open(path) as fh:
+        g = json.load(fh)
+    assert abs(g["nu_bottom"] - g["nu_top"]) < 1e-8
+    assert max(g["nu_change_last_tenth"]) < 1e-7
+    assert abs(g["nu_vol"] - g["nu_bottom"]) / g["nu_bottom"] < 1e-2
+    assert 2.0 < g["nu_bottom"] < 2.6        # convecting: well above conduction (Nu = 1)
+    T = g["T_profile"]
+    assert abs(T[0] - 0.5) < 0.05 and abs(T[-1] + 0.5) < 0.05   # near the wall temperatures
+    assert all(abs(T[j] + T[-1 - j]) < 1e-6 for j in range(len(T)))  # Boussinesq up-down symmetry
