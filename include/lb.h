@@ -75,7 +75,13 @@ enum lb_storage {
 
 enum lb_boundary {
     LB_PERIODIC = 0,
-    LB_WALL = 1   /* no-slip; for g isothermal on y walls, adiabatic on x walls */
+    LB_WALL = 1,   /* no-slip; for g isothermal on y walls, adiabatic on x walls */
+    /* Fixed density ("Boundary conditions", second rule), x axis, FV schemes,
+     * not thermal: the densities rho_x0 (face x_faces[0]) and rho_x1 (face
+     * x_faces[nx]) are imposed by ghost populations equal to the mirror
+     * cell's, rescaled by (2 rho_S - rho) / rho.  A density difference drives
+     * a pressure-driven flow (p = cs^2 rho). */
+    LB_DENSITY = 2
 };
 
 enum lb_flags {
@@ -98,6 +104,7 @@ typedef struct lb_params {
     double beta_g, T0;       /* Boussinesq: a_y += beta_g (T - T0) */
     double T_bottom, T_top;  /* wall temperatures at y = y_faces[0], y_faces[ny] */
     double rho_ref, T_ref;   /* storage offsets (LB_F32/BF16/F16): f - w rho_ref, g - w T_ref */
+    double rho_x0, rho_x1;   /* LB_DENSITY on x: densities on the faces x_faces[0] and x_faces[nx] */
     void* stream;            /* hipStream_t to enqueue on, or NULL (null stream) */
 } lb_params;
 

@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double), ("tau_g", ctypes.c_double),
                 ("ax", ctypes.c_double), ("ay", ctypes.c_double),
                 ("beta_g", ctypes.c_double), ("T0", ctypes.c_double),
-                ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double)]
+                ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
+                ("rho_lo", ctypes.c_double), ("rho_hi", ctypes.c_double)]
 
 
 _lib = None
@@ -110,10 +111,13 @@ class Case:
 
     def __init__(self, nx, ny, scheme="heun", wall_x=False, wall_y=False, thermal=False,
                  dt=1.0, tau=0.5, tau_g=0.5, ax=0.0, ay=0.0, beta_g=0.0, T0=0.0,
-                 T_bottom=0.0, T_top=0.0, xf=None, yf=None):
+                 T_bottom=0.0, T_top=0.0, xf=None, yf=None, rho_lo=1.0, rho_hi=1.0):
+        """wall_x, wall_y: False/0 periodic, True/1 no-slip wall, 2 fixed density
+        (rho_lo on the low face, rho_hi on the high face of that axis)."""
         self.p = _Params(nx, ny, int(wall_x), int(wall_y), int(thermal), SCHEMES[scheme],
                          float(dt), float(tau), float(tau_g), float(ax), float(ay),
-                         float(beta_g), float(T0), float(T_bottom), float(T_top))
+                         float(beta_g), float(T0), float(T_bottom), float(T_top),
+                         float(rho_lo), float(rho_hi))
         self.nx, self.ny, self.thermal, self.scheme = nx, ny, thermal, scheme
         self.xf = np.ascontiguousarray(xf if xf is not None else np.arange(nx + 1, dtype=float))
         self.yf = np.ascontiguousarray(yf if yf is not None else np.arange(ny + 1, dtype=float))
@@ -159,4 +163,4 @@ class Case:
         p = self.p
         return dict(nx=p.nx, ny=p.ny, wall_x=p.wall_x, wall_y=p.wall_y, thermal=p.thermal, dt=p.dt,
                     tau=p.tau, tau_g=p.tau_g, ax=p.ax, ay=p.ay, beta_g=p.beta_g, T0=p.T0,
-                    T_bottom=p.T_bottom, T_top=p.T_top)
+                    T_bottom=p.T_bottom, T_top=p.T_top, rho_lo=p.rho_lo, rho_hi=p.rho_hi)

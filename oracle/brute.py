@@ -116,6 +116,14 @@ class _Case:
             k = k % n
             return phi[a][other][k] if axis == 0 else phi[a][k][other]
         mirror = -k - 1 if k < 0 else 2 * n - 1 - k
+        if wall == 2:
+            # fixed density on the boundary face: rescale the mirror cell's
+            # population by (extrapolated ghost density) / (mirror density)
+            at = (lambda q: phi[q][other][mirror]) if axis == 0 else (lambda q: phi[q][mirror][other])
+            rho_m = sum(at(q) for q in range(9))
+            rho_face = p["rho_lo"] if k < 0 else p["rho_hi"]
+            rho_ghost = rho_m + 2.0 * (rho_face - rho_m)
+            return at(a) * (rho_ghost / rho_m)
         b = OPPOSITE[a]
         v = phi[b][other][mirror] if axis == 0 else phi[b][mirror][other]
         if thermal and axis == 1:

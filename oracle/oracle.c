@@ -28,6 +28,9 @@
  *    discrete steady state.  Walls normal to x are adiabatic for g (plain
  *    double reflection).
  *  - ST walls: half-way bounce-back for f, anti-bounce-back for g.
+ *  - fixed-density boundaries ("Boundary conditions", second rule) are
+ *    implemented for the flow populations of the FV schemes only; the paper
+ *    gives no thermal rule for them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -51,7 +54,7 @@ enum { OB_FV_HEUN = 0, OB_FV_SEMI = 1, OB_FV_EULER = 2, OB_ST = 3 };
 
 typedef struct {
     int32_t nx, ny;
-    int32_t wall_x, wall_y; /* 0: periodic, 1: no-slip wall */
+    int32_t wall_x, wall_y; /* 0: periodic, 1: no-slip wall, 2: fixed density (FV, flow only) */
     int32_t thermal;        /* 1: double-population thermal model (sec. 5) */
     int32_t scheme;         /* OB_* */
     double dt;
@@ -59,6 +62,7 @@ typedef struct {
     double ax, ay;          /* constant body acceleration */
     double beta_g, T0;      /* Boussinesq: a_y += beta g (T - T0) (sec. 5) */
     double T_bottom, T_top; /* isothermal wall temperatures on the y walls */
+    double rho_lo, rho_hi;  /* fixed densities on the low / high face of a fixed-density axis */
 } ob_params;
 
 int ob_abi_version(void) { return 1; }
@@ -272,10 +276,21 @@ static double node_value(const fv_ctx* C, const double* phi, int s, int a,
         j = axis == 0 ? o : m;
         return phi[a * C->N + (size_t)j * C->nx + i];
     }
-    /* double reflection: f_a(x_-k) = f_inv(a)(x_k) */
     int m = k < 0 ? -k - 1 : 2 * n - 1 - k;
     i = axis == 0 ? m : o;
     j = axis == 0 ? o : m;
+    if (wall == 2) {
+        /* fixed density rho_S on the boundary face: the ghost density is the
+         * linear extrapolation through (x_S, rho_S) and (x_k, rho(x_k)) to
+         * the mirror point x_-k, i.e. 2 rho_S - rho(x_k), and the ghost
+         * populations are the mirror cell's rescaled by rho(x_-k)/rho(x_k) */
+        double rhoS = k < 0 ? C->p->rho_lo : C->p->rho_hi;
+        double rk = 0.0;
+        for (int b = 0; b < Q; ++b) rk += phi[b * C->N + (size_t)j * C->nx + i];
+        double rg = 2.0 * rhoS - rk;
+        return rg / rk * phi[a * C->N + (size_t)j * C->nx + i];
+    }
+    /* double reflection: f_a(x_-k) = f_inv(a)(x_k) */
     double v = phi[INV[a] * C->N + (size_t)j * C->nx + i];
     if (s == 1 && axis == 1) {
         /* isothermal y walls: anti-reflection about the wall temperature */
@@ -411,6 +426,7 @@ int ob_fv_run(const ob_params* p, const double* xf, const double* yf,
 {
     fv_ctx C;
     if (p->nx < 1 || p->ny < 1 || p->scheme == OB_ST) return -1;
+    if (p->thermal && (p->wall_x == 2 || p->wall_y == 2)) return -1;
     if (fv_setup(&C, p, xf, yf)) return -2;
     size_t N = C.N, QN = Q * N;
     int th = p->thermal;
@@ -494,6 +510,7 @@ static int st_dest(const ob_params* p, int a, int i, int j, int* di, int* dj,
 /* Post-collision value of eq:ST's right-hand side, then streaming. */
 int ob_st_run(const ob_params* p, double* ft, double* gt, long long nsteps)
 {
+    if (p->wall_x == 2 || p->wall_y == 2) return -1; /* fixed density: FV only */
     size_t N = (size_t)p->nx * p->ny, QN = Q * N;
     int th = p->thermal;
     double* nf = malloc(sizeof(double) * QN);

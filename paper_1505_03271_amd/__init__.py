@@ -29,7 +29,11 @@ def cell_bytes(storage, thermal=True):
     if storage in ("bf16s", "f16s"):   # float moments + 16-bit residuals
         return 44 if thermal else 24
     return (18 if thermal else 9) * STORAGE_BYTES[storage]
+
+
 FLAG_STREAM_ONLY = 1
+# boundary kinds per axis: periodic, no-slip wall, fixed density (x only)
+BOUNDARY = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "periodic": 0, "wall": 1, "density": 2}
 STATUS = {0: "LB_OK", 1: "LB_EINVAL", 2: "LB_ENOMEM", 3: "LB_EDEVICE", 4: "LB_ESTATE", 5: "LB_EUNSTABLE"}
 
 
@@ -46,7 +50,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("tau_g", ctypes.c_double), ("ax", ctypes.c_double),
                 ("ay", ctypes.c_double), ("beta_g", ctypes.c_double), ("T0", ctypes.c_double),
                 ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double), ("rho_ref", ctypes.c_double),
-                ("T_ref", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("T_ref", ctypes.c_double), ("rho_x0", ctypes.c_double), ("rho_x1", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
 
 
 _lib = None
@@ -144,13 +149,15 @@ class Sim:
 
     def __init__(self, nx, ny, scheme="heun", storage="f64", thermal=False, wall_x=False, wall_y=False,
                  dt=1.0, tau=0.5, tau_g=0.5, ax=0.0, ay=0.0, beta_g=0.0, T0=0.0, T_bottom=0.0, T_top=0.0,
-                 rho_ref=1.0, T_ref=0.0, stream=None, stream_only=False):
+                 rho_ref=1.0, T_ref=0.0, stream=None, stream_only=False, rho_x0=1.0, rho_x1=1.0):
+        """wall_x, wall_y: False/"periodic", True/"wall", or (x only) "density"
+        with the face densities rho_x0, rho_x1."""
         self.nx, self.ny, self.thermal = nx, ny, bool(thermal)
         self.scheme, self.storage = scheme, storage
-        self.p = Params(nx, ny, SCHEMES[scheme], STORAGE[storage], int(bool(thermal)), int(bool(wall_x)),
-                        int(bool(wall_y)), FLAG_STREAM_ONLY if stream_only else 0, float(dt), float(tau),
+        self.p = Params(nx, ny, SCHEMES[scheme], STORAGE[storage], int(bool(thermal)), BOUNDARY[wall_x],
+                        BOUNDARY[wall_y], FLAG_STREAM_ONLY if stream_only else 0, float(dt), float(tau),
                         float(tau_g), float(ax), float(ay), float(beta_g), float(T0), float(T_bottom),
-                        float(T_top), float(rho_ref), float(T_ref),
+                        float(T_top), float(rho_ref), float(T_ref), float(rho_x0), float(rho_x1),
                         stream.value if isinstance(stream, ctypes.c_void_p) else stream)
         self.h = ctypes.c_void_p()
         _check(lib().lb_create(ctypes.byref(self.p), ctypes.byref(self.h)))

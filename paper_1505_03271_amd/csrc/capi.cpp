@@ -230,6 +230,8 @@ void fill_stage_k(const lb_params& p, StageK<R>& k) {
     k.k1g = R(k1g); k.omk1g = R(1 - k1g);
     k.kc = R(kc); k.kf = R(kf); k.kcx3 = R(3 * kc); k.kfx3 = R(3 * kf); k.omkc = R(1 - kc); k.omkcg = R(1 - kcg);
     k.kcg = R(kcg);
+    k.cP = R(kh - (1 - k1) * hdt);
+    k.cB = R(kf - (1 - kc) * hdt);
 }
 
 template <class R>
@@ -244,8 +246,8 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     a.rest_off = uint32_t(8 * size_t(s->nsp) * size_t(s->plane) * es);
     a.nx = s->p.nx;
     a.ny = s->p.ny;
-    a.wall_x = s->p.bc_x == LB_WALL;
-    a.wall_y = s->p.bc_y == LB_WALL;
+    a.wall_x = s->p.bc_x;   // LB_PERIODIC 0, LB_WALL 1, LB_DENSITY 2
+    a.wall_y = s->p.bc_y;
     a.strip_w = FV_LANES - 2 * FV_HALO;
     a.chunk_h = s->chunk_h;
     a.n_strips = (s->p.nx + a.strip_w - 1) / a.strip_w;
@@ -258,6 +260,8 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     fill_stage_k<R>(s->p, a.k);
     a.Tb = R(s->p.T_bottom);
     a.Tt = R(s->p.T_top);
+    a.rho_x0 = R(s->p.rho_x0);
+    a.rho_x1 = R(s->p.rho_x1);
     a.tref = reinterpret_cast<const R*>(s->tref);  // float rows for FP32 arithmetic, NULL for FP64
     return a;
 }
@@ -429,8 +433,13 @@ int lb_create(const lb_params* p, lb_sim** out) {
             return fail(LB_EINVAL, "lb_create: moment-split storage (LB_BF16S, LB_F16S) is for the FV schemes only");
         if (!(p->tau > 0) || (p->thermal && !(p->tau_g > 0))) return fail(LB_EINVAL, "lb_create: tau and tau_g must be > 0");
         if (p->scheme != LB_ST && !(p->dt > 0)) return fail(LB_EINVAL, "lb_create: dt must be > 0");
-        if ((p->bc_x != LB_PERIODIC && p->bc_x != LB_WALL) || (p->bc_y != LB_PERIODIC && p->bc_y != LB_WALL))
-            return fail(LB_EINVAL, "lb_create: bad boundary kind");
+        if ((p->bc_x != LB_PERIODIC && p->bc_x != LB_WALL && p->bc_x != LB_DENSITY) ||
+            (p->bc_y != LB_PERIODIC && p->bc_y != LB_WALL))
+            return fail(LB_EINVAL, "lb_create: bad boundary kind (fixed density is available on x only)");
+        if (p->bc_x == LB_DENSITY && (p->scheme == LB_ST || p->thermal))
+            return fail(LB_EINVAL, "lb_create: fixed-density boundaries are for the flow populations of the FV schemes");
+        if (p->bc_x == LB_DENSITY && !(p->rho_x0 > 0 && p->rho_x1 > 0))
+            return fail(LB_EINVAL, "lb_create: fixed densities rho_x0, rho_x1 must be > 0");
         if ((p->flags & LB_FLAG_STREAM_ONLY) && p->scheme != LB_ST)
             return fail(LB_EINVAL, "lb_create: LB_FLAG_STREAM_ONLY needs LB_ST");
         if (state_size(p->storage, p->thermal != 0, uint64_t(p->nx) * uint64_t(p->ny)) >= (1ull << 32))

@@ -62,6 +62,15 @@ __device__ constexpr int dpop(int p) { return p == 0 ? 4 : p == 1 ? 7 : 8; }
 
 template <int N> struct Slot { static constexpr int value = N; };
 
+// Cache policy of the corrector's state stores: 2 = non-temporal (the new
+// state is read again only by the next step, after it has left the caches).
+// The predictor's output, read back at once by the corrector, keeps the
+// default policy.
+#ifndef LB_STORE_POLICY
+#define LB_STORE_POLICY 2
+#endif
+constexpr int CORR_STORE_POL = LB_STORE_POLICY;
+
 // Heun corrector input: with HEUN_H the predictor also stores
 // H = (f~n + C(f~n))/2 and the corrector reads it (6 Q b bytes per cell-step);
 // without, the corrector reads f~n at its cell and recomputes C (5 Q b).
@@ -101,10 +110,10 @@ template <> struct Io<double> {
         d[2] = R(as_f64(y[0], y[1]));
         d[3] = R(as_f64(y[2], y[3]));
     }
-    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         const double a0 = d[0], a1 = d[1], a2 = d[2], a3 = d[3];
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, STORE_POL);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -116,13 +125,13 @@ template <> struct Io<double> {
             d[0] = R(as_f64(x[0], x[1]));
         }
     }
-    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
         const double a0 = d[0];
         if (N == 2) {
             const double a1 = d[1];
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, STORE_POL);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, STORE_POL);
         }
     }
 };
@@ -132,10 +141,10 @@ template <> struct Io<float> {
 #pragma unroll
         for (int q = 0; q < 4; ++q) d[q] = R(__uint_as_float(x[q]));
     }
-    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         u32x4 x{__float_as_uint(float(d[0])), __float_as_uint(float(d[1])), __float_as_uint(float(d[2])),
                 __float_as_uint(float(d[3]))};
-        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, STORE_POL);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -146,12 +155,12 @@ template <> struct Io<float> {
             d[0] = R(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, 0)));
         }
     }
-    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
         if (N == 2)
             __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(d[0])), __float_as_uint(float(d[1]))},
-                                                  b.r, v, s, 0);
+                                                  b.r, v, s, STORE_POL);
         else
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(d[0])), b.r, v, s, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(d[0])), b.r, v, s, STORE_POL);
     }
 };
 // 16-bit formats: two elements per dword, element k in bits 16 * (k % 2)
@@ -173,9 +182,9 @@ template <bool BF> struct Io16 {
         d[2] = R(dec(x[1], 0));
         d[3] = R(dec(x[1], 1));
     }
-    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{enc2(float(d[0]), float(d[1])), enc2(float(d[2]), float(d[3]))},
-                                              b.r, v, s, 0);
+                                              b.r, v, s, STORE_POL);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -186,9 +195,9 @@ template <bool BF> struct Io16 {
             d[0] = R(dec(__builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, 0), 0));
         }
     }
-    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
-        if (N == 2) __builtin_amdgcn_raw_buffer_store_b32(enc2(float(d[0]), float(d[1])), b.r, v, s, 0);
-        else __builtin_amdgcn_raw_buffer_store_b16(enc(float(d[0])), b.r, v, s, 0);
+    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+        if (N == 2) __builtin_amdgcn_raw_buffer_store_b32(enc2(float(d[0]), float(d[1])), b.r, v, s, STORE_POL);
+        else __builtin_amdgcn_raw_buffer_store_b16(enc(float(d[0])), b.r, v, s, STORE_POL);
     }
 };
 template <> struct Io<bf16_t> : Io16<true> {};
@@ -211,18 +220,18 @@ __device__ inline void load_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t
     if (TH) g[0] = r0[NSP - 1];
 }
 
-template <class R, class S, bool TH>
+template <class R, class S, bool TH, int STORE_POL>
 __device__ inline void store_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t rest_off, const R* f, const R* g) {
     constexpr int NSP = TH ? 2 : 1;
     const uint32_t v4 = cell * uint32_t(4 * sizeof(S));
-    Io<S>::template st4<R>(b, v4, 0u, f + 1);
-    Io<S>::template st4<R>(b, v4, gbytes, f + 5);
+    Io<S>::template st4<R, STORE_POL>(b, v4, 0u, f + 1);
+    Io<S>::template st4<R, STORE_POL>(b, v4, gbytes, f + 5);
     if (TH) {
-        Io<S>::template st4<R>(b, v4, 2 * gbytes, g + 1);
-        Io<S>::template st4<R>(b, v4, 3 * gbytes, g + 5);
+        Io<S>::template st4<R, STORE_POL>(b, v4, 2 * gbytes, g + 1);
+        Io<S>::template st4<R, STORE_POL>(b, v4, 3 * gbytes, g + 5);
     }
     R r0[2] = {f[0], TH ? g[0] : R(0)};
-    Io<S>::template str<R, NSP>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
+    Io<S>::template str<R, NSP, STORE_POL>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
 }
 
 template <class R> __device__ inline R recip(R x) { return R(1) / x; }
@@ -389,30 +398,86 @@ __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, 
     }
 }
 
-// Residuals (stored entries in rf, rg) -> offsets d of all populations, in
-// place, plus the cell's macroscopic state.
-template <class R, bool TH>
-__device__ inline void split_decode(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R& rho, R& T, R& ux,
-                                    R& uy, R& ay) {
+// The stage of a split cell, straight from its moments and residuals r
+// (f~ = f_eq - dt/2 F + r, g = g_eq + r_g).  With P = f_eq / (w rho) =
+// 1 + (E - 1) +- O per opposite pair and F / (w rho) = Fe +- Fo:
+//   phi - w ref   = w (rho' + rho ((E-1 + cP Fe) +- (O + cP Fo))) + (1 - k1) r,  cP = kh - (1 - k1) dt/2
+//   f~ + C - w ref = w (rho' + rho ((E-1 + cB Fe) +- (O + cB Fo))) + (1 - kc) r, cB = kf - (1 - kc) dt/2
+//   f~ - w ref    = w (rho' + rho ((E-1 - dt/2 Fe) +- (O - dt/2 Fo))) + r
+//   phi_g - w Tr  = w (T' + T (E-1 +- O)) + (1 - k1g) r_g,  and likewise with kcg, or r_g alone
+// (rho' = rho - ref, T' = T - Tr).  On entry df, dg hold the stored
+// residuals (f: a = 3..8, g: a = 1..8); the rest follow from zero mass and
+// momentum.  With NEED_D they are replaced by the offsets d of all
+// populations.
+template <class R, bool TH, bool BASE, bool NEED_D>
+__device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
+    constexpr int NSP = TH ? 2 : 1;
     df[1] = df[3] - df[5] + df[6] + df[7] - df[8];
     df[2] = df[4] - df[5] - df[6] + df[7] + df[8];
     df[0] = -(((df[1] + df[2]) + (df[3] + df[4])) + ((df[5] + df[6]) + (df[7] + df[8])));
     if (TH) dg[0] = -(((dg[1] + dg[2]) + (dg[3] + dg[4])) + ((dg[5] + dg[6]) + (dg[7] + dg[8])));
-    split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
-    split_eq<R, TH>(m, rho, T, ux, uy, ay, k, [&](int s, int a, R e) __attribute__((always_inline)) {
-        if (s == 0) df[a] += e; else dg[a] += e;
-    });
-}
-
-template <class R, bool TH, bool BASE>
-__device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
     R rho, T, ux, uy, ay;
-    split_decode<R, TH>(m, df, dg, k, Tr, rho, T, ux, uy, ay);
-    stage_core<R, TH, BASE>(df, dg, m[0], rho, TH ? m[3] : R(0), T, ux, uy, ay, k, ph, bs);
+    split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
+    const R uu = R(1.5) * (ux * ux + uy * uy);
+    const R ua3 = R(3) * (ux * k.ax + uy * ay);
+    const R rp = m[0], Tp = TH ? m[3] : R(0);
+    constexpr R w0 = wt<R>(0);
+    // rest population: no flux
+    if (BASE) {
+        bs[0][0] = w0 * (rp - rho * (uu + k.cB * ua3)) + k.omkc * df[0];
+        if (TH) bs[NSP - 1][0] = w0 * (Tp - T * uu) + k.omkcg * dg[0];
+    }
+    if (NEED_D) {
+        df[0] = w0 * (rp + rho * (k.hdt * ua3 - uu)) + df[0];
+        if (TH) dg[0] = w0 * (Tp - T * uu) + dg[0];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int a = pa(p), b = pb(p);
+        const R w = p < 2 ? wt<R>(1) : wt<R>(5);
+        R cu, ca;
+        if (p == 0) { cu = ux; ca = k.ax; }
+        else if (p == 1) { cu = uy; ca = ay; }
+        else if (p == 2) { cu = ux + uy; ca = k.ax + ay; }
+        else { cu = uy - ux; ca = ay - k.ax; }
+        const R Em = (R(4.5) * cu) * cu - uu;
+        const R O = R(3) * cu;
+        const R Fe = (R(9) * cu) * ca - ua3;
+        const R Fo = R(3) * ca;
+        const R ra = df[a], rb = df[b];
+        const R PE = Em + k.cP * Fe, PO = O + k.cP * Fo;
+        ph[0][a] = w * (rp + rho * (PE + PO)) + k.omk1 * ra;
+        ph[0][b] = w * (rp + rho * (PE - PO)) + k.omk1 * rb;
+        R Gp = 0, Gm = 0;
+        if (TH) {
+            Gp = w * (Tp + T * (Em + O));
+            Gm = w * (Tp + T * (Em - O));
+            ph[NSP - 1][a] = Gp + k.omk1g * dg[a];
+            ph[NSP - 1][b] = Gm + k.omk1g * dg[b];
+        }
+        if (BASE) {
+            const R BE = Em + k.cB * Fe, BO = O + k.cB * Fo;
+            bs[0][a] = w * (rp + rho * (BE + BO)) + k.omkc * ra;
+            bs[0][b] = w * (rp + rho * (BE - BO)) + k.omkc * rb;
+            if (TH) {
+                bs[NSP - 1][a] = Gp + k.omkcg * dg[a];
+                bs[NSP - 1][b] = Gm + k.omkcg * dg[b];
+            }
+        }
+        if (NEED_D) {
+            const R QE = Em - k.hdt * Fe, QO = O - k.hdt * Fo;
+            df[a] = w * (rp + rho * (QE + QO)) + ra;
+            df[b] = w * (rp + rho * (QE - QO)) + rb;
+            if (TH) {
+                dg[a] = Gp + dg[a];
+                dg[b] = Gm + dg[b];
+            }
+        }
+    }
 }
 
 // Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
-template <class R, class S, bool TH>
+template <class R, class S, bool TH, int STORE_POL>
 __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
                                    const R Tr) {
     using IO = Narrow<S>;
@@ -433,17 +498,17 @@ __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df
     if (TH) {
         __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
                                                      __float_as_uint(float(m[2])), __float_as_uint(float(m[3]))},
-                                               b.r, cell * 16u, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, 2 * G, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[7], rf[8]), e2(rg[1], rg[2])}, b.r, v8, 3 * G, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rg[3], rg[4]), e2(rg[5], rg[6])}, b.r, v8, 4 * G, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(e2(rg[7], rg[8]), b.r, v4, 5 * G, 0);
+                                               b.r, cell * 16u, 0u, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, 2 * G, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[7], rf[8]), e2(rg[1], rg[2])}, b.r, v8, 3 * G, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rg[3], rg[4]), e2(rg[5], rg[6])}, b.r, v8, 4 * G, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b32(e2(rg[7], rg[8]), b.r, v4, 5 * G, STORE_POL);
     } else {
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(m[0])), __float_as_uint(float(m[1]))}, b.r,
-                                              v8, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(m[2])), b.r, v4, G, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, G + G / 2, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(e2(rf[7], rf[8]), b.r, v4, 2 * G + G / 2, 0);
+                                              v8, 0u, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(m[2])), b.r, v4, G, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, G + G / 2, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b32(e2(rf[7], rf[8]), b.r, v4, 2 * G + G / 2, STORE_POL);
     }
 }
 
@@ -488,13 +553,17 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // ---- this lane's column (ghost columns mirror or wrap) ----
     const int xg = x0 - FV_HALO + t;
     int col = xg;
-    bool mx = false;
+    bool mx = false;   // ghost column of a no-slip wall
+    bool dxg = false;  // ghost column of a fixed-density boundary (density rho_S on its face)
+    R rho_S = R(1);
     if (xg < 0) {
-        if (A.wall_x) { col = -xg - 1; mx = true; } else col = xg + A.nx;
+        if (A.wall_x) { col = -xg - 1; mx = A.wall_x == 1; dxg = A.wall_x == 2; rho_S = A.rho_x0; }
+        else col = xg + A.nx;
     } else if (xg >= A.nx) {
-        if (A.wall_x) { col = 2 * A.nx - 1 - xg; mx = true; } else col = xg - A.nx;
+        if (A.wall_x) { col = 2 * A.nx - 1 - xg; mx = A.wall_x == 1; dxg = A.wall_x == 2; rho_S = A.rho_x1; }
+        else col = xg - A.nx;
     }
-    if (t >= lanes) { col = 0; mx = false; }  // idle lane of a live wave
+    if (t >= lanes) { col = 0; mx = false; dxg = false; }  // idle lane of a live wave
     const bool owned = t >= FV_HALO && t < FV_HALO + own;
 
     R xc[8];
@@ -548,7 +617,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     constexpr bool AHEAD = sizeof(R) == 4;
     // The corrector's own-cell input goes one row ahead only for 16-bit
     // storage, whose prefetched words stay packed two to a register.
-    constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2;
+    constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2 && !is_split<S>::value;
     // moment-split storage: PF/PG hold the stored residuals, PM the moments
     constexpr bool SPLIT = is_split<S>::value;
     R PF[2][9], PG[2][9], PH[2][9], PHG[2][9], PM[2][4], PHM[2][4];
@@ -565,8 +634,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // store the offsets of a cell of a row whose thermal reference is trow
     auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
                          __attribute__((always_inline)) {
-        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow);
-        else store_cell<R, S, TH>(b, cell, gb, ro, f, g);
+        constexpr int POL = CORR ? CORR_STORE_POL : 0;
+        if constexpr (SPLIT) store_split<R, S, TH, POL>(b, cell, gb, f, g, k, trow);
+        else store_cell<R, S, TH, POL>(b, cell, gb, ro, f, g);
     };
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
@@ -591,13 +661,12 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 
         R ph[NSP][9], bs[NSP][9];
         if constexpr (SPLIT) {  // decodes df, dg to offsets in place
-            if (CORR) stage_split<R, TH, false>(PM[SL & 1], df, dg, k, Tr, ph, bs);
-            else stage_split<R, TH, true>(PM[SL & 1], df, dg, k, Tr, ph, bs);
+            if (CORR) stage_split<R, TH, false, true>(PM[SL & 1], df, dg, k, Tr, ph, bs);
+            else stage_split<R, TH, true, false>(PM[SL & 1], df, dg, k, Tr, ph, bs);
         } else {
             if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
             else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
         }
-
         // ghost row (y walls): double reflection of f, anti-reflection of g
         {
             R tmp[NSP][9];
@@ -620,6 +689,25 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 #pragma unroll
                 for (int a = 1; a < 9; ++a) ph[s][a] = tmp[opp(a)];
             }
+        }
+        if (!TH && A.wall_x == 2) {
+            // ghost column of a fixed-density boundary ("Boundary conditions",
+            // second rule): the ghost density 2 rho_S - rho (linear through
+            // the face value and the mirror cell) rescales the mirror cell's
+            // brackets: phi_ghost = s phi, s = (2 rho_S - rho) / rho, i.e.
+            // phi - w ref -> s (phi - w ref) + (s - 1) w ref.  Flow only.
+            R rho;
+            if constexpr (SPLIT) rho = PM[SL & 1][0] + k.ref_f;
+            else {
+                rho = df[0];
+#pragma unroll
+                for (int a = 1; a < 9; ++a) rho += df[a];
+                rho += k.ref_f;
+            }
+            const R sc = dxg ? (R(2) * rho_S - rho) / rho : R(1);
+            const R sr = (sc - R(1)) * k.ref_f;
+#pragma unroll
+            for (int a = 1; a < 9; ++a) ph[0][a] = sc * ph[0][a] + wt<R>(a) * sr;
         }
 
         // ---- y flux: finish row j = r - 2 (phi rows j-2 .. j+2) before the
@@ -687,8 +775,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                     hg[a] = PHG[SL & 1][a];
                 }
                 if constexpr (SPLIT) {
-                    R q0, q1, q2, q3, q4;
-                    split_decode<R, TH>(PHM[SL & 1], hf, hg, k, Tr, q0, q1, q2, q3, q4);
+                    R phh[NSP][9], bsh[NSP][9];
+                    stage_split<R, TH, false, true>(PHM[SL & 1], hf, hg, k, Tr, phh, bsh);
                 }
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
@@ -705,7 +793,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                         hf[a] = PH[SL & 1][a];
                         hg[a] = PHG[SL & 1][a];
                     }
-                    stage_split<R, TH, true>(PHM[SL & 1], hf, hg, k, Tr, phn, bn);
+                    stage_split<R, TH, true, false>(PHM[SL & 1], hf, hg, k, Tr, phn, bn);
                 } else {
                     stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
                 }

@@ -31,6 +31,7 @@ struct StageK {
     R hdt, ax, ay, bg, T0, ref_f, ref_g;
     R k1, kh, k1x3, khx3, omk1, k1g, omk1g;
     R kc, kf, kcx3, kfx3, omkc, omkcg, kcg;
+    R cP, cB;   // force weights of the split stage: kh - (1 - k1) hdt, kf - (1 - kc) hdt
 };
 
 template <class R>
@@ -42,7 +43,7 @@ struct FvArgs {
     uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
     uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
     int nx, ny;
-    int wall_x, wall_y;
+    int wall_x, wall_y;  // 0 periodic, 1 no-slip wall, 2 (x only) fixed density
     int strip_w;       // owned columns per strip (<= FV_LANES - 4)
     int chunk_h;       // rows per chunk
     int n_strips, n_items;  // work items: n_strips * n_chunks, chunk-major
@@ -50,6 +51,7 @@ struct FvArgs {
     const R* ycoef;    // [ny][8]
     StageK<R> k;
     R Tb, Tt;          // wall temperatures (bottom, top) for the isothermal anti-reflection of g
+    R rho_x0, rho_x1;  // densities on the x faces of a fixed-density axis
     const R* tref;     // per-row thermal reference (g stored as g - w_a tref[row]), or NULL: k.ref_g
 };
 

@@ -21,6 +21,8 @@ def make_pair(nx, ny, scheme, storage, xf, yf, fields, chunk=None, **kw):
         sim.set_fv_chunk(chunk)
     sim.init(*fields)
     okw = {k: v for k, v in kw.items() if k in _OKEYS}
+    if kw.get("wall_x") == "density":
+        okw.update(wall_x=2, rho_lo=kw.get("rho_x0", 1.0), rho_hi=kw.get("rho_x1", 1.0))
     ref = oracle.Case(nx, ny, scheme=scheme, xf=xf, yf=yf, **okw)
     ref.init(*fields)
     torch.cuda.synchronize()

@@ -47,6 +47,11 @@ def test_grid_helpers_match_the_paper_formula():
     (dict(tau=-1.0), "tau"),
     (dict(dt=0.0), "dt"),
     (dict(scheme="heun", stream_only=True), "STREAM_ONLY"),
+    (dict(wall_y="density"), "boundary kind"),
+    (dict(wall_x="density", thermal=True, tau_g=0.5), "fixed-density"),
+    (dict(wall_x="density", scheme="st"), "fixed-density"),
+    (dict(wall_x="density", rho_x0=0.0), "rho_x0"),
+    (dict(scheme="st", storage="bf16s"), "moment-split"),
 ])
 def test_create_rejects_bad_parameters(kw, msg):
     args = dict(nx=16, ny=16, scheme="heun", storage="f32", tau=0.5, dt=1.0)
@@ -58,7 +63,7 @@ def test_create_rejects_bad_parameters(kw, msg):
 
 
 def test_bad_storage_and_scheme_codes():
-    p = lb.Params(16, 16, 0, 7, 0, 0, 0, 0, 1.0, 0.5, 0.5, 0, 0, 0, 0, 0, 0, 1.0, 0.0, None)
+    p = lb.Params(16, 16, 0, 7, 0, 0, 0, 0, 1.0, 0.5, 0.5, 0, 0, 0, 0, 0, 0, 1.0, 0.0, 1.0, 1.0, None)
     h = ctypes.c_void_p()
     assert lb.lib().lb_create(ctypes.byref(p), ctypes.byref(h)) == 1
     assert b"storage" in lb.lib().lb_last_error()

@@ -363,3 +363,74 @@ def test_call_order_errors():
         st.set_grid(np.arange(17.0) * 0.5, np.arange(17.0))
     with pytest.raises(lb.LBError):
         sim.nusselt()
+
+
+# ------------------------------------------------ fixed-density boundary ----
+
+@pytest.mark.parametrize("scheme", ["heun", "semi", "euler"])
+def test_fixed_density_fp64_parity(scheme):
+    """x faces at fixed densities ("Boundary conditions", second rule), y
+    walls, stretched grids, ragged strip: FP64 against the oracle."""
+    nx, ny = 261, 45
+    say(f"fixed density f64 {scheme}")
+    r = np.random.default_rng(17)
+    xf = np.concatenate([[0.0], np.cumsum(r.uniform(0.6, 1.4, nx))])
+    yf = workloads.faces_tanh(ny, 2.0 * ny, 1.5)
+    dt = {"heun": 0.5, "semi": 0.2, "euler": 0.1}[scheme]
+    kw = dict(wall_x="density", wall_y=True, dt=dt, tau=0.3, ax=0.0, ay=-1e-5, rho_x0=1.01, rho_x1=0.995)
+    fields = random_fields(nx, ny, 21, thermal=False)
+    sim, ref = make_pair(nx, ny, scheme, "f64", xf, yf, fields, chunk=16, **kw)
+    sim.step(40)
+    ref.step(40)
+    f, _ = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s"])
+def test_fixed_density_narrow_against_oracle(storage):
+    nx, ny = 130, 40
+    say(f"fixed density {storage}")
+    xf = workloads.faces_uniform(nx, float(nx))
+    yf = workloads.faces_tanh(ny, 2.0 * ny, 1.5)
+    kw = dict(wall_x="density", wall_y=True, dt=0.5, tau=0.3, rho_x0=1.01, rho_x1=0.995)
+    fields = random_fields(nx, ny, 23, thermal=False)
+    sim, ref = make_pair(nx, ny, "heun", storage, xf, yf, fields, chunk=16, **kw)
+    u = UNIT[storage]
+    for steps in (1, 5):
+        sim.step(1 if steps == 1 else 4)
+        ref.step(1 if steps == 1 else 4)
+        f, _ = sim.populations()
+        if storage == "bf16s":
+            R = _residual_scale(ref.f, None, 0.5, 0.0, 0.0, 0.0, 0.0)
+        else:
+            R = np.abs(offsets(ref.f, 1.0)).max()
+        bound = steps * (8 * u * R + 64 * 2.0 ** -24)
+        ef = np.abs(f - ref.f).max()
+        say(f"  steps={steps} err={ef:.3e} bound={bound:.3e}")
+        assert ef < bound
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16s"])
+def test_pressure_driven_channel_steady_state(storage):
+    """A density difference across a walled channel drives Poiseuille flow:
+    uniform mass flux along x and the centreline speed
+    cs^2 (rho0 - rho1) / L_x * L_y^2 / (8 rho nu) (first-order walls and a
+    coarse grid: within 3%)."""
+    nx, ny, drho, tau = 48, 24, 0.002, 1.0 / 6.0
+    say(f"pressure-driven channel {storage}")
+    xf = workloads.faces_uniform(nx, float(nx))
+    yf = workloads.faces_tanh(ny, float(ny), 1.0)
+    x = 0.5 * (xf[1:] + xf[:-1])
+    rho = np.tile(1.0 + drho / 2 - drho * x / nx, (ny, 1))
+    sim = lb.Sim(nx, ny, scheme="heun", storage=storage, wall_x="density", wall_y=True, dt=0.5, tau=tau,
+                 rho_x0=1.0 + drho / 2, rho_x1=1.0 - drho / 2, stream=lb.current_stream())
+    sim.set_grid(xf, yf)
+    sim.init(rho, np.zeros((ny, nx)), np.zeros((ny, nx)))
+    sim.step(40000)
+    m = sim.moments()
+    flux = (m["rho"] * m["ux"] * np.diff(yf)[:, None]).sum(axis=0)
+    assert np.abs(flux - flux.mean()).max() < 5e-4 * abs(flux.mean())
+    u_max = (drho / 3.0 / nx) * ny ** 2 / (8.0 * tau / 3.0)
+    centre = m["ux"][ny // 2 - 1:ny // 2 + 1, nx // 2].mean()
+    say(f"  centre/u_max = {centre / u_max:.4f}")
+    assert abs(centre / u_max - 1) < 0.03

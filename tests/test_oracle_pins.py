@@ -244,6 +244,7 @@ BRUTE = [
     dict(nx=5, ny=7, wall_y=True, stretched=True, thermal=True, ax=1e-3),
     dict(nx=8, ny=6, wall_y=True, wall_x=True, stretched=True, thermal=True, ax=-2e-3),
     dict(nx=6, ny=5, wall_y=False, stretched=True, thermal=True, ax=0.0),
+    dict(nx=7, ny=5, wall_y=True, wall_x=2, stretched=True, thermal=False, ax=0.0),
 ]
 
 
@@ -255,7 +256,7 @@ def test_fv_heun_matches_brute_force(cfg):
     xf = np.concatenate([[0.0], np.cumsum(r.uniform(0.5, 1.5, nx))]) if cfg.get("wall_x") else np.arange(nx + 1.0)
     c = oracle.Case(nx, ny, wall_x=cfg.get("wall_x", False), wall_y=cfg["wall_y"], thermal=cfg["thermal"],
                     dt=0.6, tau=0.25, tau_g=0.15, ax=cfg["ax"], ay=5e-4, beta_g=2e-3, T0=0.1,
-                    T_bottom=0.7, T_top=-0.3, xf=xf, yf=yf)
+                    T_bottom=0.7, T_top=-0.3, xf=xf, yf=yf, rho_lo=1.004, rho_hi=0.997)
     c.init(*_random_state(ny, nx, nx + ny, thermal=cfg["thermal"]))
     f0 = c.f.copy()
     g0 = c.g.copy() if cfg["thermal"] else None
@@ -266,7 +267,7 @@ def test_fv_heun_matches_brute_force(cfg):
         assert np.abs(bg - c.g).max() < 1e-13
 
 
-@pytest.mark.parametrize("cfg", BRUTE, ids=lambda c: f"{c['nx']}x{c['ny']}")
+@pytest.mark.parametrize("cfg", [c for c in BRUTE if c.get("wall_x") != 2], ids=lambda c: f"{c['nx']}x{c['ny']}")
 def test_st_matches_brute_force(cfg):
     nx, ny = cfg["nx"], cfg["ny"]
     c = oracle.Case(nx, ny, scheme="st", wall_x=cfg.get("wall_x", False), wall_y=cfg["wall_y"],
@@ -527,3 +528,52 @@ def test_golden_steady_roll_is_steady_and_balanced():
     T = g["T_profile"]
     assert abs(T[0] - 0.5) < 0.05 and abs(T[-1] + 0.5) < 0.05   # near the wall temperatures
     assert all(abs(T[j] + T[-1 - j]) < 1e-6 for j in range(len(T)))  # Boussinesq up-down symmetry
+
+
+# ------------------------------------------------ fixed-density boundary ----
+# "Boundary conditions", second rule: ghost densities extrapolated linearly
+# through the boundary value, ghost populations = the mirror cell's rescaled.
+
+def test_fixed_density_rest_state_is_a_fixed_point():
+    """Fluid at rest at the boundary density: the ghosts equal their mirror
+    cells, every face value equals the cell value, and nothing moves."""
+    nx, ny = 12, 8
+    xf = np.concatenate([[0.0], np.cumsum(np.random.default_rng(2).uniform(0.5, 1.5, nx))])
+    yf = oracle.grid_tanh(ny, 8.0, 0.8)
+    c = oracle.Case(nx, ny, wall_x=2, wall_y=True, dt=0.5, tau=0.3, xf=xf, yf=yf, rho_lo=1.02, rho_hi=1.02)
+    c.init(np.full((ny, nx), 1.02), np.zeros((ny, nx)), np.zeros((ny, nx)))
+    f0 = c.f.copy()
+    c.step(20)
+    assert np.abs(c.f - f0).max() < 1e-15
+
+
+def _pressure_channel(nx, ny, steps, drho=0.002, tau=1.0 / 6.0, dt=0.5):
+    L_x, L_y = float(nx), float(ny)
+    c = oracle.Case(nx, ny, wall_x=2, wall_y=True, dt=dt, tau=tau, xf=np.arange(nx + 1.0),
+                    yf=oracle.grid_tanh(ny, L_y, 0.8), rho_lo=1.0 + drho / 2, rho_hi=1.0 - drho / 2)
+    x = 0.5 * (c.xf[1:] + c.xf[:-1])
+    rho0 = np.tile(1.0 + drho / 2 - drho * x / L_x, (ny, 1))
+    c.init(rho0, np.zeros((ny, nx)), np.zeros((ny, nx)))
+    c.step(steps)
+    return c, L_x, L_y
+
+
+def test_pressure_driven_channel_reaches_poiseuille():
+    """A density difference across a walled channel drives the Poiseuille
+    flow: at steady state the mass flux through every cross-section is the
+    same, the density falls linearly, and the centreline speed is
+    dp/dx L_y^2 / (8 rho nu) with p = cs^2 rho (nu = tau cs^2)."""
+    nx, ny, drho, tau = 24, 16, 0.002, 1.0 / 6.0
+    c, L_x, L_y = _pressure_channel(nx, ny, 6000, drho=drho, tau=tau)
+    m = c.moments()
+    dy = np.diff(c.yf)
+    flux = (m["rho"] * m["ux"] * dy[:, None]).sum(axis=0)       # per column
+    assert np.abs(flux - flux.mean()).max() < 2e-4 * abs(flux.mean())
+    assert abs(m["uy"]).max() < 1e-3 * m["ux"].max()
+    rho_mean = m["rho"].mean(axis=0)
+    slope = np.polyfit(np.arange(nx) + 0.5, rho_mean, 1)[0]
+    assert abs(slope * L_x / -drho - 1) < 0.05
+    nu = tau / 3.0
+    u_max = (drho / 3.0 / L_x) * L_y ** 2 / (8.0 * nu * 1.0)
+    centre = m["ux"][ny // 2 - 1:ny // 2 + 1, nx // 2].mean()
+    assert abs(centre / u_max - 1) < 0.03
