@@ -134,6 +134,13 @@ int lb_set_grid(lb_sim* sim, const double* x_faces, int64_t n_xf,
 int lb_grid_uniform(int64_t n, double L, double* faces);
 /* Hyperbolic tangent with the paper's factor s1 = tanh(stretch). */
 int lb_grid_tanh(int64_t n, double L, double stretch, double* faces);
+/* Hyperbolic sine with factor s2 (the paper uses 6.5); n must be even (the
+ * two branches of eq:grids meet at i = n/2), else LB_EINVAL. */
+int lb_grid_sinh(int64_t n, double L, double s2, double* faces);
+/* Chebyshev faces xi_i = L/2 (1 - cos(i pi / n)), i = 0..n: the printed
+ * form, with i - 1/2 in place of i, does not start at 0 nor end at L; this
+ * reading keeps the nodes' spacing and spans [0, L]. */
+int lb_grid_chebyshev(int64_t n, double L, double* faces);
 
 /* Initial state at equilibrium (sec. 3.2, sec. 5): host arrays [ny][nx],
  * caller-owned; T is ignored (may be NULL) unless thermal.  Populations are
@@ -161,6 +168,21 @@ int lb_moments(lb_sim* sim, double* rho, double* ux, double* uy, double* T);
  * 1 + H <u_y T>_V / (kappa dT), kappa = tau_g / 3, dT = T_bottom - T_top.
  * FP64 reductions on the device.  LB_EINVAL unless thermal with y walls. */
 int lb_nusselt(lb_sim* sim, double* nu_bottom, double* nu_top, double* nu_vol);
+
+/* Horizontal (x) averages per row j, FP64 device reductions (sec. 5; the
+ * paper time-averages them, which is left to the caller).  out is a
+ * caller-owned host array [6][ny], n_out = 6 * ny:
+ *   0  T_m(y)    = <T>_x
+ *   1  T_rms(y)  = sqrt(<T^2>_x - <T>_x^2)
+ *   2  <u_x^2>_x^(1/2),  3  <u_y^2>_x^(1/2)
+ *   4  <u_y T>_x
+ *   5  Nu(y) = (<u_y T>_x - kappa d<T>_x/dy) / (kappa dT / H), the
+ *      derivative from the parabola through the neighbouring cell centres
+ *      (through the wall value at the first and last row), kappa = tau_g/3.
+ * x averages are weighted by the cell widths.  Rows 0, 1 and 4 are
+ * filled for any thermal run; row 5 needs y walls at different
+ * temperatures (else 0).  LB_EINVAL unless thermal or if n_out != 6 ny. */
+int lb_profiles(lb_sim* sim, double* out, int64_t n_out);
 
 /* FP64 device reductions, out[8]: mass sum V rho, kinetic sum V rho|u|^2/2,
  * thermal sum V T, Nu bottom, Nu top, Nu volume (0 if not applicable),

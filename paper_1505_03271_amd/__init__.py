@@ -73,6 +73,9 @@ def lib():
             "lb_set_grid": ([h, _DP, ctypes.c_int64, _DP, ctypes.c_int64], ctypes.c_int),
             "lb_grid_uniform": ([ctypes.c_int64, ctypes.c_double, _DP], ctypes.c_int),
             "lb_grid_tanh": ([ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP], ctypes.c_int),
+            "lb_grid_sinh": ([ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP], ctypes.c_int),
+            "lb_grid_chebyshev": ([ctypes.c_int64, ctypes.c_double, _DP], ctypes.c_int),
+            "lb_profiles": ([h, _DP, ctypes.c_int64], ctypes.c_int),
             "lb_init": ([h, _DP, _DP, _DP, _DP], ctypes.c_int),
             "lb_step": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_sync": ([h], ctypes.c_int),
@@ -138,6 +141,18 @@ def grid_tanh(n, L, stretch):
     return out
 
 
+def grid_sinh(n, L, s2):
+    out = np.empty(n + 1)
+    _check(lib().lb_grid_sinh(n, L, s2, _dptr(out)))
+    return out
+
+
+def grid_chebyshev(n, L):
+    out = np.empty(n + 1)
+    _check(lib().lb_grid_chebyshev(n, L, _dptr(out)))
+    return out
+
+
 def current_stream():
     """hipStream_t of torch's current stream on the current device."""
     import torch
@@ -193,6 +208,14 @@ class Sim:
         out = [np.empty((self.ny, self.nx)) for _ in range(4)]
         _check(lib().lb_moments(self.h, *[_dptr(o) for o in out]))
         return dict(rho=out[0], ux=out[1], uy=out[2], T=out[3])
+
+    def profiles(self):
+        """Per-row x averages (lb_profiles): dict of [ny] arrays T_mean,
+        T_rms, ux_rms, uy_rms, uyT, Nu."""
+        out = np.empty(6 * self.ny)
+        _check(lib().lb_profiles(self.h, _dptr(out), out.size))
+        out = out.reshape(6, self.ny)
+        return dict(T_mean=out[0], T_rms=out[1], ux_rms=out[2], uy_rms=out[3], uyT=out[4], Nu=out[5])
 
     def nusselt(self):
         b, t, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -357,6 +357,45 @@ __global__ void __launch_bounds__(256) diag_kernel(DiagArgs D, double* partial) 
     }
 }
 
+template <class S>
+__global__ void __launch_bounds__(256) profile_kernel(AuxArgs A, double inv_Lx, double* out) {
+    __shared__ double sh[4];
+    const int j = blockIdx.x;
+    double acc[PROFILE_ROWS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < A.nx; i += 256) {
+        const int64_t c = int64_t(j) * A.nx + i;
+        const Macro<double> m = cell_macro<S>(A, c);
+        const double w = A.dx[i] * inv_Lx;
+        acc[0] += w * m.T;
+        acc[1] += w * m.T * m.T;
+        acc[2] += w * m.ux * m.ux;
+        acc[3] += w * m.uy * m.uy;
+        acc[4] += w * m.uy * m.T;
+    }
+    for (int q = 0; q < PROFILE_ROWS; ++q) {
+        const double r = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) out[int64_t(q) * A.ny + j] = r;
+    }
+}
+
+template <class S>
+static hipError_t profiles_typed(const AuxArgs& a, double inv_Lx, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(profile_kernel<S>, dim3(a.ny), dim3(256), 0, s, a, inv_Lx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_profiles(int storage, const AuxArgs& a, double inv_Lx, double* out, hipStream_t s) {
+    switch (storage) {
+        case ST_F64: return profiles_typed<double>(a, inv_Lx, out, s);
+        case ST_F32: return profiles_typed<float>(a, inv_Lx, out, s);
+        case ST_BF16: return profiles_typed<bf16_t>(a, inv_Lx, out, s);
+        case ST_F16: return profiles_typed<f16_t>(a, inv_Lx, out, s);
+        case ST_BF16S: return profiles_typed<bf16s_t>(a, inv_Lx, out, s);
+        case ST_F16S: return profiles_typed<f16s_t>(a, inv_Lx, out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 __global__ void __launch_bounds__(256) diag_fold(const double* partial, int nblocks, double* out) {
     __shared__ double sh[4];
     for (int q = 0; q < D_COUNT; ++q) {

@@ -422,6 +422,27 @@ int lb_grid_tanh(int64_t n, double L, double stretch, double* faces) {
     return LB_OK;
 }
 
+int lb_grid_sinh(int64_t n, double L, double s2, double* faces) {
+    if (n < 2 || (n & 1) || !faces || !(L > 0) || !(s2 > 0))
+        return fail(LB_EINVAL, "lb_grid_sinh: needs even n >= 2, L > 0, s2 > 0");
+    // eq:grids: A sinh(s2 i / n) up to the middle face, mirrored above it
+    const double A = 0.5 * L / std::sinh(0.5 * s2);
+    for (int64_t i = 0; i <= n; ++i)
+        faces[i] = 2 * i <= n ? A * std::sinh(s2 * double(i) / double(n)) : L - A * std::sinh(s2 * double(n - i) / double(n));
+    faces[0] = 0.0;
+    faces[n] = L;
+    return LB_OK;
+}
+
+int lb_grid_chebyshev(int64_t n, double L, double* faces) {
+    if (n < 1 || !faces || !(L > 0)) return fail(LB_EINVAL, "lb_grid_chebyshev: bad arguments");
+    const double pi = 3.14159265358979323846;
+    for (int64_t i = 0; i <= n; ++i) faces[i] = 0.5 * L * (1.0 - std::cos(pi * double(i) / double(n)));
+    faces[0] = 0.0;
+    faces[n] = L;
+    return LB_OK;
+}
+
 int lb_create(const lb_params* p, lb_sim** out) {
     try {
         if (!p || !out) return fail(LB_EINVAL, "lb_create: NULL argument");
@@ -627,6 +648,54 @@ int lb_diagnostics(lb_sim* s, double* out) {
     if (!out) return fail(LB_EINVAL, "lb_diagnostics: NULL output");
     if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics: no state");
     return run_diagnostics(s, out);
+}
+
+int lb_profiles(lb_sim* s, double* out, int64_t n_out) {
+    if (int rc = check_sim(s)) return rc;
+    const int ny = s->p.ny;
+    if (!s->p.thermal) return fail(LB_EINVAL, "lb_profiles: needs a thermal run");
+    if (!out || n_out != 6 * int64_t(ny)) return fail(LB_EINVAL, "lb_profiles: need an output of 6 * ny = %lld doubles", (long long)(6 * int64_t(ny)));
+    if (!s->has_init) return fail(LB_ESTATE, "lb_profiles: no state");
+    try {
+        double* d = nullptr;
+        HIP_TRY(hipMalloc(&d, sizeof(double) * PROFILE_ROWS * ny));
+        hipError_t e = launch_profiles(s->p.storage, aux_args(s), 1.0 / (s->xf[s->p.nx] - s->xf[0]), d, s->stream);
+        std::vector<double> h(size_t(PROFILE_ROWS) * ny);
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(d);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lb_profiles: %s", hipGetErrorString(e));
+        const double* Tm = h.data();
+        for (int j = 0; j < ny; ++j) {
+            out[j] = Tm[j];
+            out[ny + j] = std::sqrt(std::max(0.0, h[size_t(ny) + j] - Tm[j] * Tm[j]));
+            out[2 * ny + j] = std::sqrt(h[2 * size_t(ny) + j]);
+            out[3 * ny + j] = std::sqrt(h[3 * size_t(ny) + j]);
+            out[4 * ny + j] = h[4 * size_t(ny) + j];
+            out[5 * ny + j] = 0.0;
+        }
+        const double dT = s->p.T_bottom - s->p.T_top;
+        if (s->p.bc_y == LB_WALL && dT != 0.0 && ny >= 2) {
+            const auto& yf = s->yf;
+            const double H = yf[ny] - yf[0], kappa = s->p.tau_g / 3.0;
+            auto yc = [&](int j) { return 0.5 * (yf[j] + yf[j + 1]); };
+            for (int j = 0; j < ny; ++j) {
+                // derivative at y_j of the parabola through three (position, value) points
+                double x0, x1, x2, v0, v1, v2;
+                if (j == 0) { x0 = yf[0]; v0 = s->p.T_bottom; x1 = yc(0); v1 = Tm[0]; x2 = yc(1); v2 = Tm[1]; }
+                else if (j == ny - 1) { x0 = yc(ny - 2); v0 = Tm[ny - 2]; x1 = yc(ny - 1); v1 = Tm[ny - 1]; x2 = yf[ny]; v2 = s->p.T_top; }
+                else { x0 = yc(j - 1); v0 = Tm[j - 1]; x1 = yc(j); v1 = Tm[j]; x2 = yc(j + 1); v2 = Tm[j + 1]; }
+                const double y = yc(j);
+                const double dTdy = v0 * (2 * y - x1 - x2) / ((x0 - x1) * (x0 - x2)) +
+                                    v1 * (2 * y - x0 - x2) / ((x1 - x0) * (x1 - x2)) +
+                                    v2 * (2 * y - x0 - x1) / ((x2 - x0) * (x2 - x1));
+                out[5 * ny + j] = (h[4 * size_t(ny) + j] - kappa * dTdy) / (kappa * dT / H);
+            }
+        }
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb_profiles: out of host memory");
+    }
 }
 
 int lb_nusselt(lb_sim* s, double* nu_bottom, double* nu_top, double* nu_vol) {

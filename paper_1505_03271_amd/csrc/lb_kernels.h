@@ -119,6 +119,10 @@ struct DiagArgs {
     int walls;               // thermal with y walls: compute the wall Nusselt sums
 };
 constexpr int DIAG_BLOCKS = 1024;
+// Per-row x averages (one block per row, fixed reduction order):
+// out[q * ny + j], q = 0 <T>, 1 <T^2>, 2 <ux^2>, 3 <uy^2>, 4 <uy T>, weighted by dx / Lx.
+constexpr int PROFILE_ROWS = 5;
+hipError_t launch_profiles(int storage, const AuxArgs& a, double inv_Lx, double* out, hipStream_t s);
 hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, double* out,
                               hipStream_t s);
 

@@ -76,3 +76,22 @@ def test_null_handle_is_rejected():
     assert lb.lib().lb_step(None, 1) == 1
     assert lb.lib().lb_sync(None) == 1
     lb.lib().lb_destroy(None)  # no-op
+
+
+def test_sinh_and_chebyshev_grids():
+    """eq:grids: the sinh grid against the oracle's independent generator and
+    its closed-form middle face; the Chebyshev faces (reading with i in place
+    of i - 1/2) are symmetric, end at 0 and L, and their cell widths grow
+    like sin(i pi / n) away from the walls."""
+    import oracle
+    x = lb.grid_sinh(64, 64.0, 6.5)
+    np.testing.assert_allclose(x, oracle.grid_sinh(64, 64.0, 6.5), rtol=0, atol=1e-12)
+    assert x[32] == pytest.approx(32.0, abs=1e-12)
+    assert np.all(np.diff(x) > 0) and x[0] == 0.0 and x[-1] == 64.0
+    with pytest.raises(lb.LBError):
+        lb.grid_sinh(63, 64.0, 6.5)
+    c = lb.grid_chebyshev(40, 2.0)
+    assert c[0] == 0.0 and c[-1] == 2.0
+    np.testing.assert_allclose(c + c[::-1], 2.0, atol=1e-14)
+    i = np.arange(40) + 0.5
+    np.testing.assert_allclose(np.diff(c), 2.0 * np.sin(i * np.pi / 40) * np.sin(np.pi / 80), rtol=1e-12)
