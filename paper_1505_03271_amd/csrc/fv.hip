@@ -62,15 +62,6 @@ __device__ constexpr int dpop(int p) { return p == 0 ? 4 : p == 1 ? 7 : 8; }
 
 template <int N> struct Slot { static constexpr int value = N; };
 
-// Cache policy of the corrector's state stores: 2 = non-temporal (the new
-// state is read again only by the next step, after it has left the caches).
-// The predictor's output, read back at once by the corrector, keeps the
-// default policy.
-#ifndef LB_STORE_POLICY
-#define LB_STORE_POLICY 2
-#endif
-constexpr int CORR_STORE_POL = LB_STORE_POLICY;
-
 // Heun corrector input: with HEUN_H the predictor also stores
 // H = (f~n + C(f~n))/2 and the corrector reads it (6 Q b bytes per cell-step);
 // without, the corrector reads f~n at its cell and recomputes C (5 Q b).
@@ -110,10 +101,10 @@ template <> struct Io<double> {
         d[2] = R(as_f64(y[0], y[1]));
         d[3] = R(as_f64(y[2], y[3]));
     }
-    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         const double a0 = d[0], a1 = d[1], a2 = d[2], a3 = d[3];
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, 0);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -125,13 +116,13 @@ template <> struct Io<double> {
             d[0] = R(as_f64(x[0], x[1]));
         }
     }
-    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
         const double a0 = d[0];
         if (N == 2) {
             const double a1 = d[1];
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, STORE_POL);
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, STORE_POL);
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, 0);
         }
     }
 };
@@ -141,10 +132,10 @@ template <> struct Io<float> {
 #pragma unroll
         for (int q = 0; q < 4; ++q) d[q] = R(__uint_as_float(x[q]));
     }
-    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         u32x4 x{__float_as_uint(float(d[0])), __float_as_uint(float(d[1])), __float_as_uint(float(d[2])),
                 __float_as_uint(float(d[3]))};
-        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, 0);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -155,12 +146,12 @@ template <> struct Io<float> {
             d[0] = R(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, 0)));
         }
     }
-    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
         if (N == 2)
             __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(d[0])), __float_as_uint(float(d[1]))},
-                                                  b.r, v, s, STORE_POL);
+                                                  b.r, v, s, 0);
         else
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(d[0])), b.r, v, s, STORE_POL);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(d[0])), b.r, v, s, 0);
     }
 };
 // 16-bit formats: two elements per dword, element k in bits 16 * (k % 2)
@@ -182,9 +173,9 @@ template <bool BF> struct Io16 {
         d[2] = R(dec(x[1], 0));
         d[3] = R(dec(x[1], 1));
     }
-    template <class R, int STORE_POL = 0> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
+    template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{enc2(float(d[0]), float(d[1])), enc2(float(d[2]), float(d[3]))},
-                                              b.r, v, s, STORE_POL);
+                                              b.r, v, s, 0);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -195,9 +186,9 @@ template <bool BF> struct Io16 {
             d[0] = R(dec(__builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, 0), 0));
         }
     }
-    template <class R, int N, int STORE_POL = 0> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
-        if (N == 2) __builtin_amdgcn_raw_buffer_store_b32(enc2(float(d[0]), float(d[1])), b.r, v, s, STORE_POL);
-        else __builtin_amdgcn_raw_buffer_store_b16(enc(float(d[0])), b.r, v, s, STORE_POL);
+    template <class R, int N> __device__ static void str(Buf b, uint32_t v, uint32_t s, const R* d) {
+        if (N == 2) __builtin_amdgcn_raw_buffer_store_b32(enc2(float(d[0]), float(d[1])), b.r, v, s, 0);
+        else __builtin_amdgcn_raw_buffer_store_b16(enc(float(d[0])), b.r, v, s, 0);
     }
 };
 template <> struct Io<bf16_t> : Io16<true> {};
@@ -220,18 +211,18 @@ __device__ inline void load_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t
     if (TH) g[0] = r0[NSP - 1];
 }
 
-template <class R, class S, bool TH, int STORE_POL>
+template <class R, class S, bool TH>
 __device__ inline void store_cell(Buf b, uint32_t cell, uint32_t gbytes, uint32_t rest_off, const R* f, const R* g) {
     constexpr int NSP = TH ? 2 : 1;
     const uint32_t v4 = cell * uint32_t(4 * sizeof(S));
-    Io<S>::template st4<R, STORE_POL>(b, v4, 0u, f + 1);
-    Io<S>::template st4<R, STORE_POL>(b, v4, gbytes, f + 5);
+    Io<S>::template st4<R>(b, v4, 0u, f + 1);
+    Io<S>::template st4<R>(b, v4, gbytes, f + 5);
     if (TH) {
-        Io<S>::template st4<R, STORE_POL>(b, v4, 2 * gbytes, g + 1);
-        Io<S>::template st4<R, STORE_POL>(b, v4, 3 * gbytes, g + 5);
+        Io<S>::template st4<R>(b, v4, 2 * gbytes, g + 1);
+        Io<S>::template st4<R>(b, v4, 3 * gbytes, g + 5);
     }
     R r0[2] = {f[0], TH ? g[0] : R(0)};
-    Io<S>::template str<R, NSP, STORE_POL>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
+    Io<S>::template str<R, NSP>(b, cell * uint32_t(NSP * sizeof(S)), rest_off, r0);
 }
 
 template <class R> __device__ inline R recip(R x) { return R(1) / x; }
@@ -316,41 +307,40 @@ __device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, const
 
 // ---- moment-split cells (storage BF16S / F16S) ---------------------------
 // Layout (SplitLayout, with G = 8 bytes x cells = group_bytes): thermal
-// cells keep m as one float4 at 16 c, residual planes at 2G, 3G, 4G and the
-// tail at 5G; other cells keep (m0, m1) at 8 c, m2 at G + 4 c, the residual
-// plane at 1.5 G and the tail at 2.5 G.
+// cells keep m as a float4 at 16 c, residual slots 0..7 at 2G + 16 c and
+// 8..13 at 4G + 12 c; other cells keep m as three floats at 12 c and the
+// residuals at 1.5 G + 12 c.  One wide load per record and lane.
 template <class S> struct Narrow;
 template <> struct Narrow<bf16s_t> : Io16<true> {};
 template <> struct Narrow<f16s_t> : Io16<false> {};
+typedef __attribute__((ext_vector_type(3))) unsigned u32x3;
 
 template <class R, class S, bool TH>
 __device__ inline void load_split(Buf b, uint32_t cell, uint32_t G, R* m, R* rf, R* rg) {
     using IO = Narrow<S>;
     constexpr float irs = 1.0f / split_scale<S>::value;
     auto d = [&](uint32_t w, int hi) __attribute__((always_inline)) { return R(IO::dec(w, hi) * irs); };
-    const uint32_t v8 = cell * 8u, v4 = cell * 4u;
+    const uint32_t v12 = cell * 12u;
     if (TH) {
-        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, cell * 16u, 0u, 0);
+        const uint32_t v16 = cell * 16u;
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 0u, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[q] = R(__uint_as_float(x[q]));
-        const u32x2 p0 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 2 * G, 0);
-        const u32x2 p1 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 3 * G, 0);
-        const u32x2 p2 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 4 * G, 0);
-        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(b.r, v4, 5 * G, 0);
-        rf[3] = d(p0[0], 0); rf[4] = d(p0[0], 1); rf[5] = d(p0[1], 0); rf[6] = d(p0[1], 1);
-        rf[7] = d(p1[0], 0); rf[8] = d(p1[0], 1); rg[1] = d(p1[1], 0); rg[2] = d(p1[1], 1);
-        rg[3] = d(p2[0], 0); rg[4] = d(p2[0], 1); rg[5] = d(p2[1], 0); rg[6] = d(p2[1], 1);
-        rg[7] = d(t, 0); rg[8] = d(t, 1);
+        const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 2 * G, 0);
+        const u32x3 t = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, 4 * G, 0);
+        rf[3] = d(p[0], 0); rf[4] = d(p[0], 1); rf[5] = d(p[1], 0); rf[6] = d(p[1], 1);
+        rf[7] = d(p[2], 0); rf[8] = d(p[2], 1); rg[1] = d(p[3], 0); rg[2] = d(p[3], 1);
+        rg[3] = d(t[0], 0); rg[4] = d(t[0], 1); rg[5] = d(t[1], 0); rg[6] = d(t[1], 1);
+        rg[7] = d(t[2], 0); rg[8] = d(t[2], 1);
     } else {
-        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, 0u, 0);
+        const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, 0u, 0);
         m[0] = R(__uint_as_float(x[0]));
         m[1] = R(__uint_as_float(x[1]));
-        m[2] = R(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, v4, G, 0)));
+        m[2] = R(__uint_as_float(x[2]));
         m[3] = R(0);
-        const u32x2 p0 = __builtin_amdgcn_raw_buffer_load_b64(b.r, v8, G + G / 2, 0);
-        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(b.r, v4, 2 * G + G / 2, 0);
-        rf[3] = d(p0[0], 0); rf[4] = d(p0[0], 1); rf[5] = d(p0[1], 0); rf[6] = d(p0[1], 1);
-        rf[7] = d(t, 0); rf[8] = d(t, 1);
+        const u32x3 p = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, G + G / 2, 0);
+        rf[3] = d(p[0], 0); rf[4] = d(p[0], 1); rf[5] = d(p[1], 0); rf[6] = d(p[1], 1);
+        rf[7] = d(p[2], 0); rf[8] = d(p[2], 1);
     }
 }
 
@@ -477,7 +467,7 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
 }
 
 // Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
-template <class R, class S, bool TH, int STORE_POL>
+template <class R, class S, bool TH>
 __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
                                    const R Tr) {
     using IO = Narrow<S>;
@@ -494,21 +484,22 @@ __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df
         if (s == 0) rf[a] = df[a] - e; else rg[a] = dg[a] - e;
     });
     auto e2 = [&](R lo, R hi) __attribute__((always_inline)) { return IO::enc2(float(lo) * rs, float(hi) * rs); };
-    const uint32_t v8 = cell * 8u, v4 = cell * 4u;
+    const uint32_t v12 = cell * 12u;
     if (TH) {
+        const uint32_t v16 = cell * 16u;
         __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
                                                      __float_as_uint(float(m[2])), __float_as_uint(float(m[3]))},
-                                               b.r, cell * 16u, 0u, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, 2 * G, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[7], rf[8]), e2(rg[1], rg[2])}, b.r, v8, 3 * G, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rg[3], rg[4]), e2(rg[5], rg[6])}, b.r, v8, 4 * G, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b32(e2(rg[7], rg[8]), b.r, v4, 5 * G, STORE_POL);
+                                               b.r, v16, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8]), e2(rg[1], rg[2])},
+                                               b.r, v16, 2 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{e2(rg[3], rg[4]), e2(rg[5], rg[6]), e2(rg[7], rg[8])}, b.r, v12,
+                                              4 * G, 0);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(float(m[0])), __float_as_uint(float(m[1]))}, b.r,
-                                              v8, 0u, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(m[2])), b.r, v4, G, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{e2(rf[3], rf[4]), e2(rf[5], rf[6])}, b.r, v8, G + G / 2, STORE_POL);
-        __builtin_amdgcn_raw_buffer_store_b32(e2(rf[7], rf[8]), b.r, v4, 2 * G + G / 2, STORE_POL);
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
+                                                    __float_as_uint(float(m[2]))},
+                                              b.r, v12, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8])}, b.r, v12,
+                                              G + G / 2, 0);
     }
 }
 
@@ -634,9 +625,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // store the offsets of a cell of a row whose thermal reference is trow
     auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
                          __attribute__((always_inline)) {
-        constexpr int POL = CORR ? CORR_STORE_POL : 0;
-        if constexpr (SPLIT) store_split<R, S, TH, POL>(b, cell, gb, f, g, k, trow);
-        else store_cell<R, S, TH, POL>(b, cell, gb, ro, f, g);
+        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow);
+        else store_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {

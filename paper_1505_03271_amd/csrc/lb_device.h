@@ -102,28 +102,23 @@ template <> struct split_scale<f16s_t> { static constexpr float value = 1024.0f;
 __host__ __device__ constexpr int split_slot(int s, int a) {
     return s == 0 ? (a >= 3 ? a - 3 : -1) : (a >= 1 ? 5 + a : -1);
 }
-// Byte layout of a split state with `cells` cells:
-//   thermal:      [float4 m per cell][3 planes of 4 residuals (8 B per cell)][plane of 2 residuals]
-//   not thermal:  [float2 (m0, m1) per cell][float m2 per cell][1 plane of 4 residuals][plane of 2]
-// Residual slot k lives in plane k / 4 (element k % 4) for k < 4 K4, else in
-// the 2-element tail plane (element k - 4 K4), K4 = 3 (thermal) or 1.
+// Byte layout of a split state with `cells` cells (each record is read by
+// one lane with one 16- or 12-byte load):
+//   thermal:      [float4 m per cell][8 residuals (16 B) per cell][6 residuals (12 B) per cell]
+//   not thermal:  [float3 m per cell][6 residuals (12 B) per cell]
+// Thermal residual slots 0..7 are in the first residual plane, 8..13 in the
+// second; not thermal, slots 0..5 in the one plane.
 struct SplitLayout {
     bool thermal;
     int64_t cells;
-    __host__ __device__ int k4() const { return thermal ? 3 : 1; }
-    __host__ __device__ int64_t mom2_off() const { return 8 * cells; }   // not thermal: float m2 plane
-    __host__ __device__ int64_t res_off() const { return (thermal ? 16 : 12) * cells; }
-    __host__ __device__ int64_t tail_off() const { return res_off() + 8 * k4() * cells; }
-    __host__ __device__ int64_t bytes() const { return tail_off() + 4 * cells; }
-    // byte offset of moment q (0..3) of cell c
-    __host__ __device__ int64_t mom(int q, int64_t c) const {
-        if (thermal) return 16 * c + 4 * q;
-        return q < 2 ? 8 * c + 4 * q : mom2_off() + 4 * c;
-    }
+    __host__ __device__ int64_t bytes() const { return (thermal ? 44 : 24) * cells; }
+    // byte offset of moment q (0..3; 0..2 when not thermal) of cell c
+    __host__ __device__ int64_t mom(int q, int64_t c) const { return (thermal ? 16 : 12) * c + 4 * q; }
     // byte offset of residual slot k of cell c
     __host__ __device__ int64_t res(int k, int64_t c) const {
-        if (k < 4 * k4()) return res_off() + int64_t(k / 4) * 8 * cells + 8 * c + 2 * (k % 4);
-        return tail_off() + 4 * c + 2 * (k - 4 * k4());
+        if (!thermal) return 12 * cells + 12 * c + 2 * k;
+        if (k < 8) return 16 * cells + 16 * c + 2 * k;
+        return 32 * cells + 12 * c + 2 * (k - 8);
     }
 };
 
