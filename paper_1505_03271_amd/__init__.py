@@ -65,6 +65,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(there is no CPU fallback)")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one liblb links against; whichever is loaded first serves the whole
+        # process.  Load torch's first so that torch and liblb share it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         h = ctypes.c_void_p
         sig = {

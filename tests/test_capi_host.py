@@ -95,3 +95,18 @@ def test_sinh_and_chebyshev_grids():
     np.testing.assert_allclose(c + c[::-1], 2.0, atol=1e-14)
     i = np.arange(40) + 0.5
     np.testing.assert_allclose(np.diff(c), 2.0 * np.sin(i * np.pi / 40) * np.sin(np.pi / 80), rtol=1e-12)
+
+
+
+@pytest.mark.parametrize("storage,n,ok", [("bf16s", 9800, True), ("bf16s", 9900, False), ("f64", 5500, False),
+                                         ("f32", 7700, True), ("f32", 7800, False)])
+def test_state_size_limit(storage, n, ok):
+    """A population state must stay below 4 GiB (32-bit buffer offsets):
+    thermal 44 B/cell (split), 144 B (F64), 72 B (F32).  Rejected before
+    any device allocation; accepted sizes are not created here (no GPU)."""
+    per = {"bf16s": 44, "f64": 144, "f32": 72}[storage]
+    assert (per * n * n < 2 ** 32) == ok
+    if not ok:
+        with pytest.raises(lb.LBError) as e:
+            lb.Sim(n, n, scheme="heun", storage=storage, thermal=True, tau=0.5, tau_g=0.5, dt=1.0)
+        assert e.value.code == 1 and "4 GiB" in str(e.value)

@@ -246,24 +246,46 @@ def test_split_storage_against_oracle(storage, scheme, case):
     assert d["nonfinite"] == 0.0
 
 
-def test_full_size_rb4096_bf16_one_step():
-    """The benchmark's workload and launch shape (4096^2, BF16 storage,
-    default chunking): one full step against the oracle on every cell."""
+@pytest.mark.parametrize("storage", ["bf16s", "bf16"])
+def test_full_size_rb4096_one_step(storage):
+    """The benchmark's workload and launch shape (4096^2, default chunking):
+    two full steps against the oracle on every cell."""
     cfg = workloads.rb4096_config()
     n = cfg["nx"]
-    say(f"rb4096 heun bf16 one step dt={cfg['dt']:.3f}")
+    say(f"rb4096 heun {storage} two steps dt={cfg['dt']:.3f}")
     kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
               T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
-    sim, ref = make_pair(n, n, "heun", "bf16", cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"]), **kw)
-    sim.step(1)
-    ref.step(1)
+    sim, ref = make_pair(n, n, "heun", storage, cfg["xf"], cfg["yf"], (cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"]), **kw)
+    sim.step(2)
+    ref.step(2)
     f, g = sim.populations()
-    bound = _narrow_bound("bf16", ref.f, ref.g, 1)
+    if storage == "bf16s":
+        R = _residual_scale(ref.f, ref.g, cfg["dt"], 0.0, 0.0, cfg["beta_g"], cfg["T0"])
+        bound = 2 * (8 * UNIT[storage] * R + 64 * 2.0 ** -24)
+    else:
+        bound = _narrow_bound(storage, ref.f, ref.g, 2)
     ef, eg = np.abs(f - ref.f).max(), np.abs(g - ref.g).max()
     say(f"  err f={ef:.3e} g={eg:.3e} bound={bound:.3e}")
     assert ef < bound and eg < bound
-    d = sim.diagnostics()
+    d, od = sim.diagnostics(), ref.diagnostics()
     assert d["nonfinite"] == 0.0
+    assert abs(d["mass"] - od["mass"]) < 1e-6 * od["mass"]
+
+
+def test_minimum_grid_and_zero_steps():
+    """The smallest grid the library takes (4 x 4, one strip of four owned
+    columns, y walls, thermal) against the oracle; zero steps change nothing."""
+    say("minimum grid 4x4")
+    kw = dict(thermal=True, wall_y=True, dt=0.4, tau=0.3, tau_g=0.25, beta_g=1e-3, T_bottom=0.5, T_top=-0.5)
+    xf, yf = workloads.faces_uniform(4, 4.0), workloads.faces_tanh(4, 4.0, 1.0)
+    sim, ref = make_pair(4, 4, "heun", "f64", xf, yf, random_fields(4, 4, 51), **kw)
+    before = sim.get_state()
+    sim.step(0)
+    assert np.array_equal(sim.get_state(), before)
+    sim.step(25)
+    ref.step(25)
+    f, g = sim.populations()
+    assert rel_max(f, ref.f) < 1e-12 and rel_max(g, ref.g) < 1e-12
 
 
 # ------------------------------------------------ streaming permutation ----
