@@ -27,7 +27,7 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol():
-    L = ctypes.CDLL(lb.LIB_PATH)
+    L = lb.lib()   # the binding's loader (it puts torch's HIP runtime in place first)
     missing = [n for n in declared_functions() if not hasattr(L, n)]
     assert not missing, f"liblb.so lacks {missing}"
 
