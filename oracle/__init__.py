@@ -164,3 +164,82 @@ class Case:
         return dict(nx=p.nx, ny=p.ny, wall_x=p.wall_x, wall_y=p.wall_y, thermal=p.thermal, dt=p.dt,
                     tau=p.tau, tau_g=p.tau_g, ax=p.ax, ay=p.ay, beta_g=p.beta_g, T0=p.T0,
                     T_bottom=p.T_bottom, T_top=p.T_top, rho_lo=p.rho_lo, rho_hi=p.rho_hi)
+
+
+# ---------------------------------------------------------------- 3D -------
+
+class _Params3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("wall", ctypes.c_int32 * 3), ("thermal", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("tau", ctypes.c_double), ("tau_g", ctypes.c_double),
+                ("a0", ctypes.c_double * 3), ("beta_g", ctypes.c_double), ("T0", ctypes.c_double),
+                ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double)]
+
+
+def _lib3():
+    L = lib()
+    if not hasattr(L, "_ob3_ready"):
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(_Params3)
+        L.ob3_init.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
+        L.ob3_moments.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
+        L.ob3_fv_run.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_longlong]
+        L.ob3_fv_run.restype = ctypes.c_int
+        L.ob3_diagnostics.argtypes = [pp, dp, dp, dp, dp, dp, dp]
+        L._ob3_ready = True
+    return L
+
+
+class Case3D:
+    """One 3D simulation (D3Q19, FV schemes): populations [19][nz][ny][nx];
+    z is the vertical axis (gravity, isothermal walls)."""
+
+    def __init__(self, nx, ny, nz, scheme="heun", walls=(False, False, False), thermal=False, dt=1.0,
+                 tau=0.5, tau_g=0.5, a=(0.0, 0.0, 0.0), beta_g=0.0, T0=0.0, T_bottom=0.0, T_top=0.0,
+                 xf=None, yf=None, zf=None):
+        self.p = _Params3(nx, ny, nz, (ctypes.c_int32 * 3)(*[int(w) for w in walls]), int(thermal),
+                          SCHEMES[scheme], float(dt), float(tau), float(tau_g),
+                          (ctypes.c_double * 3)(*[float(v) for v in a]), float(beta_g), float(T0),
+                          float(T_bottom), float(T_top))
+        self.n = (nx, ny, nz)
+        self.thermal = thermal
+        f = lambda v, n: np.ascontiguousarray(v if v is not None else np.arange(n + 1, dtype=float), dtype=float)
+        self.xf, self.yf, self.zf = f(xf, nx), f(yf, ny), f(zf, nz)
+        self.f = np.zeros((19, nz, ny, nx))
+        self.g = np.zeros((19, nz, ny, nx)) if thermal else None
+
+    def init(self, rho, ux, uy, uz, T=None):
+        c = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        rho, ux, uy, uz = c(rho), c(ux), c(uy), c(uz)
+        T = c(T) if T is not None else np.zeros_like(rho)
+        g = self.g if self.thermal else np.zeros_like(self.f)
+        _lib3().ob3_init(ctypes.byref(self.p), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(T), _ptr(self.f),
+                         _ptr(g))
+
+    def step(self, n=1):
+        g = self.g if self.thermal else np.zeros(1)
+        rc = _lib3().ob3_fv_run(ctypes.byref(self.p), _ptr(self.xf), _ptr(self.yf), _ptr(self.zf), _ptr(self.f),
+                                _ptr(g), n)
+        if rc != 0:
+            raise RuntimeError(f"oracle 3D step failed ({rc})")
+
+    def moments(self):
+        shape = self.f.shape[1:]
+        out = {k: np.empty(shape) for k in ("rho", "ux", "uy", "uz", "T")}
+        g = self.g if self.thermal else np.zeros_like(self.f)
+        _lib3().ob3_moments(ctypes.byref(self.p), _ptr(self.f), _ptr(g), _ptr(out["rho"]), _ptr(out["ux"]),
+                            _ptr(out["uy"]), _ptr(out["uz"]), _ptr(out["T"]))
+        return out
+
+    def diagnostics(self):
+        out = np.empty(8)
+        g = self.g if self.thermal else np.zeros_like(self.f)
+        _lib3().ob3_diagnostics(ctypes.byref(self.p), _ptr(self.xf), _ptr(self.yf), _ptr(self.zf), _ptr(self.f),
+                                _ptr(g), _ptr(out))
+        keys = ("mass", "ekin", "etherm", "nu_bottom", "nu_top", "nu_vol", "volume", "nonfinite")
+        return dict(zip(keys, out))
+
+    def brute_params(self):
+        p = self.p
+        return dict(n=tuple(self.n), wall=tuple(p.wall), thermal=p.thermal, dt=p.dt, tau=p.tau, tau_g=p.tau_g,
+                    a=tuple(p.a0), beta_g=p.beta_g, T0=p.T0, T_bottom=p.T_bottom, T_top=p.T_top)

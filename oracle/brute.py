@@ -228,3 +228,115 @@ def st(p, f, g, nsteps):
         f = nf
         g = ng if p["thermal"] else None
     return np.array(f), (np.array(g) if p["thermal"] else None)
+
+
+# ---------------------------------------------------------------- 3D -------
+# D3Q19, derived from the velocity set: all (cx, cy, cz) in {-1, 0, 1}^3 with
+# at most two non-zero components, in an order of our own.
+
+VEL3 = [c for c in ((x, y, z) for x in (-1, 0, 1) for y in (-1, 0, 1) for z in (-1, 0, 1))
+        if abs(c[0]) + abs(c[1]) + abs(c[2]) <= 2]
+
+
+def _w3(c):
+    s = abs(c[0]) + abs(c[1]) + abs(c[2])
+    return {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0}[s]
+
+
+W3 = [_w3(c) for c in VEL3]
+OPP3 = [VEL3.index((-c[0], -c[1], -c[2])) for c in VEL3]
+
+
+def fv_heun_3d(p, faces, f, g, nsteps, order):
+    """eq:semi-heun in 3D on a tiny grid.  f, g: [19][nz][ny][nx] in the
+    caller's population order `order` (a list of velocity tuples); the
+    result is returned in that order."""
+    nx, ny, nz = p["n"]
+    dt = p["dt"]
+    idx = [VEL3.index(tuple(c)) for c in order]     # caller a -> our a
+    F = np.zeros((19, nz, ny, nx))
+    G = np.zeros((19, nz, ny, nx))
+    for a, b in enumerate(idx):
+        F[b] = f[a]
+        if p["thermal"]:
+            G[b] = g[a]
+    cen = [_centres_with_ghosts(list(map(float, faces[d])), not p["wall"][d]) for d in range(3)]
+
+    def macro(F, G, k, j, i):
+        rho = float(F[:, k, j, i].sum())
+        T = float(G[:, k, j, i].sum()) if p["thermal"] else 0.0
+        acc = list(p["a"])
+        if p["thermal"]:
+            acc[2] += p["beta_g"] * (T - p["T0"])
+        u = [sum(VEL3[a][d] * F[a, k, j, i] for a in range(19)) / rho + dt / 2 * acc[d] for d in range(3)]
+        return rho, u, T, acc
+
+    def stage(F, G):
+        tt, ttg = p["tau"] + dt / 2, p["tau_g"] + dt / 2
+        ph, Cf, phg, Cg = (np.zeros_like(F) for _ in range(4))
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    rho, u, T, acc = macro(F, G, k, j, i)
+                    uu = sum(x * x for x in u)
+                    for a, c in enumerate(VEL3):
+                        cu = sum(c[d] * u[d] for d in range(3))
+                        fe = W3[a] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
+                        Fa = W3[a] * rho * sum((3 * (c[d] - u[d]) + 9 * cu * c[d]) * acc[d] for d in range(3))
+                        fv = F[a, k, j, i]
+                        ph[a, k, j, i] = fv + dt / (2 * tt) * (fe - fv) + dt / 2 * Fa
+                        Cf[a, k, j, i] = dt / tt * (fe - fv) + dt * (1 - dt / (2 * tt)) * Fa
+                        if p["thermal"]:
+                            gv, ge = G[a, k, j, i], T / rho * fe
+                            phg[a, k, j, i] = gv + dt / (2 * ttg) * (ge - gv)
+                            Cg[a, k, j, i] = dt / ttg * (ge - gv)
+        return ph, Cf, phg, Cg
+
+    def node(phi, thermal, a, axis, q, pos):
+        n = p["n"][axis]
+        pos = list(pos)
+        b, sgn, add = a, 1.0, 0.0
+        if 0 <= q < n or not p["wall"][axis]:
+            pos[axis] = q % n
+        else:
+            pos[axis] = -q - 1 if q < 0 else 2 * n - 1 - q
+            b = OPP3[a]
+            if thermal and axis == 2:
+                sgn, add = -1.0, 2 * W3[a] * (p["T_bottom"] if q < 0 else p["T_top"])
+        return sgn * phi[b, pos[2], pos[1], pos[0]] + add
+
+    def div(phi, thermal):
+        D = np.zeros_like(phi)
+        for a, c in enumerate(VEL3):
+            for k in range(nz):
+                for j in range(ny):
+                    for i in range(nx):
+                        pos = (i, j, k)
+                        d = 0.0
+                        for axis in range(3):
+                            if c[axis] == 0:
+                                continue
+                            vals = []
+                            for q in (pos[axis] - 1, pos[axis]):    # faces q | q+1
+                                ks = (q - 1, q, q + 1) if c[axis] > 0 else (q, q + 1, q + 2)
+                                xs = [cen[axis][m] for m in ks]
+                                vs = [node(phi, thermal, a, axis, m, pos) for m in ks]
+                                vals.append(_parabola_at(xs, vs, float(faces[axis][q + 1])))
+                            d += c[axis] * (vals[1] - vals[0]) / (faces[axis][pos[axis] + 1] - faces[axis][pos[axis]])
+                        D[a, k, j, i] = d
+        return D
+
+    for _ in range(nsteps):
+        ph, Cf, phg, Cg = stage(F, G)
+        Df, Dg = div(ph, False), (div(phg, True) if p["thermal"] else None)
+        Fs = F - dt * Df + Cf
+        Gs = G - dt * Dg + Cg if p["thermal"] else G
+        phs, _, phgs, _ = stage(Fs, Gs)
+        F = F - dt / 2 * (Df + div(phs, False)) + Cf
+        if p["thermal"]:
+            G = G - dt / 2 * (Dg + div(phgs, True)) + Cg
+    fo, go = np.zeros_like(F), np.zeros_like(G)
+    for a, b in enumerate(idx):
+        fo[a] = F[b]
+        go[a] = G[b]
+    return fo, (go if p["thermal"] else None)

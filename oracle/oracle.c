@@ -643,3 +643,344 @@ void ob_diagnostics(const ob_params* p, const double* xf, const double* yf,
     out[6] = V;
     out[7] = bad;
 }
+
+/* ======================================================================== */
+/* Three dimensions: D3Q19 (the lattice of the paper's own runs, "Boundary   */
+/* conditions", last paragraph; sec. 5).  Same scheme, face by face along    */
+/* x, y and z; gravity and the isothermal walls are along z.                 */
+/* ======================================================================== */
+
+#define Q3 19
+/* rest, 6 axis velocities, 12 edge velocities; opposite pairs adjacent */
+static const int C3[Q3][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double w3(int a)
+{
+    int s = abs(C3[a][0]) + abs(C3[a][1]) + abs(C3[a][2]);
+    return s == 0 ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+static int inv3(int a)
+{
+    for (int b = 0; b < Q3; ++b)
+        if (C3[b][0] == -C3[a][0] && C3[b][1] == -C3[a][1] && C3[b][2] == -C3[a][2]) return b;
+    return -1;
+}
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t wall[3];        /* per axis: 0 periodic, 1 no-slip wall */
+    int32_t thermal, scheme;
+    double dt, tau, tau_g;
+    double a0[3];           /* constant acceleration */
+    double beta_g, T0;      /* a_z += beta g (T - T0) */
+    double T_bottom, T_top; /* isothermal z walls */
+} ob3_params;
+
+typedef struct {
+    double rho, u[3], T, a[3];
+} ob3_macro;
+
+static ob3_macro macro3(const ob3_params* p, const double* ft, const double* gt, size_t N, size_t c,
+                        double half)
+{
+    ob3_macro m;
+    double rho = 0, j[3] = {0, 0, 0}, T = 0;
+    for (int a = 0; a < Q3; ++a) {
+        double v = ft[a * N + c];
+        rho += v;
+        for (int d = 0; d < 3; ++d) j[d] += C3[a][d] * v;
+    }
+    if (p->thermal)
+        for (int a = 0; a < Q3; ++a) T += gt[a * N + c];
+    m.rho = rho;
+    m.T = T;
+    for (int d = 0; d < 3; ++d) m.a[d] = p->a0[d];
+    if (p->thermal) m.a[2] += p->beta_g * (T - p->T0);
+    for (int d = 0; d < 3; ++d) m.u[d] = j[d] / rho + half * m.a[d];
+    return m;
+}
+
+static double feq3(int a, double rho, const double* u)
+{
+    double cu = 0, uu = 0;
+    for (int d = 0; d < 3; ++d) {
+        cu += C3[a][d] * u[d];
+        uu += u[d] * u[d];
+    }
+    return w3(a) * rho * (1.0 + cu / CS2 + 0.5 * cu * cu / (CS2 * CS2) - 0.5 * uu / CS2);
+}
+
+static double guo3(int a, double rho, const double* u, const double* acc)
+{
+    double cu = 0, s = 0;
+    for (int d = 0; d < 3; ++d) cu += C3[a][d] * u[d];
+    for (int d = 0; d < 3; ++d) s += ((C3[a][d] - u[d]) / CS2 + cu * C3[a][d] / (CS2 * CS2)) * acc[d];
+    return w3(a) * s * rho;
+}
+
+int ob3_abi_version(void) { return 1; }
+
+void ob3_init(const ob3_params* p, const double* rho, const double* ux, const double* uy, const double* uz,
+              const double* T, double* ft, double* gt)
+{
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    double half = p->scheme == OB_FV_EULER ? 0.0 : 0.5 * p->dt;
+    for (size_t c = 0; c < N; ++c) {
+        double u[3] = {ux[c], uy[c], uz[c]};
+        double acc[3] = {p->a0[0], p->a0[1], p->a0[2] + (p->thermal ? p->beta_g * (T[c] - p->T0) : 0.0)};
+        for (int a = 0; a < Q3; ++a) {
+            double fe = feq3(a, rho[c], u);
+            ft[a * N + c] = fe - half * guo3(a, rho[c], u, acc);
+            if (p->thermal) gt[a * N + c] = T[c] / rho[c] * fe;
+        }
+    }
+}
+
+void ob3_moments(const ob3_params* p, const double* ft, const double* gt, double* rho, double* ux,
+                 double* uy, double* uz, double* T)
+{
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    double half = p->scheme == OB_FV_EULER ? 0.0 : 0.5 * p->dt;
+    for (size_t c = 0; c < N; ++c) {
+        ob3_macro m = macro3(p, ft, gt, N, c, half);
+        if (rho) rho[c] = m.rho;
+        if (ux) ux[c] = m.u[0];
+        if (uy) uy[c] = m.u[1];
+        if (uz) uz[c] = m.u[2];
+        if (T) T[c] = m.T;
+    }
+}
+
+typedef struct {
+    const ob3_params* p;
+    int n[3];
+    size_t N;
+    const double* faces[3];
+    double* gam[3];  /* QUICK gammas per axis, 4 per face */
+    double* inv[3];  /* 1 / cell width per axis */
+} fv3_ctx;
+
+/* advected value of population a (species s) at index k along `axis`, the
+ * cell's other two indices taken from (i, j, l) */
+static double node3(const fv3_ctx* C, const double* phi, int s, int a, int axis, int k, int i, int j, int l)
+{
+    int n = C->n[axis];
+    int idx[3] = {i, j, l};
+    int wall = C->p->wall[axis];
+    int b = a;
+    double sgn = 1.0, add = 0.0;
+    if (k >= 0 && k < n) {
+        idx[axis] = k;
+    } else if (!wall) {
+        idx[axis] = ((k % n) + n) % n;
+    } else {
+        /* double reflection; isothermal anti-reflection for g on z walls */
+        idx[axis] = k < 0 ? -k - 1 : 2 * n - 1 - k;
+        b = inv3(a);
+        if (s == 1 && axis == 2) {
+            sgn = -1.0;
+            add = 2.0 * w3(a) * (k < 0 ? C->p->T_bottom : C->p->T_top);
+        }
+    }
+    size_t c = ((size_t)idx[2] * C->n[1] + idx[1]) * C->n[0] + idx[0];
+    return sgn * phi[b * C->N + c] + add;
+}
+
+static double face3(const fv3_ctx* C, const double* phi, int s, int a, int axis, int k, int i, int j, int l)
+{
+    int n = C->n[axis];
+    if (!C->p->wall[axis] && k < 0) k += n;
+    const double* gm = C->gam[axis] + 4 * (k + 1);
+    double P = node3(C, phi, s, a, axis, k, i, j, l);
+    double E = node3(C, phi, s, a, axis, k + 1, i, j, l);
+    if (C3[a][axis] > 0) {
+        double Wv = node3(C, phi, s, a, axis, k - 1, i, j, l);
+        return (1.0 - gm[0] + gm[1]) * P + gm[0] * E - gm[1] * Wv;
+    }
+    double EE = node3(C, phi, s, a, axis, k + 2, i, j, l);
+    return (1.0 - gm[2] + gm[3]) * E + gm[2] * P - gm[3] * EE;
+}
+
+static void flux3(const fv3_ctx* C, const double* phi, int s, double* D)
+{
+    int nx = C->n[0], ny = C->n[1], nz = C->n[2];
+#pragma omp parallel for schedule(static)
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = ((size_t)l * ny + j) * nx + i;
+                int pos[3] = {i, j, l};
+                D[c] = 0.0;
+                for (int a = 1; a < Q3; ++a) {
+                    double d = 0.0;
+                    for (int ax = 0; ax < 3; ++ax)
+                        if (C3[a][ax] != 0)
+                            d += C3[a][ax] * (face3(C, phi, s, a, ax, pos[ax], i, j, l) -
+                                              face3(C, phi, s, a, ax, pos[ax] - 1, i, j, l)) * C->inv[ax][pos[ax]];
+                    D[a * C->N + c] = d;
+                }
+            }
+}
+
+static void stage3(const fv3_ctx* C, const double* ft, const double* gt, double* phf, double* Cf, double* phg,
+                   double* Cg)
+{
+    const ob3_params* p = C->p;
+    size_t N = C->N;
+    double dt = p->dt;
+    int euler = p->scheme == OB_FV_EULER;
+    double tt = euler ? p->tau : p->tau + 0.5 * dt;
+    double ttg = euler ? p->tau_g : p->tau_g + 0.5 * dt;
+    double half = euler ? 0.0 : 0.5 * dt;
+#pragma omp parallel for schedule(static)
+    for (long long cc = 0; cc < (long long)N; ++cc) {
+        size_t c = (size_t)cc;
+        ob3_macro m = macro3(p, ft, gt, N, c, half);
+        for (int a = 0; a < Q3; ++a) {
+            double f = ft[a * N + c];
+            double fe = feq3(a, m.rho, m.u);
+            double F = guo3(a, m.rho, m.u, m.a);
+            if (euler) {
+                phf[a * N + c] = f;
+                if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * F;
+            } else {
+                phf[a * N + c] = f + dt / (2.0 * tt) * (fe - f) + 0.5 * dt * F;
+                if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * (1.0 - dt / (2.0 * tt)) * F;
+            }
+            if (p->thermal) {
+                double g = gt[a * N + c];
+                double ge = m.T / m.rho * fe;
+                phg[a * N + c] = euler ? g : g + dt / (2.0 * ttg) * (ge - g);
+                if (Cg) Cg[a * N + c] = dt / ttg * (ge - g);
+            }
+        }
+    }
+}
+
+int ob3_fv_run(const ob3_params* p, const double* xf, const double* yf, const double* zf, double* ft,
+               double* gt, long long nsteps)
+{
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->scheme == OB_ST) return -1;
+    fv3_ctx C;
+    C.p = p;
+    C.n[0] = p->nx;
+    C.n[1] = p->ny;
+    C.n[2] = p->nz;
+    C.N = (size_t)p->nx * p->ny * p->nz;
+    C.faces[0] = xf;
+    C.faces[1] = yf;
+    C.faces[2] = zf;
+    int ok = 1;
+    for (int d = 0; d < 3; ++d) {
+        C.gam[d] = malloc(sizeof(double) * 4 * (C.n[d] + 1));
+        C.inv[d] = malloc(sizeof(double) * C.n[d]);
+        if (!C.gam[d] || !C.inv[d]) ok = 0;
+    }
+    size_t N = C.N, QN = Q3 * N;
+    int th = p->thermal;
+    double* buf = ok ? malloc(sizeof(double) * QN * (th ? 10 : 5)) : NULL;
+    if (!buf) {
+        for (int d = 0; d < 3; ++d) {
+            free(C.gam[d]);
+            free(C.inv[d]);
+        }
+        return -2;
+    }
+    for (int d = 0; d < 3; ++d) {
+        ob_quick_gammas(C.n[d], C.faces[d], !p->wall[d], C.gam[d]);
+        for (int k = 0; k < C.n[d]; ++k) C.inv[d][k] = 1.0 / (C.faces[d][k + 1] - C.faces[d][k]);
+    }
+    double *phf = buf, *Cf = buf + QN, *Df = buf + 2 * QN, *fs = buf + 3 * QN, *Ds = buf + 4 * QN;
+    double *phg = th ? buf + 5 * QN : NULL, *Cg = th ? buf + 6 * QN : NULL, *Dg = th ? buf + 7 * QN : NULL,
+           *gs = th ? buf + 8 * QN : NULL, *Dgs = th ? buf + 9 * QN : NULL;
+    double dt = p->dt;
+    for (long long n = 0; n < nsteps; ++n) {
+        stage3(&C, ft, gt, phf, Cf, phg, Cg);
+        flux3(&C, phf, 0, Df);
+        if (th) flux3(&C, phg, 1, Dg);
+        if (p->scheme != OB_FV_HEUN) {
+            for (size_t k = 0; k < QN; ++k) ft[k] += -dt * Df[k] + Cf[k];
+            if (th)
+                for (size_t k = 0; k < QN; ++k) gt[k] += -dt * Dg[k] + Cg[k];
+            continue;
+        }
+        for (size_t k = 0; k < QN; ++k) fs[k] = ft[k] - dt * Df[k] + Cf[k];
+        if (th)
+            for (size_t k = 0; k < QN; ++k) gs[k] = gt[k] - dt * Dg[k] + Cg[k];
+        stage3(&C, fs, gs, phf, NULL, phg, NULL);
+        flux3(&C, phf, 0, Ds);
+        if (th) flux3(&C, phg, 1, Dgs);
+        for (size_t k = 0; k < QN; ++k) ft[k] += -0.5 * dt * (Df[k] + Ds[k]) + Cf[k];
+        if (th)
+            for (size_t k = 0; k < QN; ++k) gt[k] += -0.5 * dt * (Dg[k] + Dgs[k]) + Cg[k];
+    }
+    free(buf);
+    for (int d = 0; d < 3; ++d) {
+        free(C.gam[d]);
+        free(C.inv[d]);
+    }
+    return 0;
+}
+
+/* out[8] as ob_diagnostics, with the Nusselt numbers on the z walls
+ * (horizontal averages over x and y, weighted by the cell areas) */
+void ob3_diagnostics(const ob3_params* p, const double* xf, const double* yf, const double* zf,
+                     const double* ft, const double* gt, double* out)
+{
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    size_t N = (size_t)nx * ny * nz, A = (size_t)nx * ny;
+    double half = p->scheme == OB_FV_EULER ? 0.0 : 0.5 * p->dt;
+    double M = 0, Ek = 0, Et = 0, uT = 0, V = 0;
+    int bad = 0;
+    double* T = malloc(sizeof(double) * N);
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = ((size_t)l * ny + j) * nx + i;
+                ob3_macro m = macro3(p, ft, gt, N, c, half);
+                double v = (xf[i + 1] - xf[i]) * (yf[j + 1] - yf[j]) * (zf[l + 1] - zf[l]);
+                M += v * m.rho;
+                Ek += v * 0.5 * m.rho * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
+                Et += v * m.T;
+                uT += v * m.u[2] * m.T;
+                V += v;
+                T[c] = m.T;
+                for (int a = 0; a < Q3; ++a) {
+                    if (!isfinite(ft[a * N + c])) bad = 1;
+                    if (p->thermal && !isfinite(gt[a * N + c])) bad = 1;
+                }
+            }
+    double nub = 0, nut = 0, nuv = 0;
+    if (p->thermal && p->wall[2] && nz >= 2) {
+        double H = zf[nz] - zf[0], dT = p->T_bottom - p->T_top, kappa = p->tau_g * CS2;
+        double z0 = 0.5 * (zf[0] + zf[1]), z1 = 0.5 * (zf[1] + zf[2]);
+        double t0 = 0.5 * (zf[nz - 1] + zf[nz]), t1 = 0.5 * (zf[nz - 2] + zf[nz - 1]);
+        double Area = (xf[nx] - xf[0]) * (yf[ny] - yf[0]);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t c = (size_t)j * nx + i;
+                double w = (xf[i + 1] - xf[i]) * (yf[j + 1] - yf[j]) / Area;
+                double gb = d_parabola(zf[0], p->T_bottom, z0, T[c], z1, T[A + c]);
+                double gtp = d_parabola(zf[nz], p->T_top, t0, T[(size_t)(nz - 1) * A + c], t1,
+                                        T[(size_t)(nz - 2) * A + c]);
+                nub += w * (-gb * H / dT);
+                nut += w * (-gtp * H / dT);
+            }
+        nuv = 1.0 + H * (uT / V) / (kappa * dT);
+    }
+    free(T);
+    out[0] = M;
+    out[1] = Ek;
+    out[2] = Et;
+    out[3] = nub;
+    out[4] = nut;
+    out[5] = nuv;
+    out[6] = V;
+    out[7] = bad;
+}
