@@ -261,6 +261,57 @@ int lb_group_remaining(lb_group* group, int64_t* left);
 /* Message of the last failing call on this thread ("" if none). */
 const char* lb_last_error(void);
 
+/* ======================================================================
+ * Three dimensions: D3Q19, the lattice of the paper's own runs ("Boundary
+ * conditions", last paragraph; sec. 5).  The same FV schemes (LB_FV_HEUN,
+ * LB_FV_SEMI, LB_FV_EULER), QUICK along x, y and z, double reflection at
+ * walls; gravity (Boussinesq a_z += beta_g (T - T0)) and the isothermal
+ * walls (T_bottom at z_faces[0], T_top at z_faces[nz]) are along z, walls
+ * normal to x or y are adiabatic for g.  Populations a = 0..18 have the
+ * velocities
+ *   (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
+ *   (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+ *   (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ * (weights 1/3, 1/18, 1/36).  Field arrays are [nz][ny][nx] (x fastest),
+ * population arrays [19][nz][ny][nx].  Storage LB_F64 or LB_F32 (offsets
+ * p - w rho_ref, g - w T_ref).  Each FV stage runs two kernels (brackets to a
+ * scratch buffer, then flux + update).  Same error conventions as above.
+ * ====================================================================== */
+typedef struct lb3_params {
+    int32_t nx, ny, nz;      /* cells, >= 4 each */
+    int32_t scheme;          /* LB_FV_HEUN, LB_FV_SEMI or LB_FV_EULER */
+    int32_t storage;         /* LB_F64 or LB_F32 */
+    int32_t thermal;
+    int32_t bc[3];           /* LB_PERIODIC or LB_WALL for x, y, z */
+    double dt, tau, tau_g;   /* paper's tau, as in lb_params */
+    double a[3];             /* constant acceleration */
+    double beta_g, T0, T_bottom, T_top;
+    double rho_ref, T_ref;   /* storage offsets for LB_F32 */
+    void* stream;
+} lb3_params;
+
+typedef struct lb3_sim lb3_sim;
+
+int lb3_create(const lb3_params* p, lb3_sim** out);
+void lb3_destroy(lb3_sim* sim);
+/* faces per axis, n+1 each, strictly increasing (copied) */
+int lb3_set_grid(lb3_sim* sim, const double* x_faces, int64_t n_xf, const double* y_faces, int64_t n_yf,
+                 const double* z_faces, int64_t n_zf);
+/* equilibrium start from host fields [nz][ny][nx]; T may be NULL unless thermal */
+int lb3_init(lb3_sim* sim, const double* rho, const double* ux, const double* uy, const double* uz,
+             const double* T);
+int lb3_step(lb3_sim* sim, int64_t nsteps);
+int lb3_sync(lb3_sim* sim);
+/* rho, force-corrected u, T in double; any pointer may be NULL */
+int lb3_moments(lb3_sim* sim, double* rho, double* ux, double* uy, double* uz, double* T);
+/* decoded populations [19][nz][ny][nx] in double (g may be NULL) */
+int lb3_get_populations(lb3_sim* sim, double* f, double* g);
+/* out[8] as lb_diagnostics, the Nusselt numbers on the z walls */
+int lb3_diagnostics(lb3_sim* sim, double* out);
+/* HIP-event timing of the stage passes: launches[2], ms[2] = (first pass, corrector) */
+int lb3_set_timing(lb3_sim* sim, int on);
+int lb3_kernel_times(lb3_sim* sim, int64_t* launches, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

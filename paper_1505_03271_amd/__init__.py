@@ -54,6 +54,15 @@ class Params(ctypes.Structure):
                 ("stream", ctypes.c_void_p)]
 
 
+class Params3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("storage", ctypes.c_int32), ("thermal", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3), ("dt", ctypes.c_double), ("tau", ctypes.c_double),
+                ("tau_g", ctypes.c_double), ("a", ctypes.c_double * 3), ("beta_g", ctypes.c_double),
+                ("T0", ctypes.c_double), ("T_bottom", ctypes.c_double), ("T_top", ctypes.c_double),
+                ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
 _lib = None
 _DP = ctypes.POINTER(ctypes.c_double)
 
@@ -108,6 +117,17 @@ def lib():
             "lb_group_step": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_group_sync": ([h], ctypes.c_int),
             "lb_group_remaining": ([h, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+            "lb3_create": ([ctypes.POINTER(Params3), ctypes.POINTER(h)], ctypes.c_int),
+            "lb3_destroy": ([h], None),
+            "lb3_set_grid": ([h, _DP, ctypes.c_int64, _DP, ctypes.c_int64, _DP, ctypes.c_int64], ctypes.c_int),
+            "lb3_init": ([h, _DP, _DP, _DP, _DP, _DP], ctypes.c_int),
+            "lb3_step": ([h, ctypes.c_int64], ctypes.c_int),
+            "lb3_sync": ([h], ctypes.c_int),
+            "lb3_moments": ([h, _DP, _DP, _DP, _DP, _DP], ctypes.c_int),
+            "lb3_get_populations": ([h, _DP, _DP], ctypes.c_int),
+            "lb3_diagnostics": ([h, _DP], ctypes.c_int),
+            "lb3_set_timing": ([h, ctypes.c_int], ctypes.c_int),
+            "lb3_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -324,3 +344,76 @@ class Group:
         out = (ctypes.c_int64 * self.max_sims)()
         _check(lib().lb_group_remaining(self.h, out))
         return list(out)
+
+
+class Sim3:
+    """A 3D simulation (D3Q19, FV schemes; lb3_create ... lb3_destroy).  z is
+    the vertical axis: gravity and the isothermal walls are along z."""
+
+    def __init__(self, nx, ny, nz, scheme="heun", storage="f64", thermal=False, walls=(False, False, False),
+                 dt=1.0, tau=0.5, tau_g=0.5, a=(0.0, 0.0, 0.0), beta_g=0.0, T0=0.0, T_bottom=0.0, T_top=0.0,
+                 rho_ref=1.0, T_ref=0.0, stream=None):
+        self.n = (nx, ny, nz)
+        self.thermal = bool(thermal)
+        self.p = Params3(nx, ny, nz, SCHEMES[scheme], STORAGE[storage], int(bool(thermal)),
+                         (ctypes.c_int32 * 3)(*[BOUNDARY[w] for w in walls]), float(dt), float(tau), float(tau_g),
+                         (ctypes.c_double * 3)(*[float(v) for v in a]), float(beta_g), float(T0), float(T_bottom),
+                         float(T_top), float(rho_ref), float(T_ref),
+                         stream.value if isinstance(stream, ctypes.c_void_p) else stream)
+        self.h = ctypes.c_void_p()
+        _check(lib().lb3_create(ctypes.byref(self.p), ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().lb3_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_grid(self, xf, yf, zf):
+        x, y, z = _f64(xf), _f64(yf), _f64(zf)
+        _check(lib().lb3_set_grid(self.h, _dptr(x), x.size, _dptr(y), y.size, _dptr(z), z.size))
+
+    def init(self, rho, ux, uy, uz, T=None):
+        shape = self.n[::-1]
+        arrs = [_f64(v, shape) for v in (rho, ux, uy, uz)]
+        t = _f64(T, shape) if T is not None else None
+        _check(lib().lb3_init(self.h, *[_dptr(v) for v in arrs], _dptr(t) if t is not None else None))
+
+    def step(self, n=1):
+        _check(lib().lb3_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().lb3_sync(self.h))
+
+    def moments(self):
+        shape = self.n[::-1]
+        out = {k: np.empty(shape) for k in ("rho", "ux", "uy", "uz", "T")}
+        _check(lib().lb3_moments(self.h, *[_dptr(out[k]) for k in ("rho", "ux", "uy", "uz", "T")]))
+        return out
+
+    def populations(self):
+        shape = (19,) + self.n[::-1]
+        f = np.empty(shape)
+        g = np.empty(shape) if self.thermal else None
+        _check(lib().lb3_get_populations(self.h, _dptr(f), _dptr(g) if g is not None else None))
+        return f, g
+
+    def diagnostics(self):
+        out = np.empty(8)
+        _check(lib().lb3_diagnostics(self.h, _dptr(out)))
+        keys = ("mass", "ekin", "etherm", "nu_bottom", "nu_top", "nu_vol", "volume", "nonfinite")
+        return dict(zip(keys, out.tolist()))
+
+    def set_timing(self, on=True):
+        _check(lib().lb3_set_timing(self.h, int(bool(on))))
+
+    def kernel_times(self):
+        n = (ctypes.c_int64 * 2)()
+        ms = (ctypes.c_double * 2)()
+        _check(lib().lb3_kernel_times(self.h, n, ms))
+        return {"fv_first_pass": (n[0], ms[0]), "fv_corrector": (n[1], ms[1])}

@@ -1027,3 +1027,375 @@ int lb_group_remaining(lb_group* g, int64_t* left) {
 }
 
 }  // extern "C"
+
+// ===================================================================== 3D ==
+
+struct lb3_sim {
+    lb3_params p{};
+    int nsp = 1;
+    int64_t cells = 0;
+    size_t elem = 8, state_bytes = 0;
+    hipStream_t stream = nullptr;
+    void* A = nullptr;        // current state
+    void* B = nullptr;        // predictor / next state
+    void* phi = nullptr;      // brackets of the moving populations, [nsp * 18][cells]
+    void* metric = nullptr;   // flux stencils: pass 0 (x, y, z), pass 1 (x, y, z), [n][8] each
+    double* dxyz = nullptr;   // cell widths dx[nx], dy[ny], dz[nz]
+    double* partial = nullptr;
+    double* dout = nullptr;
+    std::vector<double> faces[3];
+    size_t coef_off[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    bool has_grid = false, has_init = false, unstable = false;
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> kinds;
+    size_t n_rec = 0;
+    int64_t launches[2] = {0, 0};
+    double ms[2] = {0, 0};
+};
+
+namespace {
+
+void release3(lb3_sim* s) {
+    for (void* q : {s->A, s->B, s->phi, s->metric, static_cast<void*>(s->dxyz), static_cast<void*>(s->partial),
+                    static_cast<void*>(s->dout)})
+        if (q) (void)hipFree(q);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    s->events.clear();
+}
+
+// the 2D stage-constant builder from the 3D parameters
+lb_params as2d(const lb3_params& q) {
+    lb_params p{};
+    p.scheme = q.scheme;
+    p.storage = q.storage;
+    p.thermal = q.thermal;
+    p.dt = q.dt;
+    p.tau = q.tau;
+    p.tau_g = q.tau_g;
+    p.ax = q.a[0];
+    p.ay = q.a[1];
+    p.beta_g = q.beta_g;
+    p.T0 = q.T0;
+    p.rho_ref = q.rho_ref;
+    p.T_ref = q.T_ref;
+    return p;
+}
+
+Aux3Args aux3_args(const lb3_sim* s) {
+    Aux3Args a{};
+    a.state = s->A;
+    a.n[0] = s->p.nx;
+    a.n[1] = s->p.ny;
+    a.n[2] = s->p.nz;
+    a.cells = s->cells;
+    a.thermal = s->p.thermal;
+    a.hdt = s->p.scheme == LB_FV_EULER ? 0.0 : 0.5 * s->p.dt;
+    for (int d = 0; d < 3; ++d) a.a[d] = s->p.a[d];
+    a.bg = s->p.thermal ? s->p.beta_g : 0.0;
+    a.T0 = s->p.T0;
+    a.ref_f = s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref;
+    a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
+    a.dx = s->dxyz;
+    a.dy = s->dxyz + s->p.nx;
+    a.dz = s->dxyz + s->p.nx + s->p.ny;
+    return a;
+}
+
+template <class R>
+Fv3Args<R> fv3_args(const lb3_sim* s, const void* src, void* dst, const void* aux, bool corrector) {
+    Fv3Args<R> a{};
+    a.src = src;
+    a.dst = dst;
+    a.aux = aux;
+    a.phi = static_cast<R*>(s->phi);
+    a.n[0] = s->p.nx;
+    a.n[1] = s->p.ny;
+    a.n[2] = s->p.nz;
+    for (int d = 0; d < 3; ++d) {
+        a.wall[d] = s->p.bc[d] == LB_WALL;
+        a.coef[d] = static_cast<const R*>(s->metric) + s->coef_off[corrector ? 1 : 0][d];
+    }
+    a.cells = s->cells;
+    fill_stage_k<R>(as2d(s->p), a.k);
+    a.az = R(s->p.a[2]);
+    a.Tb = R(s->p.T_bottom);
+    a.Tt = R(s->p.T_top);
+    return a;
+}
+
+int record3(lb3_sim* s, int kind) {
+    if (!s->timing) return LB_OK;
+    if (s->n_rec == s->events.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        s->events.push_back(e);
+        s->kinds.push_back(-1);
+    }
+    HIP_TRY(hipEventRecord(s->events[s->n_rec], s->stream));
+    s->kinds[s->n_rec] = kind;
+    ++s->n_rec;
+    return LB_OK;
+}
+
+int fold3(lb3_sim* s) {
+    if (s->n_rec == 0) return LB_OK;
+    HIP_TRY(hipEventSynchronize(s->events[s->n_rec - 1]));
+    for (size_t k = 0; k + 1 < s->n_rec; ++k) {
+        const int kind = s->kinds[k];
+        if (kind < 0 || kind > 1) continue;
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, s->events[k], s->events[k + 1]));
+        s->ms[kind] += t;
+        s->launches[kind] += 1;
+    }
+    s->n_rec = 0;
+    return LB_OK;
+}
+
+int fv3_pass(lb3_sim* s, const void* src, void* dst, const void* aux, bool corrector) {
+    if (int rc = record3(s, corrector ? 1 : 0)) return rc;
+    hipError_t e;
+    if (s->p.storage == LB_F64) {
+        Fv3Args<double> a = fv3_args<double>(s, src, dst, aux, corrector);
+        e = launch_fv3(s->p.storage, s->p.thermal, corrector, &a, s->stream);
+    } else {
+        Fv3Args<float> a = fv3_args<float>(s, src, dst, aux, corrector);
+        e = launch_fv3(s->p.storage, s->p.thermal, corrector, &a, s->stream);
+    }
+    if (e != hipSuccess) return fail(LB_EDEVICE, "3D FV launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int check3(const lb3_sim* s) { return s ? LB_OK : fail(LB_EINVAL, "NULL handle"); }
+
+}  // namespace
+
+extern "C" {
+
+int lb3_create(const lb3_params* p, lb3_sim** out) {
+    try {
+        if (!p || !out) return fail(LB_EINVAL, "lb3_create: NULL argument");
+        *out = nullptr;
+        if (p->nx < 4 || p->ny < 4 || p->nz < 4) return fail(LB_EINVAL, "lb3_create: nx, ny and nz must be >= 4");
+        if (p->scheme != LB_FV_HEUN && p->scheme != LB_FV_SEMI && p->scheme != LB_FV_EULER)
+            return fail(LB_EINVAL, "lb3_create: the 3D step has the FV schemes only");
+        if (p->storage != LB_F64 && p->storage != LB_F32) return fail(LB_EINVAL, "lb3_create: storage must be LB_F64 or LB_F32");
+        if (!(p->tau > 0) || (p->thermal && !(p->tau_g > 0)) || !(p->dt > 0))
+            return fail(LB_EINVAL, "lb3_create: tau, tau_g and dt must be > 0");
+        for (int d = 0; d < 3; ++d)
+            if (p->bc[d] != LB_PERIODIC && p->bc[d] != LB_WALL) return fail(LB_EINVAL, "lb3_create: bad boundary kind");
+        lb3_sim* s = new (std::nothrow) lb3_sim();
+        if (!s) return fail(LB_ENOMEM, "lb3_create: out of host memory");
+        s->p = *p;
+        s->nsp = p->thermal ? 2 : 1;
+        s->cells = int64_t(p->nx) * p->ny * p->nz;
+        s->elem = p->storage == LB_F64 ? 8 : 4;
+        s->state_bytes = size_t(s->nsp) * 19 * size_t(s->cells) * s->elem;
+        s->stream = static_cast<hipStream_t>(p->stream);
+        hipError_t e;
+        if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
+            (e = hipMalloc(&s->phi, size_t(s->nsp) * 18 * size_t(s->cells) * s->elem)) != hipSuccess ||
+            (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
+            (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess) {
+            release3(s);
+            delete s;
+            return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "lb3_create: device allocation failed: %s",
+                        hipGetErrorString(e));
+        }
+        *out = s;
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb3_create: unexpected failure");
+    }
+}
+
+void lb3_destroy(lb3_sim* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    release3(s);
+    delete s;
+}
+
+int lb3_set_grid(lb3_sim* s, const double* xf, int64_t nxf, const double* yf, int64_t nyf, const double* zf,
+                 int64_t nzf) {
+    if (int rc = check3(s)) return rc;
+    try {
+        const double* f[3] = {xf, yf, zf};
+        const int64_t nf[3] = {nxf, nyf, nzf};
+        const int n[3] = {s->p.nx, s->p.ny, s->p.nz};
+        for (int d = 0; d < 3; ++d) {
+            if (!f[d] || nf[d] != n[d] + 1) return fail(LB_EINVAL, "lb3_set_grid: need n+1 faces per axis");
+            for (int64_t i = 0; i + 1 < nf[d]; ++i)
+                if (!(f[d][i + 1] > f[d][i])) return fail(LB_EINVAL, "lb3_set_grid: faces not increasing");
+        }
+        std::vector<double> m, dxyz;
+        for (int pass = 0; pass < 2; ++pass) {
+            const double factor = pass == 0 ? s->p.dt : 0.5 * s->p.dt;
+            for (int d = 0; d < 3; ++d) {
+                std::vector<double> faces(f[d], f[d] + nf[d]);
+                std::vector<double> w = quick_weights(faces, s->p.bc[d] == LB_PERIODIC);
+                std::vector<double> st = flux_stencils(faces, w, factor);
+                s->coef_off[pass][d] = m.size();
+                m.insert(m.end(), st.begin(), st.end());
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            s->faces[d].assign(f[d], f[d] + nf[d]);
+            for (int i = 0; i < n[d]; ++i) dxyz.push_back(f[d][i + 1] - f[d][i]);
+        }
+        if (s->metric) { (void)hipFree(s->metric); s->metric = nullptr; }
+        if (s->dxyz) { (void)hipFree(s->dxyz); s->dxyz = nullptr; }
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (s->p.storage == LB_F64) {
+            HIP_TRY(hipMalloc(&s->metric, m.size() * sizeof(double)));
+            HIP_TRY(hipMemcpy(s->metric, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> mf(m.begin(), m.end());
+            HIP_TRY(hipMalloc(&s->metric, mf.size() * sizeof(float)));
+            HIP_TRY(hipMemcpy(s->metric, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipMalloc(&s->dxyz, dxyz.size() * sizeof(double)));
+        HIP_TRY(hipMemcpy(s->dxyz, dxyz.data(), dxyz.size() * sizeof(double), hipMemcpyHostToDevice));
+        s->has_grid = true;
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb3_set_grid: out of host memory");
+    }
+}
+
+int lb3_init(lb3_sim* s, const double* rho, const double* ux, const double* uy, const double* uz, const double* T) {
+    if (int rc = check3(s)) return rc;
+    if (!s->has_grid) return fail(LB_ESTATE, "lb3_init: call lb3_set_grid first");
+    if (!rho || !ux || !uy || !uz || (s->p.thermal && !T)) return fail(LB_EINVAL, "lb3_init: NULL field");
+    const size_t n = size_t(s->cells);
+    double* d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const double* h[5] = {rho, ux, uy, uz, s->p.thermal ? T : rho};
+    int rc = LB_OK;
+    for (int q = 0; q < 5 && rc == LB_OK; ++q) rc = upload_temp(h[q], n, &d[q], s->stream);
+    if (rc == LB_OK) {
+        const double* in[5] = {d[0], d[1], d[2], d[3], d[4]};
+        hipError_t e = launch_aux3(s->p.storage, 0, aux3_args(s), in, nullptr, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = fail(LB_EDEVICE, "lb3_init: %s", hipGetErrorString(e));
+    }
+    for (double* q : d) if (q) (void)hipFree(q);
+    if (rc == LB_OK) { s->has_init = true; s->unstable = false; }
+    return rc;
+}
+
+int lb3_step(lb3_sim* s, int64_t nsteps) {
+    if (int rc = check3(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb3_step: call lb3_init first");
+    if (nsteps < 0) return fail(LB_EINVAL, "lb3_step: negative step count");
+    if (s->unstable) return fail(LB_EUNSTABLE, "lb3_step: non-finite populations were detected");
+    for (int64_t n = 0; n < nsteps; ++n) {
+        int rc;
+        if (s->p.scheme == LB_FV_HEUN) {
+            if ((rc = fv3_pass(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
+            if ((rc = fv3_pass(s, s->B, s->A, s->A, true))) return rc;      // corrector in place over A
+        } else {
+            if ((rc = fv3_pass(s, s->A, s->B, nullptr, false))) return rc;
+            std::swap(s->A, s->B);
+        }
+    }
+    if (s->timing) return record3(s, -1);
+    return LB_OK;
+}
+
+int lb3_sync(lb3_sim* s) {
+    if (int rc = check3(s)) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return LB_OK;
+}
+
+int lb3_moments(lb3_sim* s, double* rho, double* ux, double* uy, double* uz, double* T) {
+    if (int rc = check3(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb3_moments: no state");
+    const size_t n = size_t(s->cells);
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, 5 * n * sizeof(double)));
+    double* outs[5] = {d, d + n, d + 2 * n, d + 3 * n, d + 4 * n};
+    hipError_t e = launch_aux3(s->p.storage, 1, aux3_args(s), nullptr, outs, s->stream);
+    double* h[5] = {rho, ux, uy, uz, T};
+    for (int q = 0; q < 5 && e == hipSuccess; ++q)
+        if (h[q]) e = hipMemcpyAsync(h[q], outs[q], n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb3_moments: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int lb3_get_populations(lb3_sim* s, double* f, double* g) {
+    if (int rc = check3(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb3_get_populations: no state");
+    if (!f) return fail(LB_EINVAL, "lb3_get_populations: NULL f");
+    const size_t n = size_t(s->cells) * 19;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, size_t(s->nsp) * n * sizeof(double)));
+    double* outs[1] = {d};
+    hipError_t e = launch_aux3(s->p.storage, 2, aux3_args(s), nullptr, outs, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && s->p.thermal && g) e = hipMemcpyAsync(g, d + n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb3_get_populations: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+int lb3_diagnostics(lb3_sim* s, double* out) {
+    if (int rc = check3(s)) return rc;
+    if (!s->has_init) return fail(LB_ESTATE, "lb3_diagnostics: no state");
+    if (!out) return fail(LB_EINVAL, "lb3_diagnostics: NULL output");
+    Diag3Args d{};
+    d.a = aux3_args(s);
+    const int nz = s->p.nz;
+    const auto& zf = s->faces[2];
+    const double H = zf[nz] - zf[0], dT = s->p.T_bottom - s->p.T_top;
+    d.walls = s->p.thermal && s->p.bc[2] == LB_WALL && dT != 0.0;
+    if (d.walls) {
+        d_weights(zf[0], 0.5 * (zf[0] + zf[1]), 0.5 * (zf[1] + zf[2]), d.nub);
+        d_weights(zf[nz], 0.5 * (zf[nz - 1] + zf[nz]), 0.5 * (zf[nz - 2] + zf[nz - 1]), d.nut);
+        d.nu_scale = -H / dT;
+    }
+    d.Tb = s->p.T_bottom;
+    d.Tt = s->p.T_top;
+    d.inv_area = 1.0 / ((s->faces[0].back() - s->faces[0][0]) * (s->faces[1].back() - s->faces[1][0]));
+    hipError_t e = launch_diag3(s->p.storage, d, s->partial, s->dout, s->stream);
+    double o[D_COUNT];
+    if (e == hipSuccess) e = hipMemcpyAsync(o, s->dout, sizeof o, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb3_diagnostics: %s", hipGetErrorString(e));
+    const double kappa = s->p.tau_g / 3.0;
+    out[0] = o[D_MASS];
+    out[1] = o[D_EKIN];
+    out[2] = o[D_ETH];
+    out[3] = d.walls ? o[D_NUB] : 0.0;
+    out[4] = d.walls ? o[D_NUT] : 0.0;
+    out[5] = d.walls ? 1.0 + H * (o[D_UT] / o[D_VOL]) / (kappa * dT) : 0.0;
+    out[6] = o[D_VOL];
+    out[7] = o[D_BAD];
+    if (o[D_BAD] != 0.0) s->unstable = true;
+    return LB_OK;
+}
+
+int lb3_set_timing(lb3_sim* s, int on) {
+    if (int rc = check3(s)) return rc;
+    if (s->timing && !on)
+        if (int rc = fold3(s)) return rc;
+    s->timing = on != 0;
+    s->launches[0] = s->launches[1] = 0;
+    s->ms[0] = s->ms[1] = 0;
+    s->n_rec = 0;
+    return LB_OK;
+}
+
+int lb3_kernel_times(lb3_sim* s, int64_t* launches, double* ms) {
+    if (int rc = check3(s)) return rc;
+    if (!launches || !ms) return fail(LB_EINVAL, "lb3_kernel_times: NULL output");
+    if (int rc = fold3(s)) return rc;
+    for (int k = 0; k < 2; ++k) { launches[k] = s->launches[k]; ms[k] = s->ms[k]; }
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -126,4 +126,43 @@ hipError_t launch_profiles(int storage, const AuxArgs& a, double inv_Lx, double*
 hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, double* out,
                               hipStream_t s);
 
+// ---- three dimensions (D3Q19, fv3d.hip) ----------------------------------
+template <class R>
+struct Fv3Args {
+    const void* src;   // state read by the stage and at the own cell (f~n, or f~* in the corrector)
+    void* dst;         // new state
+    const void* aux;   // corrector: f~n at the own cell; NULL otherwise
+    R* phi;            // scratch: [nsp * 18][cells] brackets
+    int n[3];
+    int wall[3];       // per axis: 0 periodic, 1 wall
+    int64_t cells;
+    const R* coef[3];  // per axis [n][8] four-point stencils (c > 0: i-2..i+1, c < 0: i-1..i+2), times dt or dt/2
+    StageK<R> k;       // stage constants (k.ax, k.ay: x and y accelerations)
+    R az;              // constant z acceleration (the Boussinesq term is added along z)
+    R Tb, Tt;          // z wall temperatures
+};
+// One FV stage (stage + update kernels) of a 3D simulation.
+hipError_t launch_fv3(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
+size_t fv3_args_bytes(int storage);
+
+struct Aux3Args {
+    void* state;       // (s * 19 + a) * cells + cell
+    int n[3];
+    int64_t cells;
+    int thermal;
+    double hdt, a[3], bg, T0, ref_f, ref_g;
+    const double *dx, *dy, *dz;
+};
+// what: 0 init (in = rho, ux, uy, uz, T), 1 moments (out = rho, ux, uy, uz, T),
+// 2 populations (out[0] = [nsp * 19][cells] in double)
+hipError_t launch_aux3(int storage, int what, const Aux3Args& a, const double* const* in, double* const* out,
+                       hipStream_t s);
+struct Diag3Args {
+    Aux3Args a;
+    double nub[3], nut[3];   // one-sided derivative weights at the z walls
+    double Tb, Tt, inv_area, nu_scale;
+    int walls;
+};
+hipError_t launch_diag3(int storage, const Diag3Args& d, double* partial, double* out, hipStream_t s);
+
 }  // namespace lbk
