@@ -114,6 +114,29 @@ def run_st(lb, torch, n, storage, steps, warmup):
     return dict(seconds=wall, kernels=kt, cells=n * n, steps=steps)
 
 
+def run_fv3d(lb, torch, n, steps, warmup, storage="f32"):
+    """The 3D (D3Q19) FV-Heun step on a cubic Rayleigh-Benard cell of n^3
+    cells (Ra = 1e8, Pr = 1, tanh(2.0) in z)."""
+    import workloads
+    cfg = workloads.rb3d_config(n, 1e8, 2.0)
+    sim = lb.Sim3(n, n, n, scheme="heun", storage=storage, thermal=True, walls=(False, False, True), dt=cfg["dt"],
+                  tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"], T_bottom=cfg["T_bottom"],
+                  T_top=cfg["T_top"], stream=lb.current_stream())
+    sim.set_grid(cfg["xf"], cfg["yf"], cfg["zf"])
+    sim.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["uz"], cfg["T"])
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = sim.kernel_times()
+    d = sim.diagnostics()
+    sim.close()
+    return dict(seconds=wall, kernels=kt, cells=n ** 3, steps=steps, nonfinite=d["nonfinite"])
+
+
 def cpu_baseline(cfg, steps=2):
     """The FP64 oracle, as is, on `steps` steps of the full workload."""
     import oracle
@@ -280,6 +303,11 @@ def main():
             log(f"FV {st}: {extra[f'fv_{st}_mlups']} MLUPS")
         if "fv_f32_mlups" in extra:
             extra["fv_speedup_vs_f32"] = round(mlups / extra["fv_f32_mlups"], 3)
+        r3 = run_fv3d(lb, torch, 256, max(args.steps // 20, 20), 5)
+        extra["fv3d_rb256_f32_mlups"] = round(r3["cells"] * r3["steps"] / r3["seconds"] / 1e6, 1)
+        (n1, t1), (n2, t2) = r3["kernels"]["fv_first_pass"], r3["kernels"]["fv_corrector"]
+        extra["fv3d_rb256_f32_pass_ms"] = [round(t1 / max(n1, 1), 3), round(t2 / max(n2, 1), 3)]
+        log(f"FV 3D 256^3 f32: {extra['fv3d_rb256_f32_mlups']} MLUPS")
         for st in ("bf16", "f32"):
             r = run_st(lb, torch, n, st, vsteps, 20)
             extra[f"st_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)

@@ -166,6 +166,10 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
     if (c >= A.cells) return;
     const int i[3] = {int(c % A.n[0]), int((c / A.n[0]) % A.n[1]), int(c / (int64_t(A.n[0]) * A.n[1]))};
     const StageK<R>& k = A.k;
+    const int64_t stride[3] = {1, int64_t(A.n[0]), int64_t(A.n[0]) * A.n[1]};
+    bool inner[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) inner[d] = i[d] >= 2 && i[d] + 2 < A.n[d];
     const S* own = static_cast<const S*>(CORR ? A.aux : A.src);
     const S* star = static_cast<const S*>(A.src);
     S* dst = static_cast<S*>(A.dst);
@@ -190,14 +194,20 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
                          : k.omkcg * d + k.kcg * w3<R>(a) * (m.T_p + m.T * pm1);
             if (CORR) b = R(0.5) * (b + R(Store3<S>::ld(star + e)));
             if (a > 0) {
+                const R* pa = A.phi + int64_t(s * 18 + a - 1) * A.cells;
 #pragma unroll
                 for (int axis = 0; axis < 3; ++axis) {
                     const int cd = c3(a, axis);
                     if (cd == 0) continue;
                     const R* w = A.coef[axis] + int64_t(i[axis]) * 8 + (cd > 0 ? 0 : 4);
-                    const int q0 = i[axis] + (cd > 0 ? -2 : -1);
+                    const int q0 = cd > 0 ? -2 : -1;
+                    if (inner[axis]) {  // all four points inside: plain strided loads
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) b -= w[q] * phi_at<R>(A, s, a, axis, q0 + q, i);
+                        for (int q = 0; q < 4; ++q) b -= w[q] * pa[c + (q0 + q) * stride[axis]];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) b -= w[q] * phi_at<R>(A, s, a, axis, i[axis] + q0 + q, i);
+                    }
                 }
             }
             Store3<S>::st(dst + e, S(b));

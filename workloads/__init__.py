@@ -95,6 +95,32 @@ def rb_fields(nx, yf, dT, T0, beta_g, noise=1e-3, seed_index=2):
     return np.repeat(rho[:, None], nx, axis=1), np.zeros((ny, nx)), np.zeros((ny, nx)), T
 
 
+def rb3d_fields(nx, ny, zf, dT, T0, beta_g, noise=1e-3, seed_index=8):
+    """The 3D Rayleigh-Benard initial state (z vertical): conductive T(z),
+    hydrostatic density, seeded uniform +-noise*dT on T; arrays [nz][ny][nx]."""
+    H = zf[-1] - zf[0]
+    zc = centres(zf) - zf[0]
+    nz = len(zc)
+    Tc = T0 + dT * (0.5 - zc / H)
+    rho = np.exp(-beta_g * dT * (zc - 0.5 * H) ** 2 / (2.0 * H * CS2))
+    r = rng(seed_index)
+    shape = (nz, ny, nx)
+    T = np.broadcast_to(Tc[:, None, None], shape) + r.uniform(-noise * dT, noise * dT, size=shape)
+    return (np.ascontiguousarray(np.broadcast_to(rho[:, None, None], shape)), np.zeros(shape), np.zeros(shape),
+            np.zeros(shape), np.ascontiguousarray(T))
+
+
+def rb3d_config(n, Ra, stretch, Pr=1.0, seed_index=8, cfl=1.0):
+    """Cubic 3D Rayleigh-Benard cell (aspect 1, periodic sides, tanh-refined
+    z), the recipe of sec. 5 as in rb_params."""
+    P = rb_params(Ra, Pr, n, n, aspect=1.0, stretch=stretch, cfl=cfl)
+    zf = P["yf"]
+    rho, ux, uy, uz, T = rb3d_fields(n, n, zf, P["dT"], P["T0"], P["beta_g"], seed_index=seed_index)
+    P.update(name=f"rb3d_{n}", nz=n, zf=zf, xf=P["xf"], yf=faces_uniform(n, P["L"]), rho=rho, ux=ux, uy=uy, uz=uz,
+             T=T)
+    return P
+
+
 # ----------------------------------------------------------- parameters ----
 
 def rb_params(Ra, Pr, nx, ny, aspect=1.0, stretch=2.0, U_ff=0.1, dT=1.0, tau_min=0.5, cfl=1.0):
