@@ -484,6 +484,39 @@ def test_rayleigh_benard_ra1e4_nusselt_fv():
     assert abs(d["nu_top"] - gold["Nu"]) < 0.05
 
 
+def test_onset_between_1600_and_1800():
+    """sec. 5: at aspect ratio 2.02 convection sets in between Ra = 1600 and
+    1800.  The oracle's stored roll energies (written by
+    tests/golden/make_onset_rates.py) decay at 1600 and grow at 1800 at a
+    steady exponential rate, and the oracle still reproduces the first
+    checkpoint of both runs."""
+    gold = json.load(open(os.path.join(GOLDEN, "rb_onset_rates.json")))
+    rate = {}
+    for key, run in gold["runs"].items():
+        e = np.array(run["roll_energy"])
+        r = e[1:] / e[:-1]
+        assert np.ptp(r) < 1e-3 * r.mean()                 # one exponential mode
+        rate[key] = r.mean()
+    assert rate["1600"] < 0.9 and rate["1800"] > 1.1
+    cfg = gold["config"]
+    for key, run in gold["runs"].items():
+        Ra = float(key)
+        nx, ny = run["nx"], cfg["ny"]
+        P = workloads.rb_params(Ra, cfg["Pr"], nx, ny, aspect=nx / ny, stretch=cfg["stretch"])
+        rho, ux, uy, T = workloads.rb_fields(nx, P["yf"], P["dT"], P["T0"], P["beta_g"], noise=cfg["noise"],
+                                             seed_index=cfg["seed_index"])
+        c = oracle.Case(nx, ny, scheme="heun", thermal=True, wall_y=True, dt=P["dt"], tau=P["tau"],
+                        tau_g=P["tau_g"], beta_g=P["beta_g"], T0=P["T0"], T_bottom=P["T_bottom"],
+                        T_top=P["T_top"], xf=P["xf"], yf=P["yf"])
+        c.init(rho, ux, uy, T)
+        c.step(run["steps_per_checkpoint"])
+        m = c.moments()
+        du = m["ux"] - m["ux"].mean(axis=1, keepdims=True)
+        dv = m["uy"] - m["uy"].mean(axis=1, keepdims=True)
+        e = 0.5 * float(np.sum(m["rho"] * (du * du + dv * dv)))
+        assert abs(e / run["roll_energy"][0] - 1) < 1e-9
+
+
 # ----------------------------------------------------------- stability ----
 
 def _kolmogorov_blows_up(scheme, tau, dt, steps=3000, n=64):
