@@ -113,6 +113,7 @@ typedef struct lb_sim lb_sim;
 /* Create a simulation.  The library owns the handle and all device buffers
  * (two population buffers of 9 or 18 planes each).  Errors: LB_EINVAL for
  * unsupported sizes/values (nx or ny < 4, tau or tau_g <= 0, dt <= 0 for FV,
+ * one population buffer of 4 GiB or more (buffer offsets are 32 bits);
  * thermal with bc_y periodic is allowed but lb_nusselt then fails),
  * LB_ENOMEM, LB_EDEVICE. */
 int lb_create(const lb_params* p, lb_sim** out);

@@ -315,32 +315,45 @@ template <> struct Narrow<bf16s_t> : Io16<true> {};
 template <> struct Narrow<f16s_t> : Io16<false> {};
 typedef __attribute__((ext_vector_type(3))) unsigned u32x3;
 
-template <class R, class S, bool TH>
-__device__ inline void load_split(Buf b, uint32_t cell, uint32_t G, R* m, R* rf, R* rg) {
-    using IO = Narrow<S>;
-    constexpr float irs = 1.0f / split_scale<S>::value;
-    auto d = [&](uint32_t w, int hi) __attribute__((always_inline)) { return R(IO::dec(w, hi) * irs); };
+// A split record as loaded: the words stay packed (11 or 6 registers) until
+// decode_split, which is placed where the values are used, so the wait for
+// a load sits there and not at the load.
+template <bool TH> struct SplitRaw {
+    u32x4 m;  // moments (thermal: 4 words; otherwise words 0..2)
+    u32x4 p;  // residual slots 0..7 (otherwise 0..5 in words 0..2)
+    u32x3 t;  // residual slots 8..13 (thermal only)
+};
+
+template <class S, bool TH>
+__device__ inline void load_split_raw(Buf b, uint32_t cell, uint32_t G, SplitRaw<TH>& w) {
     const uint32_t v12 = cell * 12u;
     if (TH) {
         const uint32_t v16 = cell * 16u;
-        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 0u, 0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) m[q] = R(__uint_as_float(x[q]));
-        const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 2 * G, 0);
-        const u32x3 t = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, 4 * G, 0);
-        rf[3] = d(p[0], 0); rf[4] = d(p[0], 1); rf[5] = d(p[1], 0); rf[6] = d(p[1], 1);
-        rf[7] = d(p[2], 0); rf[8] = d(p[2], 1); rg[1] = d(p[3], 0); rg[2] = d(p[3], 1);
-        rg[3] = d(t[0], 0); rg[4] = d(t[0], 1); rg[5] = d(t[1], 0); rg[6] = d(t[1], 1);
-        rg[7] = d(t[2], 0); rg[8] = d(t[2], 1);
+        w.m = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 0u, 0);
+        w.p = __builtin_amdgcn_raw_buffer_load_b128(b.r, v16, 2 * G, 0);
+        w.t = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, 4 * G, 0);
     } else {
         const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, 0u, 0);
-        m[0] = R(__uint_as_float(x[0]));
-        m[1] = R(__uint_as_float(x[1]));
-        m[2] = R(__uint_as_float(x[2]));
-        m[3] = R(0);
         const u32x3 p = __builtin_amdgcn_raw_buffer_load_b96(b.r, v12, G + G / 2, 0);
-        rf[3] = d(p[0], 0); rf[4] = d(p[0], 1); rf[5] = d(p[1], 0); rf[6] = d(p[1], 1);
-        rf[7] = d(p[2], 0); rf[8] = d(p[2], 1);
+        w.m = u32x4{x[0], x[1], x[2], 0u};
+        w.p = u32x4{p[0], p[1], p[2], 0u};
+    }
+}
+
+template <class R, class S, bool TH>
+__device__ inline void decode_split(const SplitRaw<TH>& w, R* m, R* rf, R* rg) {
+    using IO = Narrow<S>;
+    constexpr float irs = 1.0f / split_scale<S>::value;
+    auto d = [&](uint32_t x, int hi) __attribute__((always_inline)) { return R(IO::dec(x, hi) * irs); };
+#pragma unroll
+    for (int q = 0; q < 3; ++q) m[q] = R(__uint_as_float(w.m[q]));
+    m[3] = TH ? R(__uint_as_float(w.m[3])) : R(0);
+    rf[3] = d(w.p[0], 0); rf[4] = d(w.p[0], 1); rf[5] = d(w.p[1], 0); rf[6] = d(w.p[1], 1);
+    rf[7] = d(w.p[2], 0); rf[8] = d(w.p[2], 1);
+    if (TH) {
+        rg[1] = d(w.p[3], 0); rg[2] = d(w.p[3], 1);
+        rg[3] = d(w.t[0], 0); rg[4] = d(w.t[0], 1); rg[5] = d(w.t[1], 0); rg[6] = d(w.t[1], 1);
+        rg[7] = d(w.t[2], 0); rg[8] = d(w.t[2], 1);
     }
 }
 
@@ -609,18 +622,29 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // The corrector's own-cell input goes one row ahead only for 16-bit
     // storage, whose prefetched words stay packed two to a register.
     constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2 && !is_split<S>::value;
-    // moment-split storage: PF/PG hold the stored residuals, PM the moments
+    // Moment-split storage keeps the prefetched records packed (PR) and
+    // decodes a row where it is used; the corrector's own-cell record (AR) is
+    // loaded at the top of its row, before the next row's prefetch, and
+    // decoded only for the base, so neither wait drains the other's loads.
     constexpr bool SPLIT = is_split<S>::value;
-    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9], PM[2][4], PHM[2][4];
-    auto load_any = [&](const Buf& b, uint32_t cell, R* m, R* f, R* g) __attribute__((always_inline)) {
-        if constexpr (SPLIT) load_split<R, S, TH>(b, cell, gb, m, f, g);
-        else load_cell<R, S, TH>(b, cell, gb, ro, f, g);
+    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
+    SplitRaw<TH> PR[2], AR[2];
+
+    auto load_any = [&](const Buf& b, uint32_t cell, R* f, R* g) __attribute__((always_inline)) {
+        if constexpr (!SPLIT) load_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
     auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
-        load_any(bsrc, uint32_t(map_row(r)) * nxu + colu, PM[Q], PF[Q], PG[Q]);
-        if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n, or H)
-            load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PHM[Q], PH[Q], PHG[Q]);
+        const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
+        if constexpr (SPLIT) {
+            load_split_raw<S, TH>(bsrc, cell, gb, PR[Q]);
+            if (CORR)  // the corrector's own-cell record (every lane: row and column in range)
+                load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
+        } else {
+            load_any(bsrc, cell, PF[Q], PG[Q]);
+            if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n, or H)
+                load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PH[Q], PHG[Q]);
+        }
     };
     // store the offsets of a cell of a row whose thermal reference is trow
     auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
@@ -639,20 +663,31 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
 
         if (!AHEAD) prefetch(r, Slot<SL>{});
-        R df[9], dg[9];
+        R df[9], dg[9], mm[4];
+        if constexpr (SPLIT) {
+            // While stores are outstanding the compiler waits for all vector
+            // memory operations at the first use of a load, so each row
+            // has one such wait, here, and the next row's records are
+            // requested right after it; the own-cell record stays packed
+            // until the base needs it.
+            decode_split<R, S, TH>(PR[SL & 1], mm, df, dg);
+            __builtin_amdgcn_sched_barrier(0);
+            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+        } else {
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            df[a] = PF[SL & 1][a];
-            if (TH) dg[a] = PG[SL & 1][a];
+            for (int a = 0; a < 9; ++a) {
+                df[a] = PF[SL & 1][a];
+                if (TH) dg[a] = PG[SL & 1][a];
+            }
+            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+            if (CORR && !AHEAD_OWN && owned)  // own-cell input of this row, used after the stage
+                load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PH[SL & 1], PHG[SL & 1]);
         }
-        if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
-        if (CORR && !AHEAD_OWN && owned)  // own-cell input of this row, used after the stage
-            load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PHM[SL & 1], PH[SL & 1], PHG[SL & 1]);
 
         R ph[NSP][9], bs[NSP][9];
         if constexpr (SPLIT) {  // decodes df, dg to offsets in place
-            if (CORR) stage_split<R, TH, false, true>(PM[SL & 1], df, dg, k, Tr, ph, bs);
-            else stage_split<R, TH, true, false>(PM[SL & 1], df, dg, k, Tr, ph, bs);
+            if (CORR) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, ph, bs);
+            else stage_split<R, TH, true, false>(mm, df, dg, k, Tr, ph, bs);
         } else {
             if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
             else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
@@ -687,7 +722,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             // brackets: phi_ghost = s phi, s = (2 rho_S - rho) / rho, i.e.
             // phi - w ref -> s (phi - w ref) + (s - 1) w ref.  Flow only.
             R rho;
-            if constexpr (SPLIT) rho = PM[SL & 1][0] + k.ref_f;
+            if constexpr (SPLIT) rho = mm[0] + k.ref_f;
             else {
                 rho = df[0];
 #pragma unroll
@@ -759,14 +794,16 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             if (CORR && HEUN_H) {
                 // f~n+1 = H + f~*/2 - dt/2 D(phi*): H (offsets) at this cell
                 R hf[9], hg[9];
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    hf[a] = PH[SL & 1][a];
-                    hg[a] = PHG[SL & 1][a];
-                }
                 if constexpr (SPLIT) {
-                    R phh[NSP][9], bsh[NSP][9];
-                    stage_split<R, TH, false, true>(PHM[SL & 1], hf, hg, k, Tr, phh, bsh);
+                    R hm[4], phh[NSP][9], bsh[NSP][9];
+                    decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
+                    stage_split<R, TH, false, true>(hm, hf, hg, k, Tr, phh, bsh);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        hf[a] = PH[SL & 1][a];
+                        hg[a] = PHG[SL & 1][a];
+                    }
                 }
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
@@ -777,13 +814,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
                 R phn[NSP][9], bn[NSP][9];
                 if constexpr (SPLIT) {
-                    R hf[9], hg[9];
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        hf[a] = PH[SL & 1][a];
-                        hg[a] = PHG[SL & 1][a];
-                    }
-                    stage_split<R, TH, true, false>(PHM[SL & 1], hf, hg, k, Tr, phn, bn);
+                    R hm[4], hf[9], hg[9];
+                    decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
+                    stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, phn, bn);
                 } else {
                     stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
                 }
@@ -797,7 +830,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                 for (int s = 0; s < NSP; ++s)
 #pragma unroll
                     for (int a = 0; a < 9; ++a) base[s][a] = bs[s][a];
-                if (A.aux && out_row) {  // Heun predictor: keep H = (f~ + C)/2 for the corrector
+                if (HEUN_H && A.aux && out_row) {  // Heun predictor: keep H = (f~ + C)/2 for the corrector
                     R hf[9], hg[9];
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
@@ -848,9 +881,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     }
 }
 
+// Blocks per CU the register budget is sized for: two waves per SIMD (FP32
+// arithmetic) or one (FP64), whatever the block width.
+template <class R> constexpr int FV_MIN_BLOCKS = (sizeof(R) == 4 ? 8 : 4) * 64 / FV_LANES;
+
 // One simulation: arguments by value.
 template <class R, class S, bool TH, bool CORR>
-__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvArgs<R> A) {
+__global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>) fv_pass(FvArgs<R> A) {
     const int item = xcd_item(blockIdx.x, A.n_items);
     if (item >= A.n_items) return;
     fv_item<R, S, TH, CORR>(A, item);
@@ -863,7 +900,7 @@ __global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1) fv_pass(FvAr
 // same code as in fv_pass, so a simulation's result does not depend on what
 // else shares the launch.
 template <class R, class S, bool TH, bool CORR>
-__global__ void __launch_bounds__(FV_LANES, sizeof(R) == 4 ? 2 : 1)
+__global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
     fv_pass_multi(const FvArgs<R>* args, const int2* items, int n_items, const int64_t* left) {
     const int w = xcd_item(blockIdx.x, n_items);
     if (w >= n_items) return;
