@@ -284,6 +284,15 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells, name, args.storage),
             "kernel": name, "avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_cell": per_cell}
+    if not args.no_variants:
+        # what plain streaming sweeps reach on this device for the kernel's
+        # traffic mix (reads : writes 2 : 1 for the corrector, 1 : 1 for the
+        # predictor), measured after the timed region
+        ceil = lb.stream_probe(512 << 20)
+        mix = ceil["stream_2r1w"] if name.endswith("corrector>") else ceil["copy_1r1w"]
+        roof["stream_ceiling_GBps"] = {k: round(v, 1) for k, v in ceil.items()}
+        roof["frac_of_stream_ceiling"] = round(achieved / mix, 4) if mix > 0 else None
+        log(f"streaming ceiling: {ceil}")
 
     extra = {"storage": args.storage, "state_bytes_per_cell": b, "predictor_avg_ms": round(avg_p * 1e3, 4),
              "corrector_avg_ms": round(avg_c * 1e3, 4),

@@ -262,6 +262,16 @@ int lb_group_remaining(lb_group* group, int64_t* left);
 /* Message of the last failing call on this thread ("" if none). */
 const char* lb_last_error(void);
 
+/* Streaming bandwidth of the current device, a reference ceiling for the
+ * stage kernels' bandwidth (not part of the method).  Plain coalesced sweeps
+ * of 16 bytes per lane over three device buffers of `bytes` each (rounded
+ * down to 16 bytes, at least 16 MiB), allocated and freed by the call and
+ * run on `stream` (hipStream_t or NULL); out[3] receives the best of three
+ * launch shapes in GB/s for: 0 one read + one write per byte (a copy), 1 two
+ * reads + one write, 2 two reads.  Synchronises the stream.  LB_EINVAL for a
+ * NULL out or too small a size, LB_ENOMEM, LB_EDEVICE. */
+int lb_stream_probe(size_t bytes, void* stream, double* out);
+
 /* ======================================================================
  * Three dimensions: D3Q19, the lattice of the paper's own runs ("Boundary
  * conditions", last paragraph; sec. 5).  The same FV schemes (LB_FV_HEUN,

@@ -110,6 +110,7 @@ def lib():
             "lb_set_rebase": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_device_bytes": ([h], ctypes.c_size_t),
             "lb_last_error": ([], ctypes.c_char_p),
+            "lb_stream_probe": ([ctypes.c_size_t, ctypes.c_void_p, _DP], ctypes.c_int),
             "lb_group_create": ([ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(h)], ctypes.c_int),
             "lb_group_destroy": ([h], None),
             "lb_group_add": ([h, h, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -178,6 +179,16 @@ def grid_chebyshev(n, L):
     out = np.empty(n + 1)
     _check(lib().lb_grid_chebyshev(n, L, _dptr(out)))
     return out
+
+
+def stream_probe(bytes_per_buffer=512 << 20, stream=None):
+    """lb_stream_probe: best streaming bandwidth of the device in GB/s, as a
+    dict copy_1r1w / stream_2r1w / read_2r (a reference ceiling for the stage
+    kernels, not part of the method)."""
+    out = np.zeros(3)
+    _check(lib().lb_stream_probe(int(bytes_per_buffer), stream if stream is not None else current_stream(),
+                                 _dptr(out)))
+    return dict(copy_1r1w=float(out[0]), stream_2r1w=float(out[1]), read_2r=float(out[2]))
 
 
 def current_stream():

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblb.so")
-SOURCES = ["fv.hip", "fv3d.hip", "st.hip", "aux.hip", "capi.cpp"]
+SOURCES = ["fv.hip", "fv3d.hip", "st.hip", "aux.hip", "probe.hip", "capi.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -405,6 +405,55 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_err.c_str(); }
 
+int lb_stream_probe(size_t bytes, void* stream, double* out) {
+    if (!out) return fail(LB_EINVAL, "lb_stream_probe: out is NULL");
+    const size_t n = bytes / 16;
+    if (n < (size_t(16) << 20) / 16) return fail(LB_EINVAL, "lb_stream_probe: need at least 16 MiB per buffer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *a = nullptr, *b = nullptr, *d = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (d) (void)hipFree(d);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e = hipMalloc(&a, n * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, n * 16);
+    if (e == hipSuccess) e = hipMalloc(&d, n * 16);
+    if (e != hipSuccess) {
+        release();
+        return fail(LB_ENOMEM, "lb_stream_probe: %s", hipGetErrorString(e));
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, n * 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(b, 0, n * 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d, 0, n * 16, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // best of three launch shapes (4, 8 and 16 blocks of 256 lanes per CU)
+    const int grids[] = {1024, 2048, 4096};
+    const double moved[] = {2.0, 3.0, 2.0};  // buffers of n * 16 bytes moved per sweep
+    const int reps = 10;
+    for (int kind = 0; kind < 3 && e == hipSuccess; ++kind) {
+        double best = 0.0;
+        for (int g : grids) {
+            for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_stream(kind, g, a, b, d, n, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream(kind, g, a, b, d, n, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms > 0.f) best = std::max(best, moved[kind] * double(n) * 16.0 * reps / (double(ms) * 1e6));
+        }
+        out[kind] = best;
+    }
+    release();
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_stream_probe: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
 int lb_grid_uniform(int64_t n, double L, double* faces) {
     if (n < 1 || !faces || !(L > 0)) return fail(LB_EINVAL, "lb_grid_uniform: bad arguments");
     for (int64_t i = 0; i <= n; ++i) faces[i] = L * double(i) / double(n);

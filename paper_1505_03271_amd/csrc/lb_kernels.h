@@ -165,4 +165,9 @@ struct Diag3Args {
 };
 hipError_t launch_diag3(int storage, const Diag3Args& d, double* partial, double* out, hipStream_t s);
 
+// Streaming-bandwidth reference sweeps (probe.hip): kind 0 copy, 1 two reads
+// and a write, 2 two reads; n elements of 16 bytes per buffer, 256 lanes per
+// block.
+hipError_t launch_stream(int kind, int grid, const void* a, const void* b, void* d, size_t n, hipStream_t s);
+
 }  // namespace lbk

@@ -110,3 +110,13 @@ def test_state_size_limit(storage, n, ok):
         with pytest.raises(lb.LBError) as e:
             lb.Sim(n, n, scheme="heun", storage=storage, thermal=True, tau=0.5, tau_g=0.5, dt=1.0)
         assert e.value.code == 1 and "4 GiB" in str(e.value)
+
+
+def test_stream_probe_rejects_bad_arguments_before_touching_the_device():
+    """lb_stream_probe validates its arguments first: a NULL output or a
+    buffer below 16 MiB is LB_EINVAL (no HIP call is made)."""
+    L = lb.lib()
+    out = (ctypes.c_double * 3)()
+    assert L.lb_stream_probe(1 << 20, None, out) == 1
+    assert "16 MiB" in L.lb_last_error().decode()
+    assert L.lb_stream_probe(64 << 20, None, None) == 1

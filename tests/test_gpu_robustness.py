@@ -166,3 +166,14 @@ def test_explicit_euler_beyond_its_limit_is_reported():
     with pytest.raises(lb.LBError) as e:
         sim.step(1)
     assert e.value.code == 5
+
+
+def test_stream_probe_reports_plausible_bandwidths():
+    """The streaming reference sweeps return finite rates below the HBM peak
+    (8 TB/s), with reads alone at least as fast as a copy."""
+    say("stream probe")
+    c = lb.stream_probe(512 << 20)   # three buffers well beyond the 256 MB last-level cache
+    say(f"  {c}")
+    for v in c.values():
+        assert 100.0 < v < 8000.0
+    assert c["read_2r"] >= 0.9 * c["copy_1r1w"]
