@@ -138,19 +138,48 @@ def run_fv3d(lb, torch, n, steps, warmup, storage="f32"):
 
 
 def cpu_baseline(cfg, steps=2):
-    """The FP64 oracle, as is, on `steps` steps of the full workload."""
+    """The FP64 oracle, as is: `steps` FV steps of the full workload on all
+    host threads (the reported value); beside it, the oracle's ST step on the
+    same grid size, and both on one thread on a 1024 x 1024 sample, so that
+    the oracle's FV / ST cost per step can be set beside the paper's 8-10x
+    (sec. 4).  About 10-20 s of CPU time."""
+    import numpy as np
     import oracle
     n = cfg["nx"]
-    c = oracle.Case(n, n, scheme="heun", thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"],
-                    tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"], T_bottom=cfg["T_bottom"],
-                    T_top=cfg["T_top"], xf=cfg["xf"], yf=cfg["yf"])
-    c.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"])
+    th = dict(thermal=True, wall_y=True, tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"],
+              T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
+
+    def timed(m, scheme, k):
+        if scheme == "st":
+            c = oracle.Case(m, m, scheme="st", dt=1.0, **th)
+        else:
+            xf = cfg["xf"] if m == n else np.linspace(0.0, cfg["xf"][-1], m + 1)
+            yf = cfg["yf"] if m == n else np.linspace(0.0, cfg["yf"][-1], m + 1)
+            c = oracle.Case(m, m, scheme="heun", dt=cfg["dt"], xf=xf, yf=yf, **th)
+        sl = slice(None) if m == n else (slice(0, m), slice(0, m))
+        c.init(cfg["rho"][sl], cfg["ux"][sl], cfg["uy"][sl], cfg["T"][sl])
+        t0 = time.perf_counter()
+        c.step(k)
+        return m * m * k / (time.perf_counter() - t0) / 1e6
+
+    cores = oracle.threads()
     t0 = time.perf_counter()
-    c.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=n * n * steps / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+    fv = timed(n, "heun", steps)
+    st = timed(n, "st", 4 * steps)
+    oracle.set_threads(1)
+    try:
+        fv1 = timed(1024, "heun", 1)
+        st1 = timed(1024, "st", 4)
+    finally:
+        oracle.set_threads(cores)
+    total = time.perf_counter() - t0
+    return dict(value=fv, unit="MLUPS", cores=cores, kind="oracle",
                 sample=f"{steps} FV semi-implicit+Heun steps of the full {n}x{n} thermal workload, FP64, "
-                       f"{oracle.threads()} OpenMP threads, {dt:.1f} s")
+                       f"{cores} OpenMP threads; beside it the ST step ({4 * steps} steps, same size) and both on "
+                       f"1 thread on 1024x1024 ({total:.1f} s in all)",
+                st_mlups=round(st, 3), fv_over_st_cost_per_step=round(st / fv, 2),
+                fv_1thread_mlups=round(fv1, 3), st_1thread_mlups=round(st1, 3),
+                fv_over_st_cost_per_step_1thread=round(st1 / fv1, 2))
 
 
 def accuracy_report(lb, torch, storages=ACC_STORAGES, chunk=10000):

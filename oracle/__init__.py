@@ -52,6 +52,8 @@ def lib():
         pp = ctypes.POINTER(_Params)
         L.ob_abi_version.restype = ctypes.c_int
         L.ob_threads.restype = ctypes.c_int
+        L.ob_set_threads.argtypes = [ctypes.c_int]
+        L.ob_set_threads.restype = None
         L.ob_grid_uniform.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.ob_grid_tanh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         L.ob_grid_sinh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
@@ -77,6 +79,11 @@ def _ptr(a):
 
 def threads():
     return lib().ob_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (timing; results are the same)."""
+    lib().ob_set_threads(int(n))
 
 
 def grid_uniform(n, L):

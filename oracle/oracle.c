@@ -76,6 +76,17 @@ int ob_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (timing only; results do not
+ * depend on it: every loop writes disjoint rows). */
+void ob_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grids (sec. 3, eq:grids).  faces[0..n]; cell centres are face midpoints.  */
 /* ------------------------------------------------------------------------ */
