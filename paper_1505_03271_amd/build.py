@@ -12,6 +12,9 @@ SOURCES = ["fv.hip", "fv3d.hip", "st.hip", "aux.hip", "probe.hip", "capi.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-add fusion only inside one expression (the C rule), so that
+         # a value's rounding does not depend on the code around it
+         "-ffp-contract=on",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wno-unused-result"]
 
 

@@ -143,7 +143,6 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     void* A = nullptr;  // current state
     void* B = nullptr;  // predictor / next state
-    void* H = nullptr;  // (f~n + C)/2 between the Heun predictor and corrector
     void* metric = nullptr;   // flux stencils: x pass0, y pass0, x pass1, y pass1 ([n][8] each)
     double* dxy = nullptr;    // dx[nx], dy[ny] in double
     double* partial = nullptr;
@@ -174,7 +173,6 @@ int check_sim(const lb_sim* s) {
 void release(lb_sim* s) {
     if (s->A) (void)hipFree(s->A);
     if (s->B) (void)hipFree(s->B);
-    if (s->H) (void)hipFree(s->H);
     if (s->metric) (void)hipFree(s->metric);
     if (s->dxy) (void)hipFree(s->dxy);
     if (s->partial) (void)hipFree(s->partial);
@@ -525,7 +523,6 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->chunk_h = 0;  // chosen at the first FV launch from the occupancy
         hipError_t e;
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
-            (p->scheme == LB_FV_HEUN && fv_heun_h() && (e = hipMalloc(&s->H, s->state_bytes)) != hipSuccess) ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess ||
             (p->thermal && p->storage != LB_F64 && (e = hipMalloc(&s->tref, sizeof(float) * p->ny)) != hipSuccess)) {
@@ -640,13 +637,8 @@ int lb_step(lb_sim* s, int64_t nsteps) {
         int rc;
         switch (s->p.scheme) {
             case LB_FV_HEUN:
-                if (fv_heun_h()) {
-                    if ((rc = fv_launch(s, s->A, s->B, s->H, false))) return rc;  // f~* -> B, H
-                    if ((rc = fv_launch(s, s->B, s->A, s->H, true))) return rc;   // f~n+1 -> A
-                } else {
-                    if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
-                    if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
-                }
+                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
+                if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
                 break;
             case LB_FV_SEMI:
             case LB_FV_EULER:
@@ -838,7 +830,7 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return (s->H ? 3 : 2) * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return 2 * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
 }
 

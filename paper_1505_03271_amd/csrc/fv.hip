@@ -62,14 +62,6 @@ __device__ constexpr int dpop(int p) { return p == 0 ? 4 : p == 1 ? 7 : 8; }
 
 template <int N> struct Slot { static constexpr int value = N; };
 
-// Heun corrector input: with HEUN_H the predictor also stores
-// H = (f~n + C(f~n))/2 and the corrector reads it (6 Q b bytes per cell-step);
-// without, the corrector reads f~n at its cell and recomputes C (5 Q b).
-#ifndef LB_HEUN_H
-#define LB_HEUN_H 0
-#endif
-constexpr bool HEUN_H = LB_HEUN_H;
-
 // ---- raw buffer access: 32-bit lane offset, scalar per-plane offset ------
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
@@ -379,6 +371,8 @@ __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, 
     const R ua3 = R(3) * (ux * k.ax + uy * ay);
     put(0, 0, wt<R>(0) * (m[0] + rho * (k.hdt * ua3 - uu)));
     if (TH) put(1, 0, wt<R>(0) * (m[3] - T * uu));
+    const R wr[2] = {wt<R>(1) * rho, wt<R>(5) * rho}, wp[2] = {wt<R>(1) * m[0], wt<R>(5) * m[0]};
+    const R wT[2] = {wt<R>(1) * T, wt<R>(5) * T}, wTp[2] = {wt<R>(1) * m[3], wt<R>(5) * m[3]};
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int a = pa(p), b = pb(p);
@@ -391,12 +385,12 @@ __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, 
         const R O = R(3) * cu;
         const R Qe = Em - k.hdt * ((R(9) * cu) * ca - ua3);
         const R Qo = O - k.hdt * (R(3) * ca);
-        const R w = wt<R>(a);
-        put(0, a, w * (m[0] + rho * (Qe + Qo)));
-        put(0, b, w * (m[0] + rho * (Qe - Qo)));
+        const int c = p < 2 ? 0 : 1;
+        put(0, a, wp[c] + wr[c] * (Qe + Qo));
+        put(0, b, wp[c] + wr[c] * (Qe - Qo));
         if (TH) {
-            put(1, a, w * (m[3] + T * (Em + O)));
-            put(1, b, w * (m[3] + T * (Em - O)));
+            put(1, a, wTp[c] + wT[c] * (Em + O));
+            put(1, b, wTp[c] + wT[c] * (Em - O));
         }
     }
 }
@@ -425,6 +419,9 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
     const R ua3 = R(3) * (ux * k.ax + uy * ay);
     const R rp = m[0], Tp = TH ? m[3] : R(0);
     constexpr R w0 = wt<R>(0);
+    // w rho, w rho', w T, w T' of the axis (1/9) and diagonal (1/36) classes
+    const R wr[2] = {wt<R>(1) * rho, wt<R>(5) * rho}, wp[2] = {wt<R>(1) * rp, wt<R>(5) * rp};
+    const R wT[2] = {wt<R>(1) * T, wt<R>(5) * T}, wTp[2] = {wt<R>(1) * Tp, wt<R>(5) * Tp};
     // rest population: no flux
     if (BASE) {
         bs[0][0] = w0 * (rp - rho * (uu + k.cB * ua3)) + k.omkc * df[0];
@@ -437,7 +434,7 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int a = pa(p), b = pb(p);
-        const R w = p < 2 ? wt<R>(1) : wt<R>(5);
+        const int c = p < 2 ? 0 : 1;
         R cu, ca;
         if (p == 0) { cu = ux; ca = k.ax; }
         else if (p == 1) { cu = uy; ca = ay; }
@@ -449,19 +446,19 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
         const R Fo = R(3) * ca;
         const R ra = df[a], rb = df[b];
         const R PE = Em + k.cP * Fe, PO = O + k.cP * Fo;
-        ph[0][a] = w * (rp + rho * (PE + PO)) + k.omk1 * ra;
-        ph[0][b] = w * (rp + rho * (PE - PO)) + k.omk1 * rb;
+        ph[0][a] = (wp[c] + wr[c] * (PE + PO)) + k.omk1 * ra;
+        ph[0][b] = (wp[c] + wr[c] * (PE - PO)) + k.omk1 * rb;
         R Gp = 0, Gm = 0;
         if (TH) {
-            Gp = w * (Tp + T * (Em + O));
-            Gm = w * (Tp + T * (Em - O));
+            Gp = wTp[c] + wT[c] * (Em + O);
+            Gm = wTp[c] + wT[c] * (Em - O);
             ph[NSP - 1][a] = Gp + k.omk1g * dg[a];
             ph[NSP - 1][b] = Gm + k.omk1g * dg[b];
         }
         if (BASE) {
             const R BE = Em + k.cB * Fe, BO = O + k.cB * Fo;
-            bs[0][a] = w * (rp + rho * (BE + BO)) + k.omkc * ra;
-            bs[0][b] = w * (rp + rho * (BE - BO)) + k.omkc * rb;
+            bs[0][a] = (wp[c] + wr[c] * (BE + BO)) + k.omkc * ra;
+            bs[0][b] = (wp[c] + wr[c] * (BE - BO)) + k.omkc * rb;
             if (TH) {
                 bs[NSP - 1][a] = Gp + k.omkcg * dg[a];
                 bs[NSP - 1][b] = Gm + k.omkcg * dg[b];
@@ -469,8 +466,8 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
         }
         if (NEED_D) {
             const R QE = Em - k.hdt * Fe, QO = O - k.hdt * Fo;
-            df[a] = w * (rp + rho * (QE + QO)) + ra;
-            df[b] = w * (rp + rho * (QE - QO)) + rb;
+            df[a] = (wp[c] + wr[c] * (QE + QO)) + ra;
+            df[b] = (wp[c] + wr[c] * (QE - QO)) + rb;
             if (TH) {
                 dg[a] = Gp + dg[a];
                 dg[b] = Gm + dg[b];
@@ -622,10 +619,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // The corrector's own-cell input goes one row ahead only for 16-bit
     // storage, whose prefetched words stay packed two to a register.
     constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2 && !is_split<S>::value;
-    // Moment-split storage keeps the prefetched records packed (PR) and
-    // decodes a row where it is used; the corrector's own-cell record (AR) is
-    // loaded at the top of its row, before the next row's prefetch, and
-    // decoded only for the base, so neither wait drains the other's loads.
+    // Moment-split storage keeps the prefetched records packed (PR, AR) and
+    // decodes a row where it is used: the stencil record at the top of its
+    // row, the corrector's own-cell record only for the base.
     constexpr bool SPLIT = is_split<S>::value;
     R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
     SplitRaw<TH> PR[2], AR[2];
@@ -638,13 +634,19 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
         if constexpr (SPLIT) {
             load_split_raw<S, TH>(bsrc, cell, gb, PR[Q]);
-            if (CORR)  // the corrector's own-cell record (every lane: row and column in range)
-                load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
         } else {
             load_any(bsrc, cell, PF[Q], PG[Q]);
-            if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n, or H)
+            if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n)
                 load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PH[Q], PHG[Q]);
         }
+    };
+    // The corrector's own-cell record of the next row is requested after the
+    // row's barrier, away from the burst of the next row's stencil loads at
+    // the top of the row (every lane: row and column are in range).
+    auto prefetch_own = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int Q = decltype(slot_tag)::value & 1;
+        if constexpr (SPLIT)
+            if (CORR) load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
     };
     // store the offsets of a cell of a row whose thermal reference is trow
     auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
@@ -666,10 +668,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         R df[9], dg[9], mm[4];
         if constexpr (SPLIT) {
             // While stores are outstanding the compiler waits for all vector
-            // memory operations at the first use of a load, so each row
-            // has one such wait, here, and the next row's records are
-            // requested right after it; the own-cell record stays packed
-            // until the base needs it.
+            // memory operations at the first use of a load, so the decode of
+            // this row's stencil record comes first and the next row's is
+            // requested right after it.
             decode_split<R, S, TH>(PR[SL & 1], mm, df, dg);
             __builtin_amdgcn_sched_barrier(0);
             if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
@@ -787,30 +788,14 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 #pragma unroll
             for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
         lanes_sync();
+        if (SPLIT && CORR && AHEAD) {
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch_own(r + 1, Slot<SL + 1>{});
+            __builtin_amdgcn_sched_barrier(0);
+        }
         if (owned) {
-            const bool out_row = r >= y0 && r < y1;
-            const uint32_t ocell = uint32_t(min(r, A.ny - 1)) * nxu + colu;
             R base[NSP][9];
-            if (CORR && HEUN_H) {
-                // f~n+1 = H + f~*/2 - dt/2 D(phi*): H (offsets) at this cell
-                R hf[9], hg[9];
-                if constexpr (SPLIT) {
-                    R hm[4], phh[NSP][9], bsh[NSP][9];
-                    decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
-                    stage_split<R, TH, false, true>(hm, hf, hg, k, Tr, phh, bsh);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        hf[a] = PH[SL & 1][a];
-                        hg[a] = PHG[SL & 1][a];
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    base[0][a] = hf[a] + R(0.5) * df[a];
-                    if (TH) base[NSP - 1][a] = hg[a] + R(0.5) * dg[a];
-                }
-            } else if (CORR) {
+            if (CORR) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
                 R phn[NSP][9], bn[NSP][9];
                 if constexpr (SPLIT) {
@@ -830,15 +815,6 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                 for (int s = 0; s < NSP; ++s)
 #pragma unroll
                     for (int a = 0; a < 9; ++a) base[s][a] = bs[s][a];
-                if (HEUN_H && A.aux && out_row) {  // Heun predictor: keep H = (f~ + C)/2 for the corrector
-                    R hf[9], hg[9];
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        hf[a] = R(0.5) * bs[0][a];
-                        if (TH) hg[a] = R(0.5) * bs[NSP - 1][a];
-                    }
-                    store_any(baux, ocell, hf, hg, Tr);
-                }
             }
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
@@ -873,6 +849,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // past y1+1 (their results are never stored).  A chunk of height 4k
     // needs exactly k+1 trips.
     if (AHEAD) prefetch(y0 - 2, Slot<0>{});
+    if (AHEAD) prefetch_own(y0 - 2, Slot<0>{});
     for (int r = y0 - 2; r <= y1 + 1; r += 4) {
         row_step(r, Slot<0>{});
         row_step(r + 1, Slot<1>{});
@@ -993,8 +970,6 @@ static int resident_typed(bool thermal, bool corrector) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return per_cu * cus;
 }
-
-bool fv_heun_h() { return HEUN_H; }
 
 int fv_resident_blocks(int storage, bool thermal, bool corrector) {
     switch (storage) {

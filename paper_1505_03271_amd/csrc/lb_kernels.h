@@ -79,7 +79,6 @@ hipError_t launch_tick(int64_t* left, int n, hipStream_t s);
 size_t fv_args_bytes(int storage);
 
 // True when the Heun predictor stores H = (f~n + C)/2 for the corrector.
-bool fv_heun_h();
 // Largest number of FV blocks of one launch that are resident at once.
 int fv_resident_blocks(int storage, bool thermal, bool corrector);
 hipError_t launch_st(int storage, bool thermal, bool stream_only, const StArgs& a, hipStream_t s);
