@@ -196,9 +196,12 @@ int lb_diagnostics(lb_sim* sim, double* out);
 int lb_get_populations(lb_sim* sim, double* f, double* g);
 int lb_set_populations(lb_sim* sim, const double* f, const double* g);
 
-/* Raw state (checkpoint): stored words of f then g plus nothing else, exactly
- * lb_state_bytes() bytes; restoring it and stepping is bit-identical to not
- * having stopped. */
+/* Raw state (checkpoint), exactly lb_state_bytes() bytes: the stored words
+ * of f then g, followed by the per-row references they are encoded with
+ * (thermal non-F64 storage: T_ref[ny] floats; thermal split storage: then
+ * the heat-flux reference q[ny] floats).  Restoring it and stepping is
+ * bit-identical to not having stopped (the rebase countdown of
+ * lb_set_rebase is not part of it). */
 size_t lb_state_bytes(const lb_sim* sim);
 int lb_get_state(lb_sim* sim, void* host, size_t bytes);
 int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
@@ -213,12 +216,16 @@ int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
 
 /* Thermal reference rows (non-F64 storage of a thermal run): the stored g
  * are offsets from w_a T_ref(row), T_ref(row) starting as the row means of
- * the initial temperature (lb_init).  lb_rebase sets T_ref(row) to the
- * current row means and re-encodes the stored g (one rounding); with
- * lb_set_rebase(every > 0) lb_step does this after every `every` steps
- * (0, the default, never).  Narrow formats then resolve temperature
- * differences relative to the local mean profile, which keeps wall heat
- * fluxes accurate.  No-ops for FP64 storage or isothermal runs. */
+ * the initial temperature (lb_init).  Split storage (LB_BF16S, LB_F16S) has
+ * a second row value, the heat-flux reference q(row), 0 at lb_init: the
+ * stored g residual of population a is r_a - w_a c_ay q(row), so that the
+ * 16 bits resolve departures from the row's mean vertical heat flux (the
+ * conductive flux of a Rayleigh-Benard cell would otherwise set their
+ * rounding step).  lb_rebase sets T_ref(row) to the current row means and
+ * q(row) to 3 x the row mean of sum_a c_ay r_a, and re-encodes the stored g
+ * (one rounding); with lb_set_rebase(every > 0) lb_step does this after
+ * every `every` steps (0, the default, never; group steps never do).
+ * No-ops for FP64 storage or isothermal runs. */
 int lb_rebase(lb_sim* sim);
 int lb_set_rebase(lb_sim* sim, int64_t every);
 

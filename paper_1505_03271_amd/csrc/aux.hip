@@ -66,6 +66,9 @@ __device__ inline void split_eq_d(const AuxArgs& A, const double* m, double Tr, 
 
 __device__ inline SplitLayout split_layout(const AuxArgs& A) { return SplitLayout{A.thermal != 0, A.plane}; }
 __device__ inline double row_ref(const AuxArgs& A, int64_t c) { return A.tref ? double(A.tref[c / A.nx]) : A.ref_g; }
+// heat-flux reference of the row of cell c: the stored g residual of
+// population a is r_a - w_a c_ay q
+__device__ inline double row_qref(const AuxArgs& A, int64_t c) { return A.qref ? double(A.qref[c / A.nx]) : 0.0; }
 
 template <class S> __device__ inline void split_moments(const AuxArgs& A, int64_t c, double* m) {
     const SplitLayout L = split_layout(A);
@@ -85,6 +88,8 @@ template <class S> __device__ inline void split_decode_d(const AuxArgs& A, int64
             const int k = split_slot(s, a);
             r[s][a] = (k >= 0 && (s == 0 || A.thermal)) ? split_get<S>(st, L.res(k, c)) : 0.0;
         }
+    const double q = row_qref(A, c);
+    for (int a = 1; a < 9; ++a) r[1][a] += wt<double>(a) * cy(a) * q;  // zero mass: slot 0 is unchanged
     r[0][1] = r[0][3] - r[0][5] + r[0][6] + r[0][7] - r[0][8];
     r[0][2] = r[0][4] - r[0][5] - r[0][6] + r[0][7] + r[0][8];
     for (int s = 0; s < 2; ++s) {
@@ -116,10 +121,11 @@ template <class S> __device__ inline void split_encode_d(const AuxArgs& A, int64
     for (int q = 0; q < 4; ++q) m[q] = double(float(m[q]));  // the stored moments
     for (int q = 0; q < (A.thermal ? 4 : 3); ++q) *reinterpret_cast<float*>(st + L.mom(q, c)) = float(m[q]);
     split_eq_d(A, m, Tr, e);
+    const double q = row_qref(A, c);
     for (int s = 0; s < (A.thermal ? 2 : 1); ++s)
         for (int a = 0; a < 9; ++a) {
             const int k = split_slot(s, a);
-            if (k >= 0) split_put<S>(st, L.res(k, c), d[s][a] - e[s][a]);
+            if (k >= 0) split_put<S>(st, L.res(k, c), d[s][a] - e[s][a] - (s ? wt<double>(a) * cy(a) * q : 0.0));
         }
 }
 
@@ -240,31 +246,63 @@ __global__ void set_pops_kernel(AuxArgs A, const double* in) {
 // ---- per-row thermal reference update ----------------------------------
 // One block per row: the row mean of T becomes the row's new reference and
 // every stored g of the row is re-encoded, d_new = d_old + w_a (old - new).
+// Split storage also renews the heat-flux reference q: 3 times the row mean
+// of sum_a c_ay r_a (sum_a w_a c_ay^2 = 1/3), and each stored residual of a
+// population along y moves by w_a c_ay (q_old - q_new) (one rounding).
 template <class S>
 __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
-    __shared__ double red[4];
-    __shared__ float newref;
+    __shared__ double red[2][4];
+    __shared__ float newref, newq;
     const int j = blockIdx.x;
     S* st = static_cast<S*>(A.state);
-    double sum = 0.0;
+    constexpr bool SPLIT = is_split<S>::value;
+    const bool with_q = SPLIT && A.qref;
+    const float oldq = with_q ? A.qref[j] : 0.0f;
+    double sum = 0.0, flux = 0.0;
     for (int i = threadIdx.x; i < A.nx; i += 256) {
         const int64_t c = int64_t(j) * A.nx + i;
-        if constexpr (is_split<S>::value) sum += cell_macro<S>(A, c).T;
-        else
+        if constexpr (SPLIT) {
+            sum += cell_macro<S>(A, c).T;
+            if (with_q) {
+                const SplitLayout L = split_layout(A);
+                const char* sb = static_cast<const char*>(A.state);
+                for (int a = 1; a < 9; ++a)
+                    if (cy(a)) flux += cy(a) * split_get<S>(sb, L.res(split_slot(1, a), c));
+            }
+        } else {
             for (int a = 0; a < 9; ++a) sum += get_pop(A, st, 1, a, c, A.ref_g);
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_down(sum, o, 64);
+        flux += __shfl_down(flux, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sum;
+        red[1][threadIdx.x >> 6] = flux;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) newref = float((red[0] + red[1] + red[2] + red[3]) / A.nx);
+    if (threadIdx.x == 0) {
+        newref = float((red[0][0] + red[0][1] + red[0][2] + red[0][3]) / A.nx);
+        // stored residuals are r - w c_y q_old: their mean flux is mean(sum c_y r) - q_old / 3
+        newq = with_q ? float(3.0 * (red[1][0] + red[1][1] + red[1][2] + red[1][3]) / A.nx + double(oldq)) : 0.0f;
+    }
     __syncthreads();
     const float oldref = A.tref[j];
-    const float nr = newref;
+    const float nr = newref, nq = newq;
     for (int i = threadIdx.x; i < A.nx; i += 256) {
         const int64_t c = int64_t(j) * A.nx + i;
-        if constexpr (is_split<S>::value) {  // only the moment T - Tr changes
-            float* m3 = reinterpret_cast<float*>(static_cast<char*>(A.state) + split_layout(A).mom(3, c));
+        if constexpr (SPLIT) {  // the moment T - Tr, and the residuals along y
+            const SplitLayout L = split_layout(A);
+            char* sb = static_cast<char*>(A.state);
+            float* m3 = reinterpret_cast<float*>(sb + L.mom(3, c));
             *m3 = float(double(*m3) + (double(oldref) - double(nr)));
+            if (with_q)
+                for (int a = 1; a < 9; ++a)
+                    if (cy(a)) {
+                        const int64_t off = L.res(split_slot(1, a), c);
+                        split_put<S>(sb, off, split_get<S>(sb, off) + wt<double>(a) * cy(a) * (double(oldq) - double(nq)));
+                    }
         } else {
             const int nsp = 2;
             for (int a = 0; a < 9; ++a) {
@@ -275,7 +313,10 @@ __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) const_cast<float*>(A.tref)[j] = nr;
+    if (threadIdx.x == 0) {
+        const_cast<float*>(A.tref)[j] = nr;
+        if (with_q) const_cast<float*>(A.qref)[j] = nq;
+    }
 }
 
 template <class S>

@@ -148,6 +148,7 @@ struct lb_sim {
     double* partial = nullptr;
     double* dout = nullptr;
     float* tref = nullptr;    // per-row thermal reference of the stored g (thermal, non-F64 storage)
+    float* qref = nullptr;    // per-row heat-flux reference of the g residuals (thermal, split storage)
     int64_t rebase_every = 0, since_rebase = 0;
     size_t metric_bytes = 0;
     bool has_grid = false, has_init = false, unstable = false;
@@ -178,6 +179,7 @@ void release(lb_sim* s) {
     if (s->partial) (void)hipFree(s->partial);
     if (s->dout) (void)hipFree(s->dout);
     if (s->tref) (void)hipFree(s->tref);
+    if (s->qref) (void)hipFree(s->qref);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     s->events.clear();
 }
@@ -201,6 +203,7 @@ AuxArgs aux_args(const lb_sim* s) {
     a.dy = s->dxy + s->p.nx;
     a.grouped = s->p.scheme != LB_ST;
     a.tref = s->tref;
+    a.qref = s->qref;
     return a;
 }
 
@@ -261,6 +264,7 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     a.rho_x0 = R(s->p.rho_x0);
     a.rho_x1 = R(s->p.rho_x1);
     a.tref = reinterpret_cast<const R*>(s->tref);  // float rows for FP32 arithmetic, NULL for FP64
+    a.qref = reinterpret_cast<const R*>(s->qref);  // split storage only
     return a;
 }
 
@@ -525,7 +529,8 @@ int lb_create(const lb_params* p, lb_sim** out) {
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess ||
-            (p->thermal && p->storage != LB_F64 && (e = hipMalloc(&s->tref, sizeof(float) * p->ny)) != hipSuccess)) {
+            (p->thermal && p->storage != LB_F64 && (e = hipMalloc(&s->tref, sizeof(float) * p->ny)) != hipSuccess) ||
+            (p->thermal && is_split_storage(p->storage) && (e = hipMalloc(&s->qref, sizeof(float) * p->ny)) != hipSuccess)) {
             release(s);
             delete s;
             return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "lb_create: device allocation failed: %s",
@@ -613,6 +618,11 @@ int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, co
         }
         HIP_TRY(hipMemcpy(s->tref, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice));
     }
+    if (s->qref) {
+        // the equilibrium start has no heat flux in its residuals
+        std::vector<float> z(s->p.ny, 0.0f);
+        HIP_TRY(hipMemcpy(s->qref, z.data(), sizeof(float) * z.size(), hipMemcpyHostToDevice));
+    }
     double *d[4] = {nullptr, nullptr, nullptr, nullptr};
     const double* h[4] = {rho, ux, uy, s->p.thermal ? T : rho};
     int rc = LB_OK;
@@ -648,16 +658,14 @@ int lb_step(lb_sim* s, int64_t nsteps) {
             default:
                 if ((rc = st_launch(s))) return rc;
         }
-    }
-    if (nsteps > 0) {
-        if (int rc = record_event(s, -1)) return rc;
-        s->since_rebase += nsteps;
-        if (s->tref && s->rebase_every > 0 && s->since_rebase >= s->rebase_every) {
+        if (s->tref && s->rebase_every > 0 && ++s->since_rebase >= s->rebase_every) {
             hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
             s->since_rebase = 0;
         }
     }
+    if (nsteps > 0)
+        if (int rc = record_event(s, -1)) return rc;
     return LB_OK;
 }
 
@@ -787,22 +795,40 @@ int lb_set_populations(lb_sim* s, const double* f, const double* g) {
     return LB_OK;
 }
 
-size_t lb_state_bytes(const lb_sim* s) { return s ? s->state_bytes : 0; }
+// The checkpoint blob: the population state, then the per-row references
+// (thermal, T_ref; split, the heat-flux reference) the state is encoded with.
+size_t ref_bytes(const lb_sim* s) {
+    return (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0);
+}
+
+size_t lb_state_bytes(const lb_sim* s) { return s ? s->state_bytes + ref_bytes(s) : 0; }
 
 int lb_get_state(lb_sim* s, void* host, size_t bytes) {
     if (int rc = check_sim(s)) return rc;
-    if (!host || bytes != s->state_bytes) return fail(LB_EINVAL, "lb_get_state: need %zu bytes", s->state_bytes);
+    const size_t need = s->state_bytes + ref_bytes(s);
+    if (!host || bytes != need) return fail(LB_EINVAL, "lb_get_state: need %zu bytes", need);
     if (!s->has_init) return fail(LB_ESTATE, "lb_get_state: no state");
-    HIP_TRY(hipMemcpyAsync(host, s->A, bytes, hipMemcpyDeviceToHost, s->stream));
+    char* h = static_cast<char*>(host);
+    const size_t row = sizeof(float) * size_t(s->p.ny);
+    HIP_TRY(hipMemcpyAsync(h, s->A, s->state_bytes, hipMemcpyDeviceToHost, s->stream));
+    h += s->state_bytes;
+    if (s->tref) { HIP_TRY(hipMemcpyAsync(h, s->tref, row, hipMemcpyDeviceToHost, s->stream)); h += row; }
+    if (s->qref) HIP_TRY(hipMemcpyAsync(h, s->qref, row, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return LB_OK;
 }
 
 int lb_set_state(lb_sim* s, const void* host, size_t bytes) {
     if (int rc = check_sim(s)) return rc;
-    if (!host || bytes != s->state_bytes) return fail(LB_EINVAL, "lb_set_state: need %zu bytes", s->state_bytes);
+    const size_t need = s->state_bytes + ref_bytes(s);
+    if (!host || bytes != need) return fail(LB_EINVAL, "lb_set_state: need %zu bytes", need);
     if (!s->has_grid) return fail(LB_ESTATE, "lb_set_state: call lb_set_grid first");
-    HIP_TRY(hipMemcpyAsync(s->A, host, bytes, hipMemcpyHostToDevice, s->stream));
+    const char* h = static_cast<const char*>(host);
+    const size_t row = sizeof(float) * size_t(s->p.ny);
+    HIP_TRY(hipMemcpyAsync(s->A, h, s->state_bytes, hipMemcpyHostToDevice, s->stream));
+    h += s->state_bytes;
+    if (s->tref) { HIP_TRY(hipMemcpyAsync(s->tref, h, row, hipMemcpyHostToDevice, s->stream)); h += row; }
+    if (s->qref) HIP_TRY(hipMemcpyAsync(s->qref, h, row, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->has_init = true;
     s->unstable = false;
@@ -830,7 +856,7 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return 2 * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return 2 * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
 }
 

@@ -366,13 +366,14 @@ __device__ inline void split_macro(const R* m, const StageK<R>& k, const R Tr, R
 // its own resolution.
 template <class R, bool TH, class Fn>
 __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, const R uy, const R ay,
-                                const StageK<R>& k, Fn&& put) {
+                                const StageK<R>& k, const R q, Fn&& put) {
     const R uu = R(1.5) * (ux * ux + uy * uy);
     const R ua3 = R(3) * (ux * k.ax + uy * ay);
     put(0, 0, wt<R>(0) * (m[0] + rho * (k.hdt * ua3 - uu)));
     if (TH) put(1, 0, wt<R>(0) * (m[3] - T * uu));
     const R wr[2] = {wt<R>(1) * rho, wt<R>(5) * rho}, wp[2] = {wt<R>(1) * m[0], wt<R>(5) * m[0]};
     const R wT[2] = {wt<R>(1) * T, wt<R>(5) * T}, wTp[2] = {wt<R>(1) * m[3], wt<R>(5) * m[3]};
+    const R wq[2] = {wt<R>(1) * q, wt<R>(5) * q};  // heat-flux reference w c_y q of a c_y = +1 population
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int a = pa(p), b = pb(p);
@@ -389,8 +390,11 @@ __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, 
         put(0, a, wp[c] + wr[c] * (Qe + Qo));
         put(0, b, wp[c] + wr[c] * (Qe - Qo));
         if (TH) {
-            put(1, a, wTp[c] + wT[c] * (Em + O));
-            put(1, b, wTp[c] + wT[c] * (Em - O));
+            // equilibrium plus the reference (+- wq for the pairs along y)
+            const R A = wTp[c] + wT[c] * Em;
+            const R B = p == 0 ? wT[c] * O : wT[c] * O + wq[c];
+            put(1, a, A + B);
+            put(1, b, A - B);
         }
     }
 }
@@ -402,12 +406,14 @@ __device__ inline void split_eq(const R* m, const R rho, const R T, const R ux, 
 //   f~ + C - w ref = w (rho' + rho ((E-1 + cB Fe) +- (O + cB Fo))) + (1 - kc) r, cB = kf - (1 - kc) dt/2
 //   f~ - w ref    = w (rho' + rho ((E-1 - dt/2 Fe) +- (O - dt/2 Fo))) + r
 //   phi_g - w Tr  = w (T' + T (E-1 +- O)) + (1 - k1g) r_g,  and likewise with kcg, or r_g alone
-// (rho' = rho - ref, T' = T - Tr).  On entry df, dg hold the stored
+// (rho' = rho - ref, T' = T - Tr).  The stored g residual of a population
+// with velocity c is r_g - w c_y q, q the row's heat-flux reference.  On entry df, dg hold the stored
 // residuals (f: a = 3..8, g: a = 1..8); the rest follow from zero mass and
 // momentum.  With NEED_D they are replaced by the offsets d of all
 // populations.
 template <class R, bool TH, bool BASE, bool NEED_D>
-__device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, R (*ph)[9], R (*bs)[9]) {
+__device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k, const R Tr, const R q, R (*ph)[9],
+                                   R (*bs)[9]) {
     constexpr int NSP = TH ? 2 : 1;
     df[1] = df[3] - df[5] + df[6] + df[7] - df[8];
     df[2] = df[4] - df[5] - df[6] + df[7] + df[8];
@@ -422,6 +428,7 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
     // w rho, w rho', w T, w T' of the axis (1/9) and diagonal (1/36) classes
     const R wr[2] = {wt<R>(1) * rho, wt<R>(5) * rho}, wp[2] = {wt<R>(1) * rp, wt<R>(5) * rp};
     const R wT[2] = {wt<R>(1) * T, wt<R>(5) * T}, wTp[2] = {wt<R>(1) * Tp, wt<R>(5) * Tp};
+    const R wq[2] = {wt<R>(1) * q, wt<R>(5) * q};
     // rest population: no flux
     if (BASE) {
         bs[0][0] = w0 * (rp - rho * (uu + k.cB * ua3)) + k.omkc * df[0];
@@ -448,20 +455,24 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
         const R PE = Em + k.cP * Fe, PO = O + k.cP * Fo;
         ph[0][a] = (wp[c] + wr[c] * (PE + PO)) + k.omk1 * ra;
         ph[0][b] = (wp[c] + wr[c] * (PE - PO)) + k.omk1 * rb;
-        R Gp = 0, Gm = 0;
+        // g: the residual is the stored one plus the reference +- wq (pairs
+        // along y), which enters each formula through its odd part
+        R GA = 0, GO = 0;
         if (TH) {
-            Gp = wTp[c] + wT[c] * (Em + O);
-            Gm = wTp[c] + wT[c] * (Em - O);
-            ph[NSP - 1][a] = Gp + k.omk1g * dg[a];
-            ph[NSP - 1][b] = Gm + k.omk1g * dg[b];
+            GA = wTp[c] + wT[c] * Em;
+            GO = wT[c] * O;
+            const R B = p == 0 ? GO : GO + k.omk1g * wq[c];
+            ph[NSP - 1][a] = (GA + B) + k.omk1g * dg[a];
+            ph[NSP - 1][b] = (GA - B) + k.omk1g * dg[b];
         }
         if (BASE) {
             const R BE = Em + k.cB * Fe, BO = O + k.cB * Fo;
             bs[0][a] = (wp[c] + wr[c] * (BE + BO)) + k.omkc * ra;
             bs[0][b] = (wp[c] + wr[c] * (BE - BO)) + k.omkc * rb;
             if (TH) {
-                bs[NSP - 1][a] = Gp + k.omkcg * dg[a];
-                bs[NSP - 1][b] = Gm + k.omkcg * dg[b];
+                const R B = p == 0 ? GO : GO + k.omkcg * wq[c];
+                bs[NSP - 1][a] = (GA + B) + k.omkcg * dg[a];
+                bs[NSP - 1][b] = (GA - B) + k.omkcg * dg[b];
             }
         }
         if (NEED_D) {
@@ -469,8 +480,9 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
             df[a] = (wp[c] + wr[c] * (QE + QO)) + ra;
             df[b] = (wp[c] + wr[c] * (QE - QO)) + rb;
             if (TH) {
-                dg[a] = Gp + dg[a];
-                dg[b] = Gm + dg[b];
+                const R B = p == 0 ? GO : GO + wq[c];
+                dg[a] = (GA + B) + dg[a];
+                dg[b] = (GA - B) + dg[b];
             }
         }
     }
@@ -479,7 +491,7 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
 // Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
 template <class R, class S, bool TH>
 __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
-                                   const R Tr) {
+                                   const R Tr, const R q) {
     using IO = Narrow<S>;
     constexpr float rs = split_scale<S>::value;
     R m[4];
@@ -490,7 +502,7 @@ __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df
     R rho, T, ux, uy, ay;
     split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
     R rf[9], rg[9];
-    split_eq<R, TH>(m, rho, T, ux, uy, ay, k, [&](int s, int a, R e) __attribute__((always_inline)) {
+    split_eq<R, TH>(m, rho, T, ux, uy, ay, k, q, [&](int s, int a, R e) __attribute__((always_inline)) {
         if (s == 0) rf[a] = df[a] - e; else rg[a] = dg[a] - e;
     });
     auto e2 = [&](R lo, R hi) __attribute__((always_inline)) { return IO::enc2(float(lo) * rs, float(hi) * rs); };
@@ -586,6 +598,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // partial updates (all but the y flux) of the last two rows
     R UP[4][NSP][3], DN[4][NSP][3], U[2][NSP][9];
     R TRg[4] = {0, 0, 0, 0};  // thermal reference of the rows in the UP/DN rings
+    R QRg[4] = {0, 0, 0, 0};  // heat-flux reference of those rows (split storage)
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -649,9 +662,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
             if (CORR) load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
     };
     // store the offsets of a cell of a row whose thermal reference is trow
-    auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow)
+    auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow, const R qrow)
                          __attribute__((always_inline)) {
-        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow);
+        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow, qrow);
         else store_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
 
@@ -659,8 +672,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
         const bool my = A.wall_y && (r < 0 || r >= A.ny);
         // thermal reference of this row (uniform; ghost rows use their mirror's)
-        R Tr = k.ref_g;
+        R Tr = k.ref_g, Qr = 0;
         if (TH && A.tref) Tr = ((const CR*)A.tref)[map_row(r)];
+        if (SPLIT && TH && A.qref) Qr = ((const CR*)A.qref)[map_row(r)];
         // wall temperature for the anti-reflection of the shifted brackets
         const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
 
@@ -687,8 +701,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 
         R ph[NSP][9], bs[NSP][9];
         if constexpr (SPLIT) {  // decodes df, dg to offsets in place
-            if (CORR) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, ph, bs);
-            else stage_split<R, TH, true, false>(mm, df, dg, k, Tr, ph, bs);
+            if (CORR) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, Qr, ph, bs);
+            else stage_split<R, TH, true, false>(mm, df, dg, k, Tr, Qr, ph, bs);
         } else {
             if (CORR) stage<R, TH, false>(df, dg, k, Tr, ph, bs);
             else stage<R, TH, true>(df, dg, k, Tr, ph, bs);
@@ -778,7 +792,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                     }
                 }
             }
-            store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3]);
+            store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
         }
 
         // ---- x flux and partial update (all but the y flux) of row r ----
@@ -801,7 +815,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
                 if constexpr (SPLIT) {
                     R hm[4], hf[9], hg[9];
                     decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
-                    stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, phn, bn);
+                    stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, Qr, phn, bn);
                 } else {
                     stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bn);
                 }
@@ -836,6 +850,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         }
         // ---- push this row into the rings ----
         TRg[SL] = Tr;
+        QRg[SL] = Qr;
 #pragma unroll
         for (int s = 0; s < NSP; ++s)
 #pragma unroll

@@ -53,6 +53,8 @@ struct FvArgs {
     R Tb, Tt;          // wall temperatures (bottom, top) for the isothermal anti-reflection of g
     R rho_x0, rho_x1;  // densities on the x faces of a fixed-density axis
     const R* tref;     // per-row thermal reference (g stored as g - w_a tref[row]), or NULL: k.ref_g
+    const R* qref;     // split thermal storage: per-row heat-flux reference, the stored g residual is
+                       // r_a - w_a c_ay qref[row] (NULL: 0)
 };
 
 struct StArgs {
@@ -90,6 +92,7 @@ struct AuxArgs {
     int thermal;
     int grouped;       // 1: grouped layout (FV schemes), 0: SoA (ST)
     const float* tref; // per-row thermal reference of the stored g, or NULL: ref_g
+    const float* qref; // split thermal storage: per-row heat-flux reference of the g residuals, or NULL
     double hdt;        // velocity shift dt/2 (0 for Euler)
     double ax, ay, bg, T0;
     double ref_f, ref_g;
@@ -103,7 +106,9 @@ hipError_t launch_moments(int storage, const AuxArgs& a, double* rho, double* ux
                           double* T, hipStream_t s);
 hipError_t launch_get_pops(int storage, const AuxArgs& a, double* out, hipStream_t s);
 hipError_t launch_set_pops(int storage, const AuxArgs& a, const double* in, hipStream_t s);
-// New per-row thermal references = row means of T; stored g re-encoded.
+// New per-row thermal references = row means of T (and, for split storage,
+// heat-flux references = row means of the g residuals' vertical flux); the
+// stored g re-encoded.
 hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s);
 
 // Diagnostics: per-block FP64 partial sums, then one block folds them in a

@@ -92,7 +92,7 @@ def test_convective_onset(storage):
     assert e2 > 2.0 * e1 and 1.8 < nu < 2.4
 
 
-def _onset_run(storage, key, run, cfg, checkpoints):
+def _onset_run(storage, key, run, cfg, checkpoints, rebase=0):
     Ra = float(key)
     nx, ny = run["nx"], cfg["ny"]
     say(f"onset {storage} Ra={key} {nx}x{ny}")
@@ -104,6 +104,8 @@ def _onset_run(storage, key, run, cfg, checkpoints):
                  stream=lb.current_stream())
     sim.set_grid(P["xf"], P["yf"])
     sim.init(rho, ux, uy, T)
+    if rebase:
+        sim.set_rebase(rebase)
     got = []
     for _ in range(checkpoints):
         sim.step(run["steps_per_checkpoint"])
@@ -135,19 +137,33 @@ def test_onset_rates_match_oracle(storage, tol):
 
 @pytest.mark.parametrize("storage,floor", [("bf16s", 5e-8), ("f16s", 3e-9)])
 def test_onset_perturbation_floor_of_split_storage(storage, floor):
-    """The 16-bit residuals of the split formats also carry the conductive
-    state's heat flux (about 2e-3 on a diagonal g population at Ra = 1600,
-    with a BF16 spacing near 1.5e-5 there).  The rolls' own contribution is
-    a few 1e-6 at these amplitudes and falls below that spacing, so near the
-    onset the split formats hold the roll energy at a floor instead of
-    resolving the slow decay or growth of the FP64 run: measured 2.7e-8
+    """Without renewed references the 16-bit residuals of the split formats
+    also carry the conductive state's heat flux (about 2e-3 on a diagonal g
+    population at Ra = 1600, with a BF16 spacing near 1.5e-5 there).  The
+    rolls' own contribution is a few 1e-6 at these amplitudes and falls below
+    that spacing, so near the onset the roll energy stalls at a floor
+    instead of following the slow decay or growth of the FP64 run: 2.7e-8
     (BF16S) and 1.2e-9 (F16S) on this 48 x 24 case.  The test keeps the floor
-    at its measured size; the onset away from the threshold (Ra = 1000 and
-    5000 above) is resolved."""
+    at its measured size; the next test removes it with lb_set_rebase."""
     gold = _onset_golden()
     run = gold["runs"]["1600"]
     got = _onset_run(storage, "1600", run, gold["config"], 8)
     assert np.all(np.isfinite(got)) and got[-1] < floor and got[-1] < got[0]
+
+
+@pytest.mark.parametrize("storage,tol", [("bf16s", 1e-2), ("f16s", 1e-2)])
+def test_onset_rates_of_split_storage_with_renewed_references(storage, tol):
+    """With the references renewed every 100 steps (lb_set_rebase) the row's
+    mean heat flux is taken out of the stored residuals, and the split
+    formats follow the FP64 oracle's onset run checkpoint by checkpoint:
+    measured within 0.3% (BF16S) and 0.3% (F16S), closer than FP32 storage;
+    the tolerance is relative."""
+    gold = _onset_golden()
+    for key, run in gold["runs"].items():
+        want = np.array(run["roll_energy"])
+        got = _onset_run(storage, key, run, gold["config"], len(want), rebase=100)
+        say(f"  oracle      {['%.4e' % e for e in want]}")
+        assert np.all(np.abs(got / want - 1) < tol)
 
 
 def test_explicit_euler_beyond_its_limit_is_reported():
