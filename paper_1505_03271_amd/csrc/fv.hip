@@ -2,8 +2,8 @@
 //
 // Two launches make one semi-implicit + Heun step (eq:semi-heun):
 //   predictor:  f~* = f~n - dt D(phi(f~n)) + C(f~n)            (eq:semi)
-//               H   = (f~n + C(f~n)) / 2
-//   corrector:  f~n+1 = H + f~*/2 - dt/2 D(phi(f~*))
+//   corrector:  f~n+1 = H + f~*/2 - dt/2 D(phi(f~*)),  H = (f~n + C(f~n)) / 2
+// where the corrector reads f~n at its own cell and recomputes C(f~n).
 // with, per population (sec. 2.2.2 and the force term of sec. 2.2.4),
 //   phi = f~ + dt/(2 tau~)(f_eq - f~) + dt/2 F          (advected bracket)
 //   C   = dt/tau~ (f_eq - f~) + dt (1 - dt/(2 tau~)) F   (collision + force)
@@ -627,7 +627,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
     // Rows are loaded one row ahead of their use (software pipelining): the
     // loads of row r+1 are in flight while row r is computed.  The FP64
     // instance (the parity path) loads each row where it is used: two rows of
-    // f, g and H in double would not fit next to its rings in registers.
+    // f and g (and the corrector's own-cell input) in double would not fit
+    // next to its rings in registers.
     constexpr bool AHEAD = sizeof(R) == 4;
     // The corrector's own-cell input goes one row ahead only for 16-bit
     // storage, whose prefetched words stay packed two to a register.

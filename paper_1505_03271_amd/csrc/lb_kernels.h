@@ -38,7 +38,7 @@ template <class R>
 struct FvArgs {
     const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector)
     void* dst;         // output state
-    void* aux;         // corrector: its own-cell input (f~n, or H); predictor: H output or NULL
+    void* aux;         // corrector: its own-cell input f~n (read only); NULL otherwise
     uint32_t state_bytes;  // whole state (grouped layout, see pop_index; or SplitLayout)
     uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
     uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
