@@ -54,6 +54,8 @@ def lib():
         L.ob_threads.restype = ctypes.c_int
         L.ob_set_threads.argtypes = [ctypes.c_int]
         L.ob_set_threads.restype = None
+        L.ob_set_bracket.argtypes = [ctypes.c_int]
+        L.ob_set_bracket.restype = None
         L.ob_grid_uniform.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.ob_grid_tanh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         L.ob_grid_sinh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
@@ -79,6 +81,13 @@ def _ptr(a):
 
 def threads():
     return lib().ob_threads()
+
+
+def set_bracket(alt):
+    """Reading of the bracket's force term: False, the literal +dt/2 F (the
+    default); True, the Crank-Nicolson physical distribution's
+    dt/2 (1 - dt/(2 tau~)) F.  Only for measuring what the reading moves."""
+    lib().ob_set_bracket(int(bool(alt)))
 
 
 def set_threads(n):

@@ -355,6 +355,14 @@ static void flux(const fv_ctx* C, const double* phi, int s, double* D)
         }
 }
 
+/* Reading of the advected bracket's force term (an oracle-only switch, to
+ * measure what the choice moves): 0, the literal eq:semi / eq:semi-heun
+ * (+dt/2 F, the default); 1, the physical distribution of the Crank-Nicolson
+ * transform, whose force term is dt/2 (1 - dt/(2 tau~)) F, i.e. dt^2/(4 tau~)
+ * F less. */
+static int g_bracket_alt = 0;
+void ob_set_bracket(int alt) { g_bracket_alt = alt ? 1 : 0; }
+
 /* Local part of one semi-implicit stage (eq:semi): the advected bracket
  * phi = f~ + dt/(2 tau~)(f~eq - f~) + dt/2 F and the collision + force
  * increment Cf = dt/tau~ (f~eq - f~) + dt (1 - dt/(2 tau~)) F, and the same
@@ -382,7 +390,8 @@ static void stage(const fv_ctx* C, const double* ft, const double* gt,
                 phf[a * N + c] = f;
                 if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * F;
             } else {
-                phf[a * N + c] = f + dt / (2.0 * tt) * (fe - f) + 0.5 * dt * F;
+                double kf = g_bracket_alt ? 0.5 * dt * (1.0 - dt / (2.0 * tt)) : 0.5 * dt;
+                phf[a * N + c] = f + dt / (2.0 * tt) * (fe - f) + kf * F;
                 if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * (1.0 - dt / (2.0 * tt)) * F;
             }
             if (p->thermal) {
@@ -861,7 +870,8 @@ static void stage3(const fv3_ctx* C, const double* ft, const double* gt, double*
                 phf[a * N + c] = f;
                 if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * F;
             } else {
-                phf[a * N + c] = f + dt / (2.0 * tt) * (fe - f) + 0.5 * dt * F;
+                double kf = g_bracket_alt ? 0.5 * dt * (1.0 - dt / (2.0 * tt)) : 0.5 * dt;
+                phf[a * N + c] = f + dt / (2.0 * tt) * (fe - f) + kf * F;
                 if (Cf) Cf[a * N + c] = dt / tt * (fe - f) + dt * (1.0 - dt / (2.0 * tt)) * F;
             }
             if (p->thermal) {
