@@ -517,7 +517,7 @@ def test_onset_between_1600_and_1800():
         assert abs(e / run["roll_energy"][0] - 1) < 1e-9
 
 
-def _poiseuille_error(n, cfl, alt, L=64.0, Re=10.0, U=0.05):
+def _poiseuille_error_reading(n, cfl, alt, L=64.0, Re=10.0, U=0.05):
     """Relative L2 error of the steady FV-Heun Poiseuille profile (sec. 3.2:
     uniform cells, Re = 10, a_x = 8 nu U / L^2, three viscous times from the
     exact parabola), with the literal bracket or its alternative reading."""
@@ -547,10 +547,10 @@ def test_bracket_reading_and_the_steady_poiseuille_profile():
     same at two time steps; with the literal bracket, which the implementation
     follows, it moves by a few per cent of the discretisation error at the
     coarse grids of Fig. 3 (N = 8)."""
-    e_alt = [_poiseuille_error(8, cfl, True) for cfl in (0.5, 1.0)]
+    e_alt = [_poiseuille_error_reading(8, cfl, True) for cfl in (0.5, 1.0)]
     assert abs(e_alt[0] - e_alt[1]) < 1e-6 * e_alt[0]
     for cfl in (0.5, 1.0):
-        e_lit = _poiseuille_error(8, cfl, False)
+        e_lit = _poiseuille_error_reading(8, cfl, False)
         assert abs(e_lit - e_alt[0]) < 0.06 * e_alt[0]
 
 
