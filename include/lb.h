@@ -229,6 +229,14 @@ int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
 int lb_rebase(lb_sim* sim);
 int lb_set_rebase(lb_sim* sim, int64_t every);
 
+/* Lanes per work item of the FV kernels (a launch-shape knob): 256 (wide
+ * strips of 252 columns, one item per block of 256 lanes), 64 (narrow
+ * strips of 60 columns, four items per block, one per wave), or 0 (the
+ * default: whichever needs fewer lanes for nx, narrow weighted 4% heavier).
+ * Results are identical either way.  Resets a height set with
+ * lb_set_fv_chunk.  LB_EINVAL for other values. */
+int lb_set_fv_lanes(lb_sim* sim, int lanes);
+
 /* Rows per work item of the FV kernels (a launch-shape knob for tuning).
  * By default the height is chosen at the first step so that every item of a
  * launch is resident at once.  Any height >= 1 gives identical results.

@@ -154,6 +154,7 @@ struct lb_sim {
     bool has_grid = false, has_init = false, unstable = false;
     std::vector<double> xf, yf;
     int chunk_h = 0;
+    int lanes = 0;            // FV item width: 0 chosen from nx, or FV_LANES / FV_NARROW
     // timing
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -235,6 +236,18 @@ void fill_stage_k(const lb_params& p, StageK<R>& k) {
     k.cB = R(kf - (1 - kc) * hdt);
 }
 
+// Narrow items (four FV_NARROW-lane items per block) unless the wide strips
+// need fewer lanes for this width; narrow lanes are weighted 4% heavier (their
+// halo share and exchange cost more per owned column).
+bool narrow_strips(const lb_sim* s) {
+    if (s->lanes) return s->lanes == FV_NARROW;
+    const int64_t nx = s->p.nx;
+    const int64_t wide = FV_LANES * ((nx + FV_LANES - 2 * FV_HALO - 1) / (FV_LANES - 2 * FV_HALO));
+    const int64_t narrow = FV_NARROW * ((nx + FV_NARROW - 2 * FV_HALO - 1) / (FV_NARROW - 2 * FV_HALO));
+    return narrow * 104 < wide * 100;
+}
+int strip_width(const lb_sim* s) { return (narrow_strips(s) ? FV_NARROW : FV_LANES) - 2 * FV_HALO; }
+
 template <class R>
 FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool corrector) {
     FvArgs<R> a{};
@@ -249,7 +262,8 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     a.ny = s->p.ny;
     a.wall_x = s->p.bc_x;   // LB_PERIODIC 0, LB_WALL 1, LB_DENSITY 2
     a.wall_y = s->p.bc_y;
-    a.strip_w = FV_LANES - 2 * FV_HALO;
+    a.narrow = narrow_strips(s) ? 1 : 0;
+    a.strip_w = strip_width(s);
     a.chunk_h = s->chunk_h;
     a.n_strips = (s->p.nx + a.strip_w - 1) / a.strip_w;
     a.n_items = a.n_strips * ((s->p.ny + a.chunk_h - 1) / a.chunk_h);
@@ -300,9 +314,10 @@ int fold_timing(lb_sim* s) {
 // Rows per FV work item: as tall as possible while every item of a launch
 // is resident at once (one item per block), in steps of four rows.
 int auto_chunk(const lb_sim* s) {
-    const int n_strips = (s->p.nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
+    const int n_strips = (s->p.nx + strip_width(s) - 1) / strip_width(s);
     int cap = fv_resident_blocks(s->p.storage, s->p.thermal, false);
     if (cap <= 0) cap = 512;
+    if (narrow_strips(s)) cap *= 4;  // four items per block
     const int chunks = std::max(1, cap / n_strips);
     int h = (s->p.ny + chunks - 1) / chunks;
     h = ((h + 3) / 4) * 4;
@@ -878,6 +893,15 @@ int lb_set_rebase(lb_sim* s, int64_t every) {
     return LB_OK;
 }
 
+int lb_set_fv_lanes(lb_sim* s, int lanes) {
+    if (int rc = check_sim(s)) return rc;
+    if (lanes != 0 && lanes != FV_LANES && lanes != FV_NARROW)
+        return fail(LB_EINVAL, "lb_set_fv_lanes: lanes must be 0, %d or %d", FV_NARROW, FV_LANES);
+    s->lanes = lanes;
+    s->chunk_h = 0;  // re-chosen at the next step for the new item width
+    return LB_OK;
+}
+
 int lb_set_fv_chunk(lb_sim* s, int rows) {
     if (int rc = check_sim(s)) return rc;
     if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
@@ -898,7 +922,8 @@ struct lb_group {
     void* d_args = nullptr;     // 2 FvArgs per slot
     int2* d_items = nullptr;
     size_t items_cap = 0;
-    int n_items = 0;
+    int n_items = 0;            // all items; the first n_wide are wide-strip items
+    int n_wide = 0;
     int64_t* d_left = nullptr;
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
@@ -932,14 +957,18 @@ int group_rebuild(lb_group* g) {
     std::vector<char> host(2 * size_t(g->max_sims) * ab, 0);
     if (g->storage == LB_F64) group_fill_args<double>(g, host);
     else group_fill_args<float>(g, host);
+    // the items of wide-strip members first, then those of narrow-strip ones
     std::vector<int2> items;
-    for (int k = 0; k < g->max_sims; ++k) {
-        lb_sim* s = g->sims[k];
-        if (!s) continue;
-        const int n_strips = (s->p.nx + (FV_LANES - 2 * FV_HALO) - 1) / (FV_LANES - 2 * FV_HALO);
-        const int n = n_strips * ((s->p.ny + s->chunk_h - 1) / s->chunk_h);
-        for (int q = 0; q < n; ++q) items.push_back(int2{k, q});
-    }
+    int n_wide = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < g->max_sims; ++k) {
+            lb_sim* s = g->sims[k];
+            if (!s || narrow_strips(s) != (pass == 1)) continue;
+            const int n_strips = (s->p.nx + strip_width(s) - 1) / strip_width(s);
+            const int n = n_strips * ((s->p.ny + s->chunk_h - 1) / s->chunk_h);
+            for (int q = 0; q < n; ++q) items.push_back(int2{k, q});
+            if (pass == 0) n_wide += n;
+        }
     HIP_TRY(hipStreamSynchronize(g->stream));
     HIP_TRY(hipMemcpy(g->d_args, host.data(), host.size(), hipMemcpyHostToDevice));
     if (items.size() > g->items_cap) {
@@ -950,6 +979,7 @@ int group_rebuild(lb_group* g) {
     }
     if (!items.empty()) HIP_TRY(hipMemcpy(g->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
     g->n_items = int(items.size());
+    g->n_wide = n_wide;
     group_drop_graph(g);
     g->dirty = false;
     return LB_OK;
@@ -959,9 +989,10 @@ int group_rebuild(lb_group* g) {
 // corrector and one counter tick per step).
 hipError_t group_enqueue(lb_group* g, int64_t nsteps) {
     for (int64_t n = 0; n < nsteps; ++n) {
-        hipError_t e = launch_fv_multi(g->storage, g->thermal, false, g->d_args, g->d_items, g->n_items, g->d_left, g->stream);
+        const int nw = g->n_wide, nn = g->n_items - g->n_wide;
+        hipError_t e = launch_fv_multi(g->storage, g->thermal, false, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
         if (e == hipSuccess)
-            e = launch_fv_multi(g->storage, g->thermal, true, g->d_args, g->d_items, g->n_items, g->d_left, g->stream);
+            e = launch_fv_multi(g->storage, g->thermal, true, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
         if (e == hipSuccess) e = launch_tick(g->d_left, g->max_sims, g->stream);
         if (e != hipSuccess) return e;
     }

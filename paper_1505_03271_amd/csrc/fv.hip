@@ -34,9 +34,10 @@
 // factor (dt, or dt/2 in the corrector) and are precomputed on the host:
 //   c > 0:  nodes i-2 .. i+1,   c < 0:  nodes i-1 .. i+2.
 //
-// Mapping.  A block of FV_LANES lanes owns a strip of up to FV_LANES - 4
-// consecutive columns plus two halo columns on each side, one lane per
-// column, and marches up a chunk of rows.  Each row is read once with
+// Mapping.  A work item of W lanes (FV_LANES, or 64 in narrow mode, four
+// items to a block) owns a strip of up to W - 4 consecutive columns plus two
+// halo columns on each side, one lane per column, and marches up a chunk of
+// rows.  Each row is read once with
 // coalesced buffer loads (x fastest in every population plane; one scalar
 // offset per plane), the stage is evaluated once per cell, x neighbours come
 // through LDS (double buffered, one barrier per row) and y neighbours from a
@@ -525,12 +526,12 @@ __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df
     }
 }
 
-// Make this row's LDS writes visible to the other lanes of the block.  A
-// one-wave block only needs the wave's own LDS operations kept in program
-// order (the LDS executes a wave's instructions in order); larger blocks need
-// a workgroup barrier.
-__device__ inline void lanes_sync() {
-    if (FV_LANES == 64) {
+// Make this row's LDS writes visible to the other lanes of the item.  A
+// 64-lane item (one wave) only needs the wave's own LDS operations kept in
+// program order (the LDS executes a wave's instructions in order); a block-
+// wide item needs a workgroup barrier.
+template <int W> __device__ inline void lanes_sync() {
+    if (W == 64) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -550,13 +551,12 @@ __device__ inline int xcd_item(int b, int n_items) {
 }
 
 // One FV stage over work item `item` (strip item % n_strips, chunk
-// item / n_strips) of the simulation described by A.
-template <class R, class S, bool TH, bool CORR>
-__device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
+// item / n_strips) of the simulation described by A, on W lanes (lane t;
+// lds: this item's exchange rows).
+template <class R, class S, bool TH, bool CORR, int W>
+__device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, const int t,
+                                        R (*lds)[6 * (TH ? 2 : 1)][W]) {
     constexpr int NSP = TH ? 2 : 1;
-    __shared__ R lds[2][6 * NSP][FV_LANES];
-
-    const int t = threadIdx.x;
     const int strip = item % A.n_strips, chunk = item / A.n_strips;
     const int x0 = strip * A.strip_w;
     const int own = min(A.strip_w, A.nx - x0);
@@ -802,7 +802,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
         for (int s = 0; s < NSP; ++s)
 #pragma unroll
             for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
-        lanes_sync();
+        lanes_sync<W>();
         if (SPLIT && CORR && AHEAD) {
             __builtin_amdgcn_sched_barrier(0);
             prefetch_own(r + 1, Slot<SL + 1>{});
@@ -875,31 +875,66 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item) {
 }
 
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32
-// arithmetic) or one (FP64), whatever the block width.
+// arithmetic) or one (FP64).
 template <class R> constexpr int FV_MIN_BLOCKS = (sizeof(R) == 4 ? 8 : 4) * 64 / FV_LANES;
+
+// Block b runs one wide item (FV_LANES lanes) or, in narrow mode, four
+// independent 64-lane items, one per wave: narrow strips waste fewer lanes
+// on grids whose width is not close to a multiple of FV_LANES - 4.  A wave
+// of a narrow block synchronises with itself only.
+template <class R, class S, bool TH, bool CORR>
+__device__ __forceinline__ void fv_block(const FvArgs<R>& A, const int item, const bool narrow, R* lds_mem) {
+    constexpr int NSP = TH ? 2 : 1;
+    if (narrow) {
+        const int w = threadIdx.x >> 6;
+        fv_item<R, S, TH, CORR, 64>(A, item, threadIdx.x & 63,
+                                    reinterpret_cast<R(*)[6 * NSP][64]>(lds_mem + w * (2 * 6 * NSP * 64)));
+    } else {
+        fv_item<R, S, TH, CORR, FV_LANES>(A, item, threadIdx.x, reinterpret_cast<R(*)[6 * NSP][FV_LANES]>(lds_mem));
+    }
+}
 
 // One simulation: arguments by value.
 template <class R, class S, bool TH, bool CORR>
 __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>) fv_pass(FvArgs<R> A) {
-    const int item = xcd_item(blockIdx.x, A.n_items);
-    if (item >= A.n_items) return;
-    fv_item<R, S, TH, CORR>(A, item);
+    __shared__ R lds_mem[2 * 6 * (TH ? 2 : 1) * FV_LANES];
+    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
+    const int b = xcd_item(blockIdx.x, nb);
+    if (b >= nb) return;
+    if (A.narrow) {
+        const int item = 4 * b + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (item >= A.n_items) return;
+        fv_block<R, S, TH, CORR>(A, item, true, lds_mem);
+    } else {
+        fv_block<R, S, TH, CORR>(A, b, false, lds_mem);
+    }
 }
 
 // Many simulations in one launch (serving): a table of per-simulation
 // arguments (predictor and corrector entry per simulation), a work list of
-// (simulation, local item) pairs, and per-simulation remaining steps; the
-// items of a simulation that has finished are skipped.  Every item runs the
-// same code as in fv_pass, so a simulation's result does not depend on what
-// else shares the launch.
+// (simulation, local item) pairs, the n_wide items of wide-strip members
+// first, then the n_narrow items of narrow-strip members (four to a block),
+// and per-simulation remaining steps; the items of a simulation that has
+// finished are skipped.  Every item runs the same code as in fv_pass, so a
+// simulation's result does not depend on what else shares the launch.
 template <class R, class S, bool TH, bool CORR>
 __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
-    fv_pass_multi(const FvArgs<R>* args, const int2* items, int n_items, const int64_t* left) {
-    const int w = xcd_item(blockIdx.x, n_items);
-    if (w >= n_items) return;
-    const int2 it = items[w];
+    fv_pass_multi(const FvArgs<R>* args, const int2* items, int n_wide, int n_narrow, const int64_t* left) {
+    __shared__ R lds_mem[2 * 6 * (TH ? 2 : 1) * FV_LANES];
+    const int nb = n_wide + (n_narrow + 3) / 4;
+    const int b = xcd_item(blockIdx.x, nb);
+    if (b >= nb) return;
+    const bool narrow = b >= n_wide;
+    int idx = b;
+    if (narrow) {
+        const int k = 4 * (b - n_wide) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (k >= n_narrow) return;
+        idx = n_wide + k;
+    }
+    const int2 it = items[idx];
     if (left[it.x] <= 0) return;
-    // the argument block is uniform: copy it word by word with scalar loads
+    // the argument block is uniform over the item: copy it word by word with
+    // scalar loads
     static_assert(sizeof(FvArgs<R>) % 4 == 0, "argument block in words");
     typedef const __attribute__((address_space(4))) uint32_t CW;
     CW* src = (CW*)(args + 2 * it.x + (CORR ? 1 : 0));
@@ -908,7 +943,7 @@ __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
     for (int q = 0; q < int(sizeof(FvArgs<R>) / 4); ++q) words[q] = src[q];
     FvArgs<R> A;
     __builtin_memcpy(&A, words, sizeof(FvArgs<R>));
-    fv_item<R, S, TH, CORR>(A, it.y);
+    fv_block<R, S, TH, CORR>(A, it.y, narrow, lds_mem);
 }
 
 __global__ void tick_kernel(int64_t* left, int n) {
@@ -917,34 +952,35 @@ __global__ void tick_kernel(int64_t* left, int n) {
 }
 
 template <class R, class S>
-static hipError_t launch_multi_typed(bool thermal, bool corrector, const void* args, const int2* items, int n_items,
-                                     const int64_t* left, hipStream_t s) {
+static hipError_t launch_multi_typed(bool thermal, bool corrector, const void* args, const int2* items, int n_wide,
+                                     int n_narrow, const int64_t* left, hipStream_t s) {
     const FvArgs<R>* a = static_cast<const FvArgs<R>*>(args);
-    dim3 grid(8 * ((n_items + 7) / 8)), block(FV_LANES);
+    const int nb = n_wide + (n_narrow + 3) / 4;
+    dim3 grid(8 * ((nb + 7) / 8)), block(FV_LANES);
     if (thermal) {
         if (corrector)
-            hipLaunchKernelGGL((fv_pass_multi<R, S, true, true>), grid, block, 0, s, a, items, n_items, left);
+            hipLaunchKernelGGL((fv_pass_multi<R, S, true, true>), grid, block, 0, s, a, items, n_wide, n_narrow, left);
         else
-            hipLaunchKernelGGL((fv_pass_multi<R, S, true, false>), grid, block, 0, s, a, items, n_items, left);
+            hipLaunchKernelGGL((fv_pass_multi<R, S, true, false>), grid, block, 0, s, a, items, n_wide, n_narrow, left);
     } else {
         if (corrector)
-            hipLaunchKernelGGL((fv_pass_multi<R, S, false, true>), grid, block, 0, s, a, items, n_items, left);
+            hipLaunchKernelGGL((fv_pass_multi<R, S, false, true>), grid, block, 0, s, a, items, n_wide, n_narrow, left);
         else
-            hipLaunchKernelGGL((fv_pass_multi<R, S, false, false>), grid, block, 0, s, a, items, n_items, left);
+            hipLaunchKernelGGL((fv_pass_multi<R, S, false, false>), grid, block, 0, s, a, items, n_wide, n_narrow, left);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void* args, const int2* items,
-                           int n_items, const int64_t* left, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
+                           int n_wide, int n_narrow, const int64_t* left, hipStream_t s) {
+    if (n_wide + n_narrow <= 0) return hipSuccess;
     switch (storage) {
-        case ST_F64: return launch_multi_typed<double, double>(thermal, corrector, args, items, n_items, left, s);
-        case ST_F32: return launch_multi_typed<float, float>(thermal, corrector, args, items, n_items, left, s);
-        case ST_BF16: return launch_multi_typed<float, bf16_t>(thermal, corrector, args, items, n_items, left, s);
-        case ST_F16: return launch_multi_typed<float, f16_t>(thermal, corrector, args, items, n_items, left, s);
-        case ST_BF16S: return launch_multi_typed<float, bf16s_t>(thermal, corrector, args, items, n_items, left, s);
-        case ST_F16S: return launch_multi_typed<float, f16s_t>(thermal, corrector, args, items, n_items, left, s);
+        case ST_F64: return launch_multi_typed<double, double>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
+        case ST_F32: return launch_multi_typed<float, float>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
+        case ST_BF16: return launch_multi_typed<float, bf16_t>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
+        case ST_F16: return launch_multi_typed<float, f16_t>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
+        case ST_BF16S: return launch_multi_typed<float, bf16s_t>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
+        case ST_F16S: return launch_multi_typed<float, f16s_t>(thermal, corrector, args, items, n_wide, n_narrow, left, s);
     }
     return hipErrorInvalidValue;
 }
@@ -960,7 +996,8 @@ size_t fv_args_bytes(int storage) { return storage == ST_F64 ? sizeof(FvArgs<dou
 template <class R, class S>
 static hipError_t launch_typed(bool thermal, bool corrector, const void* args, hipStream_t s) {
     const FvArgs<R>& A = *static_cast<const FvArgs<R>*>(args);
-    dim3 grid(8 * ((A.n_items + 7) / 8)), block(FV_LANES);
+    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
+    dim3 grid(8 * ((nb + 7) / 8)), block(FV_LANES);
     if (thermal) {
         if (corrector)
             hipLaunchKernelGGL((fv_pass<R, S, true, true>), grid, block, 0, s, A);

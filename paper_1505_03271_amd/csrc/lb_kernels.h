@@ -10,13 +10,11 @@ namespace lbk {
 
 enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3, ST_BF16S = 4, ST_F16S = 5 };
 
-// Width in lanes of the FV strip kernel (one lane per column, the block
-// marches up its rows): FV_LANES - 4 owned columns + 2 halo columns on each
-// side.
-#ifndef LB_FV_LANES
-#define LB_FV_LANES 256
-#endif
-constexpr int FV_LANES = LB_FV_LANES;
+// Lanes of an FV block (one lane per column, a work item marches up its
+// rows): a wide item owns FV_LANES - 4 columns + 2 halo columns on each side;
+// in narrow mode a block runs four items of FV_NARROW lanes, one per wave.
+constexpr int FV_LANES = 256;
+constexpr int FV_NARROW = 64;
 constexpr int FV_HALO = 2;
 
 // Stage constants of the FV kernel in offset arithmetic (see fv.hip), with
@@ -44,7 +42,8 @@ struct FvArgs {
     uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
     int nx, ny;
     int wall_x, wall_y;  // 0 periodic, 1 no-slip wall, 2 (x only) fixed density
-    int strip_w;       // owned columns per strip (<= FV_LANES - 4)
+    int strip_w;       // owned columns per strip (FV_LANES - 4, or FV_NARROW - 4 in narrow mode)
+    int narrow;        // 1: four FV_NARROW-lane items per block
     int chunk_h;       // rows per chunk
     int n_strips, n_items;  // work items: n_strips * n_chunks, chunk-major
     const R* xcoef;    // [nx][8] four-point flux weights (c>0: i-2..i+1, c<0: i-1..i+2), times dt or dt/2
@@ -74,13 +73,14 @@ struct StArgs {
 hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
 // Serving: one launch over the work items of many simulations.  args holds
 // 2 FvArgs per simulation (predictor, corrector); items are (simulation,
-// local item); left[s] is the number of steps simulation s still has to do.
+// local item), the n_wide items of wide-strip members first, then the
+// n_narrow items of narrow-strip members; left[s] is the number of steps
+// simulation s still has to do.
 hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void* args, const int2* items,
-                           int n_items, const int64_t* left, hipStream_t s);
+                           int n_wide, int n_narrow, const int64_t* left, hipStream_t s);
 hipError_t launch_tick(int64_t* left, int n, hipStream_t s);
 size_t fv_args_bytes(int storage);
 
-// True when the Heun predictor stores H = (f~n + C)/2 for the corrector.
 // Largest number of FV blocks of one launch that are resident at once.
 int fv_resident_blocks(int storage, bool thermal, bool corrector);
 hipError_t launch_st(int storage, bool thermal, bool stream_only, const StArgs& a, hipStream_t s);

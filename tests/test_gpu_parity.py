@@ -357,6 +357,27 @@ def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic(storage):
         assert np.array_equal(other.get_state(), a), f"chunk {chunk}"
 
 
+@pytest.mark.parametrize("storage", ["f64", "bf16s", "bf16"])
+@pytest.mark.parametrize("wall_x", [False, True])
+def test_narrow_and_wide_strips_are_bit_identical(storage, wall_x):
+    """The FV item width is a launch shape only: 64-lane items (four per
+    block) and 256-lane items give the same state bit for bit, on a width
+    that leaves a ragged last strip in both (nx = 300)."""
+    nx, ny = 300, 53
+    say(f"narrow vs wide strips {storage} wall_x={wall_x}")
+    kw = dict(thermal=True, wall_x=wall_x, wall_y=True, dt=0.5, tau=0.3, tau_g=0.25, beta_g=1e-3, T_bottom=0.5,
+              T_top=-0.5)
+    fields = random_fields(nx, ny, 8)
+    xf, yf = workloads.faces_uniform(nx, 3.0 * nx), workloads.faces_tanh(ny, 3.0 * ny, 2.0)
+    states = []
+    for lanes in (64, 256):
+        sim, _ = make_pair(nx, ny, "heun", storage, xf, yf, fields, **kw)
+        sim.set_fv_lanes(lanes)
+        sim.step(12)
+        states.append(sim.get_state())
+    assert np.array_equal(states[0], states[1])
+
+
 def test_nonfinite_population_is_reported():
     nx, ny = 64, 32
     say("non-finite detection")
