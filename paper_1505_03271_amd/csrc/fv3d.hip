@@ -159,11 +159,10 @@ __device__ inline R phi_at(const Fv3Args<R>& A, int s, int a, int axis, int q, c
     return R(2) * w3<R>(a) * ((q < 0 ? A.Tb : A.Tt) - A.k.ref_g) - v;
 }
 
+// The update of cell c (all populations).
 template <class R, class S, bool TH, bool CORR>
-__global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
+__device__ __forceinline__ void update_cell(const Fv3Args<R>& A, const int64_t c) {
     constexpr int NSP = TH ? 2 : 1;
-    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (c >= A.cells) return;
     const int i[3] = {int(c % A.n[0]), int((c / A.n[0]) % A.n[1]), int(c / (int64_t(A.n[0]) * A.n[1]))};
     const StageK<R>& k = A.k;
     const int64_t stride[3] = {1, int64_t(A.n[0]), int64_t(A.n[0]) * A.n[1]};
@@ -212,6 +211,13 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
             }
             Store3<S>::st(dst + e, S(b));
         }
+}
+
+template <class R, class S, bool TH, bool CORR>
+__global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= A.cells) return;
+    update_cell<R, S, TH, CORR>(A, c);
 }
 
 template <class R, class S>
