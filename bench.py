@@ -368,6 +368,7 @@ def main():
         out["serving"] = {"requests": st["n_requests"], "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                           "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
                           "graph_steps": st["graph_steps"], "graph_launches": st["graph_launches"],
+                          "phases_s": st["phases_s"],
                           "hbm_budget_bytes": 16e9, "storage": args.storage,
                           "trace": "Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
                                    "steps U{2000..20000}, seed 150503275"}

@@ -267,6 +267,13 @@ void lb_group_destroy(lb_group* group);
 int lb_group_add(lb_group* group, lb_sim* sim, int64_t steps, int32_t* slot);
 /* Leave (finished or not); the slot becomes free.  Synchronises. */
 int lb_group_remove(lb_group* group, int32_t slot);
+/* Rows per work item of the members' launches: 0 (the default) chooses them
+ * at each membership change from the members' strips and the number of
+ * blocks the device holds at once (tall items when the members fill the
+ * device many times over, short ones when few are left); rows >= 1 fixes
+ * them.  Results do not depend on it.  Takes effect at the next
+ * lb_group_step.  LB_EINVAL for a NULL group or rows < 0. */
+int lb_group_set_chunk(lb_group* group, int32_t rows);
 /* Enqueue nsteps group steps (asynchronous). */
 int lb_group_step(lb_group* group, int64_t nsteps);
 int lb_group_sync(lb_group* group);

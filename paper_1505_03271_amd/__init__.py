@@ -116,6 +116,7 @@ def lib():
             "lb_group_destroy": ([h], None),
             "lb_group_add": ([h, h, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lb_group_remove": ([h, ctypes.c_int32], ctypes.c_int),
+            "lb_group_set_chunk": ([h, ctypes.c_int32], ctypes.c_int),
             "lb_group_step": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_group_sync": ([h], ctypes.c_int),
             "lb_group_remaining": ([h, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -348,6 +349,10 @@ class Group:
     def remove(self, slot):
         _check(lib().lb_group_remove(self.h, int(slot)))
         self.members.pop(slot, None)
+
+    def set_chunk(self, rows):
+        """Rows per work item (0: chosen at each membership change)."""
+        _check(lib().lb_group_set_chunk(self.h, int(rows)))
 
     def step(self, n):
         _check(lib().lb_group_step(self.h, int(n)))

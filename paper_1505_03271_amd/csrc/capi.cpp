@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -925,6 +926,7 @@ struct lb_group {
     int n_items = 0;            // all items; the first n_wide are wide-strip items
     int n_wide = 0;
     int64_t* d_left = nullptr;
+    int chunk = 0;              // rows per work item: 0 chosen at each rebuild (group_chunk), else fixed
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     int64_t exec_steps = 0;
@@ -932,7 +934,32 @@ struct lb_group {
 
 namespace {
 
-constexpr int GROUP_CHUNK = 64;  // rows per work item of group members (balanced items)
+// Rows per work item for the current members.  All items of one launch have
+// the same height h, so with B(h) blocks and `cap` of them resident at once
+// a launch takes about ceil(B / cap) rounds of h + GROUP_ITEM_ROWS row times
+// (an item also marches two rows before and after its chunk and sets up its
+// rings).  Pick the h of 16..512 (steps of 8) with the least such time: tall
+// items when the members fill the chip many times over, short ones when few
+// members are left.
+constexpr int GROUP_ITEM_ROWS = 3;
+int group_chunk(const lb_group* g) {
+    int cap = fv_resident_blocks(g->storage, g->thermal != 0, false);
+    if (cap <= 0) cap = 512;
+    int best_h = 64;
+    int64_t best_t = INT64_MAX;
+    for (int h = 16; h <= 512; h += 8) {
+        int64_t wide = 0, narrow = 0;
+        for (const lb_sim* s : g->sims) {
+            if (!s) continue;
+            const int64_t n = int64_t((s->p.nx + strip_width(s) - 1) / strip_width(s)) * ((s->p.ny + h - 1) / h);
+            (narrow_strips(s) ? narrow : wide) += n;
+        }
+        const int64_t blocks = wide + (narrow + 3) / 4;
+        const int64_t t = ((blocks + cap - 1) / cap) * (h + GROUP_ITEM_ROWS);
+        if (t <= best_t) { best_t = t; best_h = h; }
+    }
+    return best_h;
+}
 
 void group_drop_graph(lb_group* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -953,6 +980,11 @@ void group_fill_args(lb_group* g, std::vector<char>& host) {
 }
 
 int group_rebuild(lb_group* g) {
+    if (g->storage >= 0) {
+        const int h = g->chunk > 0 ? g->chunk : group_chunk(g);
+        for (lb_sim* s : g->sims)
+            if (s) s->chunk_h = h;
+    }
     const size_t ab = fv_args_bytes(g->storage);
     std::vector<char> host(2 * size_t(g->max_sims) * ab, 0);
     if (g->storage == LB_F64) group_fill_args<double>(g, host);
@@ -1060,7 +1092,6 @@ int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
     HIP_TRY(hipMemcpy(g->d_left + k, &steps, sizeof(int64_t), hipMemcpyHostToDevice));
     g->storage = s->p.storage;
     g->thermal = s->p.thermal;
-    s->chunk_h = GROUP_CHUNK;
     g->sims[k] = s;
     g->dirty = true;
     *slot = k;
@@ -1077,6 +1108,14 @@ int lb_group_remove(lb_group* g, int32_t slot) {
     bool any = false;
     for (lb_sim* m : g->sims) any = any || m;
     if (!any) { g->storage = -1; g->thermal = -1; }
+    return LB_OK;
+}
+
+int lb_group_set_chunk(lb_group* g, int32_t rows) {
+    if (!g) return fail(LB_EINVAL, "lb_group_set_chunk: NULL group");
+    if (rows < 0) return fail(LB_EINVAL, "lb_group_set_chunk: rows must be >= 0 (0: automatic)");
+    g->chunk = rows;
+    g->dirty = true;
     return LB_OK;
 }
 

@@ -67,6 +67,7 @@ class Server:
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
         launches = 0
+        phase = dict(prep_s=0.0, launch_s=0.0, wait_s=0.0, completion_s=0.0, idle_s=0.0)
         while pending or queue or active:
             now = clock()
             while pending and pending[0]["arrival"] * time_scale <= now:
@@ -80,17 +81,26 @@ class Server:
                 if used + need > self.hbm_budget:
                     break
                 queue.popleft()
+                t = clock()
                 sim = self._make(req)
                 slot = self.group.add(sim, req["steps"])
+                phase["prep_s"] += clock() - t
                 active[slot] = (req, sim, clock(), need)
                 used += need
             if not active:
                 if pending:  # idle until the next arrival
+                    t = clock()
                     time.sleep(max(0.0, pending[0]["arrival"] * time_scale - clock()))
+                    phase["idle_s"] += clock() - t
                 continue
+            t = clock()
             self.group.step(self.graph_steps)
             launches += 1
+            t1 = clock()
             left = self.group.remaining()   # synchronises
+            t2 = clock()
+            phase["launch_s"] += t1 - t
+            phase["wait_s"] += t2 - t1
             for slot in [s for s in active if left[s] == 0]:
                 req, sim, t_admit, need = active.pop(slot)
                 nu = sim.nusselt()
@@ -105,13 +115,15 @@ class Server:
                 if log:
                     log(f"req {req['id']:4d} n={req['n']:5d} steps={req['steps']:6d} "
                         f"latency {done[-1]['latency']:.2f}s nu_vol={nu[2]:.3f}")
+            phase["completion_s"] += clock() - t2
         makespan = clock()
         lat = np.array([d["latency"] for d in done])
         return dict(requests=done, n_requests=len(done), makespan_s=makespan,
                     p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
                     p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                     aggregate_mlups=cell_steps / makespan / 1e6 if makespan > 0 else None,
-                    graph_launches=launches, graph_steps=self.graph_steps)
+                    graph_launches=launches, graph_steps=self.graph_steps,
+                    phases_s={k: round(v, 3) for k, v in phase.items()})
 
     def close(self):
         self.group.close()

@@ -75,7 +75,10 @@ def test_bad_storage_and_scheme_codes():
 def test_null_handle_is_rejected():
     assert lb.lib().lb_step(None, 1) == 1
     assert lb.lib().lb_sync(None) == 1
+    assert lb.lib().lb_group_step(None, 1) == 1
+    assert lb.lib().lb_group_set_chunk(None, 0) == 1
     lb.lib().lb_destroy(None)  # no-op
+    lb.lib().lb_group_destroy(None)
 
 
 def test_sinh_and_chebyshev_grids():

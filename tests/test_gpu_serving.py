@@ -33,9 +33,12 @@ def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
 CASES = [(300, 77, 1e7, 1.0, 31), (128, 128, 1e6, 0.7, 45), (200, 150, 1e8, 7.0, 60), (97, 64, 3e6, 1.0, 0)]
 
 
-@pytest.mark.parametrize("storage", ["bf16", "bf16s", "f32", "f64"])
-def test_group_members_match_alone_bit_exact(storage):
-    say(f"group vs alone {storage}")
+@pytest.mark.parametrize("storage,chunk", [("bf16", 0), ("bf16s", 0), ("f32", 0), ("f64", 0), ("bf16s", 24),
+                                           ("f64", 8)])
+def test_group_members_match_alone_bit_exact(storage, chunk):
+    """chunk 0: rows per item chosen by the group at each membership change;
+    otherwise fixed."""
+    say(f"group vs alone {storage} chunk {chunk}")
     alone = []
     for k, (nx, ny, Ra, Pr, steps) in enumerate(CASES):
         s = _rb_sim(nx, ny, Ra, Pr, storage, 100 + k)
@@ -44,6 +47,7 @@ def test_group_members_match_alone_bit_exact(storage):
         s.close()
     sims = [_rb_sim(nx, ny, Ra, Pr, storage, 100 + k) for k, (nx, ny, Ra, Pr, _) in enumerate(CASES)]
     g = lb.Group(8, lb.current_stream())
+    g.set_chunk(chunk)
     slots = {}
     for k in (0, 1, 3):
         slots[k] = g.add(sims[k], CASES[k][4])
