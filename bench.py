@@ -361,18 +361,23 @@ def main():
     if args.serve_requests > 0:
         from paper_1505_03271_amd.serve import Server
         trace = workloads.serving_trace()[:args.serve_requests]
-        log(f"serving {len(trace)} requests ...")
-        server = Server(storage=args.storage, hbm_budget=16e9, max_sims=128, graph_steps=100)
-        st = server.run(trace)
-        server.close()
-        out["serving"] = {"requests": st["n_requests"], "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
-                          "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
-                          "graph_steps": st["graph_steps"], "graph_launches": st["graph_launches"],
-                          "phases_s": st["phases_s"],
-                          "hbm_budget_bytes": 16e9, "storage": args.storage,
-                          "trace": "Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
-                                   "steps U{2000..20000}, seed 150503275"}
-        log(f"serving: p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, {st['aggregate_mlups']:.0f} MLUPS")
+        runs = {}
+        for policy in ("srpt", "all"):
+            log(f"serving {len(trace)} requests, policy {policy} ...")
+            server = Server(storage=args.storage, hbm_budget=16e9, max_sims=128, graph_steps=100, policy=policy)
+            st = server.run(trace)
+            server.close()
+            runs[policy] = {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                            "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
+                            "graph_launches": st["graph_launches"], "preemptions": st["preemptions"],
+                            "phases_s": st["phases_s"]}
+            log(f"serving ({policy}): p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, "
+                f"{st['aggregate_mlups']:.0f} MLUPS")
+        out["serving"] = dict(requests=len(trace), policy="srpt", min_cells=8e6, **runs["srpt"],
+                              graph_steps=100, hbm_budget_bytes=16e9, storage=args.storage,
+                              trace="Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
+                                    "steps U{2000..20000}, seed 150503275",
+                              all_members=runs["all"])
     if not args.no_accuracy:
         log("accuracy against the oracle (steady roll) ...")
         out["accuracy"] = accuracy_report(lb, torch)

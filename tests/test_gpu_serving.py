@@ -96,10 +96,14 @@ def test_group_membership_rules():
     g.close()
 
 
-def test_server_serves_a_trace_and_results_equal_alone():
-    say("server small trace")
+@pytest.mark.parametrize("policy,min_cells", [("all", 0), ("srpt", 1), ("srpt", 30000)])
+def test_server_serves_a_trace_and_results_equal_alone(policy, min_cells):
+    """Every request's Nusselt numbers equal those of the same simulation run
+    alone, under either policy; with "srpt" and a small min_cells requests
+    are preempted (leave the group) and resume later."""
+    say(f"server small trace {policy} {min_cells}")
     trace = workloads.serving_trace(n_requests=8, rate=50.0, side=(64, 160), ra=(1e6, 1e8), steps=(40, 160))
-    server = Server(storage="bf16", hbm_budget=2e8, max_sims=4, graph_steps=25)
+    server = Server(storage="bf16", hbm_budget=2e8, max_sims=4, graph_steps=25, policy=policy, min_cells=min_cells)
     stats = server.run(trace)
     server.close()
     assert stats["n_requests"] == 8
@@ -107,6 +111,30 @@ def test_server_serves_a_trace_and_results_equal_alone():
     by_id = {r["id"]: r for r in stats["requests"]}
     for req in trace:
         solo = Server(storage="bf16", max_sims=1)
+        sim = solo._make(req)
+        sim.step(req["steps"])
+        nu = sim.nusselt()
+        sim.close()
+        solo.close()
+        assert by_id[req["id"]]["nu"] == nu, req["id"]
+
+
+def test_server_preempts_a_long_request_and_it_resumes_exactly():
+    """"srpt" with min_cells 1 runs only the request with the least remaining
+    work: a short request that arrives while a long one runs takes its place,
+    and the long one resumes afterwards.  Both end with the Nusselt numbers
+    of the same simulations run alone."""
+    say("server preemption")
+    trace = [dict(id=0, arrival=0.0, n=160, Ra=1e7, Pr=1.0, steps=20000),
+             dict(id=1, arrival=0.05, n=64, Ra=1e6, Pr=0.7, steps=60)]
+    server = Server(storage="bf16s", hbm_budget=2e8, max_sims=4, graph_steps=25, policy="srpt", min_cells=1)
+    stats = server.run(trace)
+    server.close()
+    assert stats["n_requests"] == 2 and stats["preemptions"] >= 1
+    by_id = {r["id"]: r for r in stats["requests"]}
+    assert by_id[1]["finished"] < by_id[0]["finished"]
+    for req in trace:
+        solo = Server(storage="bf16s", max_sims=1)
         sim = solo._make(req)
         sim.step(req["steps"])
         nu = sim.nusselt()
