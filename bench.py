@@ -114,14 +114,16 @@ def run_st(lb, torch, n, storage, steps, warmup):
     return dict(seconds=wall, kernels=kt, cells=n * n, steps=steps)
 
 
-def run_fv3d(lb, torch, n, steps, warmup, storage="f32"):
+def run_fv3d(lb, torch, n, steps, warmup, storage="f32", update="tiled"):
     """The 3D (D3Q19) FV-Heun step on a cubic Rayleigh-Benard cell of n^3
-    cells (Ra = 1e8, Pr = 1, tanh(2.0) in z)."""
+    cells (Ra = 1e8, Pr = 1, tanh(2.0) in z); `update` selects the flux +
+    update kernel (lb3_set_update)."""
     import workloads
     cfg = workloads.rb3d_config(n, 1e8, 2.0)
     sim = lb.Sim3(n, n, n, scheme="heun", storage=storage, thermal=True, walls=(False, False, True), dt=cfg["dt"],
                   tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"], T_bottom=cfg["T_bottom"],
                   T_top=cfg["T_top"], stream=lb.current_stream())
+    sim.set_update(update)
     sim.set_grid(cfg["xf"], cfg["yf"], cfg["zf"])
     sim.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["uz"], cfg["T"])
     sim.step(warmup)

@@ -308,7 +308,8 @@ int lb_stream_probe(size_t bytes, void* stream, double* out);
  * (weights 1/3, 1/18, 1/36).  Field arrays are [nz][ny][nx] (x fastest),
  * population arrays [19][nz][ny][nx].  Storage LB_F64 or LB_F32 (offsets
  * p - w rho_ref, g - w T_ref).  Each FV stage runs two kernels (brackets to a
- * scratch buffer, then flux + update).  Same error conventions as above.
+ * scratch buffer, then flux + update; see lb3_set_update).  Same error
+ * conventions as above.
  * ====================================================================== */
 typedef struct lb3_params {
     int32_t nx, ny, nz;      /* cells, >= 4 each */
@@ -341,6 +342,13 @@ int lb3_moments(lb3_sim* sim, double* rho, double* ux, double* uy, double* uz, d
 int lb3_get_populations(lb3_sim* sim, double* f, double* g);
 /* out[8] as lb_diagnostics, the Nusselt numbers on the z walls */
 int lb3_diagnostics(lb3_sim* sim, double* out);
+/* Kernel of the flux + update half of each stage: 0 (default) tiles of
+ * 32 x 4 x 4 cells whose brackets, with the halo cells their stencils
+ * reach, are staged in LDS population by population; 1 one thread per cell
+ * reading every stencil point from the scratch buffer.  Both compute the
+ * same operations in the same order (bit-identical results).  LB_EINVAL
+ * for another kind. */
+int lb3_set_update(lb3_sim* sim, int kind);
 /* HIP-event timing of the stage passes: launches[2], ms[2] = (first pass, corrector) */
 int lb3_set_timing(lb3_sim* sim, int on);
 int lb3_kernel_times(lb3_sim* sim, int64_t* launches, double* ms);

@@ -129,6 +129,7 @@ def lib():
             "lb3_moments": ([h, _DP, _DP, _DP, _DP, _DP], ctypes.c_int),
             "lb3_get_populations": ([h, _DP, _DP], ctypes.c_int),
             "lb3_diagnostics": ([h, _DP], ctypes.c_int),
+            "lb3_set_update": ([h, ctypes.c_int], ctypes.c_int),
             "lb3_set_timing": ([h, ctypes.c_int], ctypes.c_int),
             "lb3_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
         }
@@ -428,6 +429,11 @@ class Sim3:
         _check(lib().lb3_diagnostics(self.h, _dptr(out)))
         keys = ("mass", "ekin", "etherm", "nu_bottom", "nu_top", "nu_vol", "volume", "nonfinite")
         return dict(zip(keys, out.tolist()))
+
+    def set_update(self, kind):
+        """Flux + update kernel: "tiled" (LDS tiles, default) or "gather" (one
+        thread per cell); results are bit-identical."""
+        _check(lib().lb3_set_update(self.h, {"tiled": 0, "gather": 1}[kind]))
 
     def set_timing(self, on=True):
         _check(lib().lb3_set_timing(self.h, int(bool(on))))

@@ -1184,6 +1184,7 @@ struct lb3_sim {
     size_t coef_off[2][3] = {{0, 0, 0}, {0, 0, 0}};
     bool has_grid = false, has_init = false, unstable = false;
     bool timing = false;
+    int gather = 0;           // update kernel: 0 LDS tiles, 1 one thread per cell
     std::vector<hipEvent_t> events;
     std::vector<int> kinds;
     size_t n_rec = 0;
@@ -1258,6 +1259,7 @@ Fv3Args<R> fv3_args(const lb3_sim* s, const void* src, void* dst, const void* au
     a.az = R(s->p.a[2]);
     a.Tb = R(s->p.T_bottom);
     a.Tt = R(s->p.T_top);
+    a.gather = s->gather;
     return a;
 }
 
@@ -1513,6 +1515,13 @@ int lb3_diagnostics(lb3_sim* s, double* out) {
     out[6] = o[D_VOL];
     out[7] = o[D_BAD];
     if (o[D_BAD] != 0.0) s->unstable = true;
+    return LB_OK;
+}
+
+int lb3_set_update(lb3_sim* s, int kind) {
+    if (int rc = check3(s)) return rc;
+    if (kind != 0 && kind != 1) return fail(LB_EINVAL, "lb3_set_update: kind must be 0 (tiles) or 1 (per cell)");
+    s->gather = kind;
     return LB_OK;
 }
 

@@ -14,11 +14,17 @@
 //               the new state:
 //                 predictor / single stage:  f~ + C(f~) - dt D(phi)
 //                 Heun corrector:            (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*)
-// The two-kernel form keeps the radius-2 cross stencil of 3D simple; it moves
-// the brackets through HBM once more than a fused kernel would.
+// The flux + update kernel works on 32 x 4 x 4 tiles whose brackets and halo
+// brackets are staged in LDS population by population (fv3_update_tiled);
+// fv3_update, one thread per cell reading every stencil point from the
+// scratch buffer, computes the same operations in the same order.  The
+// two-kernel form moves the brackets through HBM once more than a fused
+// kernel would.
 //
 // Storage: FP64 (parity path) or FP32 offsets p - w_a ref, populations as
 // (s * 19 + a) * cells + cell, x fastest.
+#include <utility>
+
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -220,18 +226,227 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
     update_cell<R, S, TH, CORR>(A, c);
 }
 
+// ---- tiled update ---------------------------------------------------------
+// A block updates a tile of T3X x T3Y x T3Z cells.  Population by population,
+// the brackets of the tile and of the halo cells its stencils reach (two
+// cells beyond each face along each axis the population moves on: a cross,
+// no edges or corners) are staged in LDS, so a bracket is read from the
+// scratch buffer about once per tile rather than four times per axis and
+// cell.  The arithmetic is that of fv3_update, in the same order.
+constexpr int T3X = 32, T3Y = 4, T3Z = 4, T3N = T3X * T3Y * T3Z;
+constexpr int T3PD = 3;   // populations whose staged loads are in flight ahead of the one being updated
+constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
+static_assert(T3Y == 4 && T3Z == 4, "one thread per halo cell: the four halo rows / planes map to the tile's four");
+static_assert(4 * T3Y * T3Z <= T3N, "x halo cells fit the block");
+__device__ constexpr int l3(int x, int y, int z) { return ((z + 2) * L3Y + (y + 2)) * L3X + (x + 2); }
+
+// Source of one staged bracket: the cell it is read at, whether that is a
+// wall mirror (the opposite population is read) and at which z wall the
+// thermal bracket is anti-reflected.  Positions more than two cells outside
+// the domain, or outside along two axes, are never read by a cell's stencil
+// and are not loaded.
+enum { SRC_VALID = 1, SRC_MIRROR = 2, SRC_ZLO = 4, SRC_ZHI = 8 };
+struct Src3 {
+    int64_t cell;
+    int flags;
+};
+
+template <class R>
+__device__ inline Src3 src3(const Fv3Args<R>& A, const int* g) {
+    int p[3], out = 0, flags = SRC_VALID;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int q = g[d], n = A.n[d];
+        if (q >= 0 && q < n) {
+            p[d] = q;
+            continue;
+        }
+        if (q < -2 || q > n + 1) return Src3{0, 0};
+        ++out;
+        if (!A.wall[d]) {
+            p[d] = q < 0 ? q + n : q - n;
+        } else {
+            p[d] = q < 0 ? -q - 1 : 2 * n - 1 - q;
+            flags |= SRC_MIRROR;
+            if (d == 2) flags |= q < 0 ? SRC_ZLO : SRC_ZHI;
+        }
+    }
+    if (out > 1) return Src3{0, 0};
+    return Src3{(int64_t(p[2]) * A.n[1] + p[1]) * A.n[0] + p[0], flags};
+}
+
+// bracket of population a of species s at a staged source (as phi_at)
+template <class R, int s, int a>
+__device__ inline R fetch3(const Fv3Args<R>& A, const Src3& q) {
+    if (!(q.flags & SRC_VALID)) return R(0);
+    const int b = (q.flags & SRC_MIRROR) ? opp3(a) : a;
+    const R v = A.phi[int64_t(s * 18 + b - 1) * A.cells + q.cell];
+    if (s == 0 || !(q.flags & (SRC_ZLO | SRC_ZHI))) return v;
+    return R(2) * w3<R>(a) * (((q.flags & SRC_ZLO) ? A.Tb : A.Tt) - A.k.ref_g) - v;
+}
+
+// the staged values one thread contributes for population (s, a): its own
+// position and one halo cell along each axis the population moves on
+template <class R>
+struct Stage3 {
+    R own, x, y, z;
+};
+template <class R, int s, int a>
+__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q) {
+    Stage3<R> v;
+    v.own = fetch3<R, s, a>(A, q[0]);
+    v.x = c3(a, 0) ? fetch3<R, s, a>(A, q[1]) : R(0);
+    v.y = c3(a, 1) ? fetch3<R, s, a>(A, q[2]) : R(0);
+    v.z = c3(a, 2) ? fetch3<R, s, a>(A, q[3]) : R(0);
+    return v;
+}
+
+// the first T3PD moving populations' staged values
+template <class R, bool TH, int p>
+__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, Stage3<R>* v) {
+    if constexpr (p < T3PD && p < 18 * (TH ? 2 : 1)) {
+        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q);
+        fetch_first<R, TH, p + 1>(A, q, v);
+    }
+}
+
+template <class R, class S, bool TH, bool CORR, int s, int a>
+__device__ __forceinline__ void tiled_pop(const Fv3Args<R>& A, R (*lds)[L3N], const Src3* q, const int* li,
+                                          const bool xh, Stage3<R>* v, const bool mine, const int64_t c,
+                                          const R* df, const R* dg, const Mac3<R, TH>& m, const R (*w)[8]) {
+    constexpr int NSP = TH ? 2 : 1;
+    const StageK<R>& k = A.k;
+    const int64_t e = int64_t(s * 19 + a) * A.cells + c;
+    R pm1, frc;
+    eqf3<R, TH>(m, a, pm1, frc);
+    const R d = s == 0 ? df[a] : dg[a];
+    R b = s == 0 ? k.omkc * d + w3<R>(a) * (k.kc * m.rho_p + m.rho * (k.kc * pm1 + k.kf * frc))
+                 : k.omkcg * d + k.kcg * w3<R>(a) * (m.T_p + m.T * pm1);
+    if (CORR && mine) b = R(0.5) * (b + R(Store3<S>::ld(static_cast<const S*>(A.src) + e)));
+    if (a > 0) {
+        constexpr int p = s * 18 + a - 1;   // moving population 0 .. 18 NSP - 1
+        R* L = lds[p & 1];
+        Stage3<R>& u = v[p % T3PD];
+        L[li[0]] = u.own;
+        if (c3(a, 0) && xh) L[li[1]] = u.x;
+        if (c3(a, 1)) L[li[2]] = u.y;
+        if (c3(a, 2)) L[li[3]] = u.z;
+        __syncthreads();
+        // later populations' loads are in flight during this one's flux
+        if constexpr (p + T3PD < 18 * NSP) {
+            constexpr int s2 = (p + T3PD) / 18, a2 = (p + T3PD) % 18 + 1;
+            u = fetch_pop<R, s2, a2>(A, q);
+        }
+#pragma unroll
+        for (int axis = 0; axis < 3; ++axis) {
+            const int cd = c3(a, axis);
+            if (cd == 0) continue;
+            const R* wq = w[axis] + (cd > 0 ? 0 : 4);
+            const int q0 = cd > 0 ? -2 : -1;
+            const int st = axis == 0 ? 1 : axis == 1 ? L3X : L3X * L3Y;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b -= wq[j] * L[li[0] + (q0 + j) * st];
+        }
+    }
+    if (mine) Store3<S>::st(static_cast<S*>(A.dst) + e, S(b));
+}
+
+template <class R, class S, bool TH, bool CORR, int s, int... as>
+__device__ __forceinline__ void tiled_species(const Fv3Args<R>& A, R (*lds)[L3N], const Src3* q, const int* li,
+                                              const bool xh, Stage3<R>* v, const bool mine, const int64_t c,
+                                              const R* df, const R* dg, const Mac3<R, TH>& m, const R (*w)[8],
+                                              std::integer_sequence<int, as...>) {
+    (tiled_pop<R, S, TH, CORR, s, as>(A, lds, q, li, xh, v, mine, c, df, dg, m, w), ...);
+}
+
+template <class R, class S, bool TH, bool CORR>
+__global__ void __launch_bounds__(T3N) fv3_update_tiled(Fv3Args<R> A) {
+    __shared__ R lds[2][L3N];
+    const int t = threadIdx.x;
+    const int tx = t % T3X, ty = (t / T3X) % T3Y, tz = t / (T3X * T3Y);
+    const int o[3] = {int(blockIdx.x) * T3X, int(blockIdx.y) * T3Y, int(blockIdx.z) * T3Z};
+    const int i[3] = {o[0] + tx, o[1] + ty, o[2] + tz};
+    const bool mine = i[0] < A.n[0] && i[1] < A.n[1] && i[2] < A.n[2];
+    // the four positions this thread stages: its own, an x-halo cell
+    // (threads 0 .. 4 T3Y T3Z - 1), a y-halo cell and a z-halo cell
+    Src3 q[4];
+    int li[4];
+    q[0] = src3(A, i);
+    li[0] = l3(tx, ty, tz);
+    const bool xh = t < 4 * T3Y * T3Z;
+    {
+        const int h = t & 3, hy = (t >> 2) & 3, hz = (t >> 4) & 3;
+        const int rx = h < 2 ? h - 2 : T3X + h - 2;
+        const int g[3] = {o[0] + rx, o[1] + hy, o[2] + hz};
+        q[1] = xh ? src3(A, g) : Src3{0, 0};
+        li[1] = l3(rx, hy, hz);
+    }
+    {
+        const int ry = ty < 2 ? ty - 2 : T3Y + ty - 2;
+        const int g[3] = {i[0], o[1] + ry, i[2]};
+        q[2] = src3(A, g);
+        li[2] = l3(tx, ry, tz);
+    }
+    {
+        const int rz = tz < 2 ? tz - 2 : T3Z + tz - 2;
+        const int g[3] = {i[0], i[1], o[2] + rz};
+        q[3] = src3(A, g);
+        li[3] = l3(tx, ty, rz);
+    }
+    Stage3<R> v[T3PD];
+    fetch_first<R, TH, 0>(A, q, v);
+    // own record (f~n in the corrector, else the stage input), macroscopic
+    // state and the flux weights of the cell along each axis
+    const int64_t c = mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
+    R df[19], dg[19], w[3][8];
+    Mac3<R, TH> m{};
+    if (mine) {
+        load3<R, S, TH>(static_cast<const S*>(CORR ? A.aux : A.src), A.cells, c, df, dg);
+        m = macro3<R, TH>(df, dg, A.k, A.az);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[d][j] = A.coef[d][int64_t(i[d]) * 8 + j];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 19; ++a) df[a] = dg[a] = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[d][j] = R(0);
+        m.rho = R(1);
+    }
+    tiled_species<R, S, TH, CORR, 0>(A, lds, q, li, xh, v, mine, c, df, dg, m, w,
+                                     std::make_integer_sequence<int, 19>{});
+    if constexpr (TH)
+        tiled_species<R, S, TH, CORR, 1>(A, lds, q, li, xh, v, mine, c, df, dg, m, w,
+                                         std::make_integer_sequence<int, 19>{});
+}
+
+template <class R, class S, bool TH, bool CORR>
+static void launch_update3(const Fv3Args<R>& A, hipStream_t st) {
+    if (A.gather) {
+        const dim3 grid(unsigned((A.cells + 255) / 256)), block(256);
+        hipLaunchKernelGGL((fv3_update<R, S, TH, CORR>), grid, block, 0, st, A);
+    } else {
+        const dim3 grid(unsigned((A.n[0] + T3X - 1) / T3X), unsigned((A.n[1] + T3Y - 1) / T3Y),
+                        unsigned((A.n[2] + T3Z - 1) / T3Z));
+        hipLaunchKernelGGL((fv3_update_tiled<R, S, TH, CORR>), grid, dim3(T3N), 0, st, A);
+    }
+}
+
 template <class R, class S>
 static hipError_t fv3_typed(bool thermal, bool corrector, const void* args, hipStream_t st) {
     const Fv3Args<R>& A = *static_cast<const Fv3Args<R>*>(args);
     const dim3 grid(unsigned((A.cells + 255) / 256)), block(256);
     if (thermal) {
         hipLaunchKernelGGL((fv3_stage<R, S, true>), grid, block, 0, st, A);
-        if (corrector) hipLaunchKernelGGL((fv3_update<R, S, true, true>), grid, block, 0, st, A);
-        else hipLaunchKernelGGL((fv3_update<R, S, true, false>), grid, block, 0, st, A);
+        if (corrector) launch_update3<R, S, true, true>(A, st);
+        else launch_update3<R, S, true, false>(A, st);
     } else {
         hipLaunchKernelGGL((fv3_stage<R, S, false>), grid, block, 0, st, A);
-        if (corrector) hipLaunchKernelGGL((fv3_update<R, S, false, true>), grid, block, 0, st, A);
-        else hipLaunchKernelGGL((fv3_update<R, S, false, false>), grid, block, 0, st, A);
+        if (corrector) launch_update3<R, S, false, true>(A, st);
+        else launch_update3<R, S, false, false>(A, st);
     }
     return hipGetLastError();
 }

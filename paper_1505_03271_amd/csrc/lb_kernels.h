@@ -144,6 +144,7 @@ struct Fv3Args {
     StageK<R> k;       // stage constants (k.ax, k.ay: x and y accelerations)
     R az;              // constant z acceleration (the Boussinesq term is added along z)
     R Tb, Tt;          // z wall temperatures
+    int gather;        // update kernel: 0 tiles staged in LDS, 1 one thread per cell with direct loads
 };
 // One FV stage (stage + update kernels) of a 3D simulation.
 hipError_t launch_fv3(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
