@@ -273,6 +273,8 @@ def main():
                     help="requests of the serving trace to replay (0: skip serving)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 512 MiB device to device (a kernel of known traffic for counter scaling)")
+    ap.add_argument("--only-3d", choices=("tiled", "gather"), default=None,
+                    help="run only the 3D 256^3 step with this update kernel (for profiling) and print its timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -292,6 +294,13 @@ def main():
         c.copy_(a)
         torch.cuda.synchronize()
         del a, c
+    if args.only_3d:
+        r = run_fv3d(lb, torch, 256, args.steps, args.warmup, update=args.only_3d)
+        (n1, t1), (n2, t2) = r["kernels"]["fv_first_pass"], r["kernels"]["fv_corrector"]
+        print(json.dumps({"fv3d_rb256_f32_mlups": round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1),
+                          "update": args.only_3d, "steps": args.steps,
+                          "pass_ms": [round(t1 / max(n1, 1), 3), round(t2 / max(n2, 1), 3)]}))
+        return
     cfg = workloads.rb4096_config()
     n = cfg["nx"]
     log(f"rb4096: dt={cfg['dt']:.3f} tau={cfg['tau']} H={cfg['H']:.0f}")

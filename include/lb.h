@@ -307,9 +307,9 @@ int lb_stream_probe(size_t bytes, void* stream, double* out);
  *   (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
  * (weights 1/3, 1/18, 1/36).  Field arrays are [nz][ny][nx] (x fastest),
  * population arrays [19][nz][ny][nx].  Storage LB_F64 or LB_F32 (offsets
- * p - w rho_ref, g - w T_ref).  Each FV stage runs two kernels (brackets to a
- * scratch buffer, then flux + update; see lb3_set_update).  Same error
- * conventions as above.
+ * p - w rho_ref, g - w T_ref).  Each FV stage computes the brackets of its
+ * input into a scratch buffer, then the flux divergence and the update
+ * (see lb3_set_update).  Same error conventions as above.
  * ====================================================================== */
 typedef struct lb3_params {
     int32_t nx, ny, nz;      /* cells, >= 4 each */
@@ -344,10 +344,12 @@ int lb3_get_populations(lb3_sim* sim, double* f, double* g);
 int lb3_diagnostics(lb3_sim* sim, double* out);
 /* Kernel of the flux + update half of each stage: 0 (default) tiles of
  * 32 x 4 x 4 cells whose brackets, with the halo cells their stencils
- * reach, are staged in LDS population by population; 1 one thread per cell
- * reading every stencil point from the scratch buffer.  Both compute the
- * same operations in the same order (bit-identical results).  LB_EINVAL
- * for another kind. */
+ * reach, are staged in LDS population by population; the kernel also
+ * leaves the brackets of its output for the next stage in a second scratch
+ * buffer, so the bracket kernel runs only after lb3_init.  1: one thread
+ * per cell reading every stencil point from the scratch buffer, after a
+ * bracket kernel in every stage.  Both compute the same operations in the
+ * same order (bit-identical results).  LB_EINVAL for another kind. */
 int lb3_set_update(lb3_sim* sim, int kind);
 /* HIP-event timing of the stage passes: launches[2], ms[2] = (first pass, corrector) */
 int lb3_set_timing(lb3_sim* sim, int on);

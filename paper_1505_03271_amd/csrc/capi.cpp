@@ -1175,7 +1175,9 @@ struct lb3_sim {
     hipStream_t stream = nullptr;
     void* A = nullptr;        // current state
     void* B = nullptr;        // predictor / next state
-    void* phi = nullptr;      // brackets of the moving populations, [nsp * 18][cells]
+    void* phi[2] = {nullptr, nullptr};  // brackets of the moving populations, [nsp * 18][cells]
+    int phi_cur = 0;          // phi[phi_cur] feeds the next pass
+    bool phi_ok = false;      // it holds the brackets of the current state (left by the tiled update)
     void* metric = nullptr;   // flux stencils: pass 0 (x, y, z), pass 1 (x, y, z), [n][8] each
     double* dxyz = nullptr;   // cell widths dx[nx], dy[ny], dz[nz]
     double* partial = nullptr;
@@ -1195,7 +1197,7 @@ struct lb3_sim {
 namespace {
 
 void release3(lb3_sim* s) {
-    for (void* q : {s->A, s->B, s->phi, s->metric, static_cast<void*>(s->dxyz), static_cast<void*>(s->partial),
+    for (void* q : {s->A, s->B, s->phi[0], s->phi[1], s->metric, static_cast<void*>(s->dxyz), static_cast<void*>(s->partial),
                     static_cast<void*>(s->dout)})
         if (q) (void)hipFree(q);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
@@ -1246,7 +1248,9 @@ Fv3Args<R> fv3_args(const lb3_sim* s, const void* src, void* dst, const void* au
     a.src = src;
     a.dst = dst;
     a.aux = aux;
-    a.phi = static_cast<R*>(s->phi);
+    a.phi = static_cast<R*>(s->phi[s->phi_cur]);
+    a.phi_next = s->gather ? nullptr : static_cast<R*>(s->phi[s->phi_cur ^ 1]);
+    a.stage = s->gather || !s->phi_ok;
     a.n[0] = s->p.nx;
     a.n[1] = s->p.ny;
     a.n[2] = s->p.nz;
@@ -1302,7 +1306,12 @@ int fv3_pass(lb3_sim* s, const void* src, void* dst, const void* aux, bool corre
         Fv3Args<float> a = fv3_args<float>(s, src, dst, aux, corrector);
         e = launch_fv3(s->p.storage, s->p.thermal, corrector, &a, s->stream);
     }
-    if (e != hipSuccess) return fail(LB_EDEVICE, "3D FV launch failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        s->phi_ok = false;
+        return fail(LB_EDEVICE, "3D FV launch failed: %s", hipGetErrorString(e));
+    }
+    if (!s->gather) s->phi_cur ^= 1;   // the tiled update left the brackets of dst there
+    s->phi_ok = !s->gather;
     return LB_OK;
 }
 
@@ -1334,7 +1343,8 @@ int lb3_create(const lb3_params* p, lb3_sim** out) {
         s->stream = static_cast<hipStream_t>(p->stream);
         hipError_t e;
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
-            (e = hipMalloc(&s->phi, size_t(s->nsp) * 18 * size_t(s->cells) * s->elem)) != hipSuccess ||
+            (e = hipMalloc(&s->phi[0], size_t(s->nsp) * 18 * size_t(s->cells) * s->elem)) != hipSuccess ||
+            (e = hipMalloc(&s->phi[1], size_t(s->nsp) * 18 * size_t(s->cells) * s->elem)) != hipSuccess ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess) {
             release3(s);
@@ -1419,6 +1429,7 @@ int lb3_init(lb3_sim* s, const double* rho, const double* ux, const double* uy, 
         if (e != hipSuccess) rc = fail(LB_EDEVICE, "lb3_init: %s", hipGetErrorString(e));
     }
     for (double* q : d) if (q) (void)hipFree(q);
+    s->phi_ok = false;   // brackets of the old state, if any
     if (rc == LB_OK) { s->has_init = true; s->unstable = false; }
     return rc;
 }
@@ -1522,6 +1533,7 @@ int lb3_set_update(lb3_sim* s, int kind) {
     if (int rc = check3(s)) return rc;
     if (kind != 0 && kind != 1) return fail(LB_EINVAL, "lb3_set_update: kind must be 0 (tiles) or 1 (per cell)");
     s->gather = kind;
+    s->phi_ok = false;
     return LB_OK;
 }
 

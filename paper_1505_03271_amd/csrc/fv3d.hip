@@ -16,10 +16,12 @@
 //                 Heun corrector:            (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*)
 // The flux + update kernel works on 32 x 4 x 4 tiles whose brackets and halo
 // brackets are staged in LDS population by population (fv3_update_tiled);
-// fv3_update, one thread per cell reading every stencil point from the
-// scratch buffer, computes the same operations in the same order.  The
-// two-kernel form moves the brackets through HBM once more than a fused
-// kernel would.
+// it also leaves the brackets of its output for the next pass in a second
+// scratch buffer, so that only the first pass after a new state runs the
+// stage kernel.  fv3_update, one thread per cell reading every stencil point
+// from the scratch buffer, computes the same operations in the same order.
+// The scratch round trip moves the brackets through HBM once more than a
+// fused kernel would.
 //
 // Storage: FP64 (parity path) or FP32 offsets p - w_a ref, populations as
 // (s * 19 + a) * cells + cell, x fastest.
@@ -121,6 +123,22 @@ __device__ inline void base3(const R* df, const R* dg, const Mac3<R, TH>& m, con
     }
 }
 
+// brackets phi - w ref (f) and phi - w ref_g (g) of the 18 moving
+// populations of a decoded cell, written to phi[(s * 18 + a - 1) * cells + c]
+template <class R, bool TH, int a>
+__device__ __forceinline__ void bracket3(const StageK<R>& k, const R* df, const R* dg, const Mac3<R, TH>& m, R* phi,
+                                         const int64_t cells, const int64_t c) {
+    R pm1, frc;
+    eqf3<R, TH>(m, a, pm1, frc);
+    phi[int64_t(a - 1) * cells + c] = k.omk1 * df[a] + w3<R>(a) * (k.k1 * m.rho_p + m.rho * (k.k1 * pm1 + k.kh * frc));
+    if (TH) phi[int64_t(18 + a - 1) * cells + c] = k.omk1g * dg[a] + k.k1g * w3<R>(a) * (m.T_p + m.T * pm1);
+}
+template <class R, bool TH, int... as>
+__device__ __forceinline__ void brackets3(const StageK<R>& k, const R* df, const R* dg, const Mac3<R, TH>& m, R* phi,
+                                          const int64_t cells, const int64_t c, std::integer_sequence<int, as...>) {
+    (bracket3<R, TH, as + 1>(k, df, dg, m, phi, cells, c), ...);
+}
+
 template <class R, class S, bool TH>
 __global__ void __launch_bounds__(256) fv3_stage(Fv3Args<R> A) {
     const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -128,17 +146,7 @@ __global__ void __launch_bounds__(256) fv3_stage(Fv3Args<R> A) {
     R df[19], dg[19];
     load3<R, S, TH>(static_cast<const S*>(A.src), A.cells, c, df, dg);
     const Mac3<R, TH> m = macro3<R, TH>(df, dg, A.k, A.az);
-    const StageK<R>& k = A.k;
-#pragma unroll
-    for (int a = 1; a < 19; ++a) {
-        R pm1, frc;
-        eqf3<R, TH>(m, a, pm1, frc);
-        // phi - w ref (f) and phi - w ref_g (g)
-        A.phi[int64_t(a - 1) * A.cells + c] =
-            k.omk1 * df[a] + w3<R>(a) * (k.k1 * m.rho_p + m.rho * (k.k1 * pm1 + k.kh * frc));
-        if (TH)
-            A.phi[int64_t(18 + a - 1) * A.cells + c] = k.omk1g * dg[a] + k.k1g * w3<R>(a) * (m.T_p + m.T * pm1);
-    }
+    brackets3<R, TH>(A.k, df, dg, m, A.phi, A.cells, c, std::make_integer_sequence<int, 18>{});
 }
 
 // bracket of population a of species s at index q along `axis` of the cell
@@ -234,17 +242,18 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
 // scratch buffer about once per tile rather than four times per axis and
 // cell.  The arithmetic is that of fv3_update, in the same order.
 constexpr int T3X = 32, T3Y = 4, T3Z = 4, T3N = T3X * T3Y * T3Z;
+constexpr int T3G = 1;    // moving populations staged per barrier
 constexpr int T3PD = 3;   // populations whose staged loads are in flight ahead of the one being updated
 constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
 static_assert(T3Y == 4 && T3Z == 4, "one thread per halo cell: the four halo rows / planes map to the tile's four");
-static_assert(4 * T3Y * T3Z <= T3N, "x halo cells fit the block");
+static_assert(4 * T3Y * T3Z == 64, "the x-halo cells are one wave");
+static_assert(18 % T3G == 0, "groups of populations divide a species");
 __device__ constexpr int l3(int x, int y, int z) { return ((z + 2) * L3Y + (y + 2)) * L3X + (x + 2); }
 
 // Source of one staged bracket: the cell it is read at, whether that is a
 // wall mirror (the opposite population is read) and at which z wall the
 // thermal bracket is anti-reflected.  Positions more than two cells outside
-// the domain, or outside along two axes, are never read by a cell's stencil
-// and are not loaded.
+// the domain, or outside along two axes, are never read by a cell's stencil.
 enum { SRC_VALID = 1, SRC_MIRROR = 2, SRC_ZLO = 4, SRC_ZHI = 8 };
 struct Src3 {
     int64_t cell;
@@ -275,27 +284,37 @@ __device__ inline Src3 src3(const Fv3Args<R>& A, const int* g) {
     return Src3{(int64_t(p[2]) * A.n[1] + p[1]) * A.n[0] + p[0], flags};
 }
 
-// bracket of population a of species s at a staged source (as phi_at)
+// bracket of population a of species s at a staged source, as read (the
+// thermal anti-reflection at a z wall is applied when it is staged, so that
+// the load can stay in flight until then).  Positions that no stencil reads
+// point at cell 0 and are loaded all the same: branch-free loads keep the
+// compiler's count of loads in flight exact.
 template <class R, int s, int a>
 __device__ inline R fetch3(const Fv3Args<R>& A, const Src3& q) {
-    if (!(q.flags & SRC_VALID)) return R(0);
     const int b = (q.flags & SRC_MIRROR) ? opp3(a) : a;
-    const R v = A.phi[int64_t(s * 18 + b - 1) * A.cells + q.cell];
-    if (s == 0 || !(q.flags & (SRC_ZLO | SRC_ZHI))) return v;
-    return R(2) * w3<R>(a) * (((q.flags & SRC_ZLO) ? A.Tb : A.Tt) - A.k.ref_g) - v;
+    return A.phi[int64_t(s * 18 + b - 1) * A.cells + q.cell];
 }
 
-// the staged values one thread contributes for population (s, a): its own
-// position and one halo cell along each axis the population moves on
+// the staged value of a fetched bracket (as phi_at): at a z wall the
+// thermal bracket is anti-reflected, 2 w (T_w - ref_g) - phi_inv, with
+// zw = 2 (T_w - ref_g) of the position (the same exact product)
+template <class R, int s, int a>
+__device__ inline R staged3(const Src3& q, const R zw, const R v) {
+    if (s == 0 || !(q.flags & (SRC_ZLO | SRC_ZHI))) return v;
+    return w3<R>(a) * zw - v;
+}
+
+// the values one thread stages for population (s, a): its own position and
+// one halo cell along each axis the population moves on
 template <class R>
 struct Stage3 {
     R own, x, y, z;
 };
 template <class R, int s, int a>
-__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q) {
+__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const bool xh) {
     Stage3<R> v;
     v.own = fetch3<R, s, a>(A, q[0]);
-    v.x = c3(a, 0) ? fetch3<R, s, a>(A, q[1]) : R(0);
+    v.x = c3(a, 0) && xh ? fetch3<R, s, a>(A, q[1]) : R(0);
     v.y = c3(a, 1) ? fetch3<R, s, a>(A, q[2]) : R(0);
     v.z = c3(a, 2) ? fetch3<R, s, a>(A, q[3]) : R(0);
     return v;
@@ -303,124 +322,186 @@ __device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q) {
 
 // the first T3PD moving populations' staged values
 template <class R, bool TH, int p>
-__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, Stage3<R>* v) {
+__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, Stage3<R>* v) {
     if constexpr (p < T3PD && p < 18 * (TH ? 2 : 1)) {
-        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q);
-        fetch_first<R, TH, p + 1>(A, q, v);
+        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh);
+        fetch_first<R, TH, p + 1>(A, q, xh, v);
     }
 }
 
+// Everything a thread of the tiled kernel carries from population to population.
+template <class R, bool TH>
+struct Tile3 {
+    Src3 q[4];        // staged positions: own, x halo, y halo, z halo
+    int li[4];        // their LDS indices
+    bool xh, mine;    // stages an x-halo cell (wave 0); owns a cell of the domain
+    R zw[4];          // 2 (T_w - ref_g) at the z wall a staged position mirrors (else 0)
+    int64_t c;        // own cell (cell 0 for threads outside the domain)
+    R bf[19], bg[19]; // own record, then its collision bases, then the new values
+    R w[3][8];        // flux weights of the own position along each axis
+};
+
+// collision bases of the own cell in place of its record (Heun corrector:
+// (f~n + C(f~n) + f~*) / 2), as in fv3_update.  The new values are stored
+// only after every population's flux: vector loads and stores share one
+// completion counter, so a store issued between a staged load and its use
+// would make that use wait for the store as well.
 template <class R, class S, bool TH, bool CORR, int s, int a>
-__device__ __forceinline__ void tiled_pop(const Fv3Args<R>& A, R (*lds)[L3N], const Src3* q, const int* li,
-                                          const bool xh, Stage3<R>* v, const bool mine, const int64_t c,
-                                          const R* df, const R* dg, const Mac3<R, TH>& m, const R (*w)[8]) {
-    constexpr int NSP = TH ? 2 : 1;
+__device__ __forceinline__ void tile_base(const Fv3Args<R>& A, Tile3<R, TH>& T, const Mac3<R, TH>& m) {
     const StageK<R>& k = A.k;
-    const int64_t e = int64_t(s * 19 + a) * A.cells + c;
     R pm1, frc;
     eqf3<R, TH>(m, a, pm1, frc);
-    const R d = s == 0 ? df[a] : dg[a];
+    R& d = s == 0 ? T.bf[a] : T.bg[a];
     R b = s == 0 ? k.omkc * d + w3<R>(a) * (k.kc * m.rho_p + m.rho * (k.kc * pm1 + k.kf * frc))
                  : k.omkcg * d + k.kcg * w3<R>(a) * (m.T_p + m.T * pm1);
-    if (CORR && mine) b = R(0.5) * (b + R(Store3<S>::ld(static_cast<const S*>(A.src) + e)));
-    if (a > 0) {
-        constexpr int p = s * 18 + a - 1;   // moving population 0 .. 18 NSP - 1
-        R* L = lds[p & 1];
-        Stage3<R>& u = v[p % T3PD];
-        L[li[0]] = u.own;
-        if (c3(a, 0) && xh) L[li[1]] = u.x;
-        if (c3(a, 1)) L[li[2]] = u.y;
-        if (c3(a, 2)) L[li[3]] = u.z;
-        __syncthreads();
-        // later populations' loads are in flight during this one's flux
-        if constexpr (p + T3PD < 18 * NSP) {
-            constexpr int s2 = (p + T3PD) / 18, a2 = (p + T3PD) % 18 + 1;
-            u = fetch_pop<R, s2, a2>(A, q);
-        }
-#pragma unroll
-        for (int axis = 0; axis < 3; ++axis) {
-            const int cd = c3(a, axis);
-            if (cd == 0) continue;
-            const R* wq = w[axis] + (cd > 0 ? 0 : 4);
-            const int q0 = cd > 0 ? -2 : -1;
-            const int st = axis == 0 ? 1 : axis == 1 ? L3X : L3X * L3Y;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b -= wq[j] * L[li[0] + (q0 + j) * st];
-        }
-    }
-    if (mine) Store3<S>::st(static_cast<S*>(A.dst) + e, S(b));
+    if (CORR) b = R(0.5) * (b + R(Store3<S>::ld(static_cast<const S*>(A.src) + int64_t(s * 19 + a) * A.cells + T.c)));
+    d = b;
 }
-
 template <class R, class S, bool TH, bool CORR, int s, int... as>
-__device__ __forceinline__ void tiled_species(const Fv3Args<R>& A, R (*lds)[L3N], const Src3* q, const int* li,
-                                              const bool xh, Stage3<R>* v, const bool mine, const int64_t c,
-                                              const R* df, const R* dg, const Mac3<R, TH>& m, const R (*w)[8],
-                                              std::integer_sequence<int, as...>) {
-    (tiled_pop<R, S, TH, CORR, s, as>(A, lds, q, li, xh, v, mine, c, df, dg, m, w), ...);
+__device__ __forceinline__ void tile_bases(const Fv3Args<R>& A, Tile3<R, TH>& T, const Mac3<R, TH>& m,
+                                           std::integer_sequence<int, as...>) {
+    (tile_base<R, S, TH, CORR, s, as>(A, T, m), ...);
 }
 
+// the new values (indices fixed at compile time, so the arrays stay in registers)
+template <class R, class S, bool TH, int s, int... as>
+__device__ __forceinline__ void tile_stores(const Fv3Args<R>& A, const Tile3<R, TH>& T,
+                                            std::integer_sequence<int, as...>) {
+    S* dst = static_cast<S*>(A.dst);
+    ((Store3<S>::st(dst + int64_t(s * 19 + as) * A.cells + T.c, S(s == 0 ? T.bf[as] : T.bg[as]))), ...);
+}
+
+// Moving populations are staged T3G at a time (one barrier per group):
+// write the group's staged values, synchronise, put the loads of later
+// populations in flight, then apply the group's fluxes.
+template <class R, bool TH, int p>
+__device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3N], const Tile3<R, TH>& T,
+                                           const Stage3<R>* v) {
+    constexpr int s = p / 18, a = p % 18 + 1;
+    R* L = lds[(p / T3G) & 1][p % T3G];
+    const Stage3<R>& u = v[p % T3PD];
+    L[T.li[0]] = staged3<R, s, a>(T.q[0], T.zw[0], u.own);
+    if (c3(a, 0) && T.xh) L[T.li[1]] = staged3<R, s, a>(T.q[1], T.zw[1], u.x);
+    if (c3(a, 1)) L[T.li[2]] = staged3<R, s, a>(T.q[2], T.zw[2], u.y);
+    if (c3(a, 2)) L[T.li[3]] = staged3<R, s, a>(T.q[3], T.zw[3], u.z);
+}
+
+template <class R, bool TH, int p>
+__device__ __forceinline__ void tile_prefetch(const Fv3Args<R>& A, const Tile3<R, TH>& T, Stage3<R>* v) {
+    if constexpr (p + T3PD < 18 * (TH ? 2 : 1)) {
+        constexpr int p2 = p + T3PD;
+        v[p % T3PD] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh);
+    }
+}
+
+template <class R, class S, bool TH, bool CORR, int p>
+__device__ __forceinline__ void tile_update(const Fv3Args<R>& A, R (*lds)[T3G][L3N], Tile3<R, TH>& T) {
+    constexpr int s = p / 18, a = p % 18 + 1;
+    const R* L = lds[(p / T3G) & 1][p % T3G];
+    R& b = s == 0 ? T.bf[a] : T.bg[a];
+#pragma unroll
+    for (int axis = 0; axis < 3; ++axis) {
+        const int cd = c3(a, axis);
+        if (cd == 0) continue;
+        const R* wq = T.w[axis] + (cd > 0 ? 0 : 4);
+        const int q0 = cd > 0 ? -2 : -1;
+        const int st = axis == 0 ? 1 : axis == 1 ? L3X : L3X * L3Y;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b -= wq[j] * L[T.li[0] + (q0 + j) * st];
+    }
+    // the value is final here: keep the compiler from sinking this
+    // population's arithmetic (and its LDS values) down to the stores
+    asm volatile("" : "+v"(b));
+}
+
+template <class R, class S, bool TH, bool CORR, int g, int... js>
+__device__ __forceinline__ void tile_group(const Fv3Args<R>& A, R (*lds)[T3G][L3N], Tile3<R, TH>& T,
+                                           Stage3<R>* v, std::integer_sequence<int, js...>) {
+    (tile_write<R, TH, g * T3G + js>(A, lds, T, v), ...);
+    __syncthreads();
+    (tile_prefetch<R, TH, g * T3G + js>(A, T, v), ...);
+    (tile_update<R, S, TH, CORR, g * T3G + js>(A, lds, T), ...);
+}
+
+template <class R, class S, bool TH, bool CORR, int... gs>
+__device__ __forceinline__ void tile_groups(const Fv3Args<R>& A, R (*lds)[T3G][L3N], Tile3<R, TH>& T,
+                                            Stage3<R>* v, std::integer_sequence<int, gs...>) {
+    (tile_group<R, S, TH, CORR, gs>(A, lds, T, v, std::make_integer_sequence<int, T3G>{}), ...);
+}
+
+// The tile's new state and, when phi_next is set, the brackets of that state
+// for the next stage (the stage kernel's arithmetic on the same values), so
+// that the next pass needs no stage kernel.
 template <class R, class S, bool TH, bool CORR>
 __global__ void __launch_bounds__(T3N) fv3_update_tiled(Fv3Args<R> A) {
-    __shared__ R lds[2][L3N];
+    __shared__ R lds[2][T3G][L3N];
     const int t = threadIdx.x;
     const int tx = t % T3X, ty = (t / T3X) % T3Y, tz = t / (T3X * T3Y);
     const int o[3] = {int(blockIdx.x) * T3X, int(blockIdx.y) * T3Y, int(blockIdx.z) * T3Z};
     const int i[3] = {o[0] + tx, o[1] + ty, o[2] + tz};
-    const bool mine = i[0] < A.n[0] && i[1] < A.n[1] && i[2] < A.n[2];
+    Tile3<R, TH> T;
+    T.mine = i[0] < A.n[0] && i[1] < A.n[1] && i[2] < A.n[2];
     // the four positions this thread stages: its own, an x-halo cell
-    // (threads 0 .. 4 T3Y T3Z - 1), a y-halo cell and a z-halo cell
-    Src3 q[4];
-    int li[4];
-    q[0] = src3(A, i);
-    li[0] = l3(tx, ty, tz);
-    const bool xh = t < 4 * T3Y * T3Z;
+    // (wave 0 only), a y-halo cell and a z-halo cell
+    T.q[0] = src3(A, i);
+    T.li[0] = l3(tx, ty, tz);
+    T.xh = __builtin_amdgcn_readfirstlane(t) < 4 * T3Y * T3Z;   // a uniform branch
     {
         const int h = t & 3, hy = (t >> 2) & 3, hz = (t >> 4) & 3;
         const int rx = h < 2 ? h - 2 : T3X + h - 2;
         const int g[3] = {o[0] + rx, o[1] + hy, o[2] + hz};
-        q[1] = xh ? src3(A, g) : Src3{0, 0};
-        li[1] = l3(rx, hy, hz);
+        T.q[1] = T.xh ? src3(A, g) : Src3{0, 0};
+        T.li[1] = l3(rx, hy, hz);
     }
     {
         const int ry = ty < 2 ? ty - 2 : T3Y + ty - 2;
         const int g[3] = {i[0], o[1] + ry, i[2]};
-        q[2] = src3(A, g);
-        li[2] = l3(tx, ry, tz);
+        T.q[2] = src3(A, g);
+        T.li[2] = l3(tx, ry, tz);
     }
     {
         const int rz = tz < 2 ? tz - 2 : T3Z + tz - 2;
         const int g[3] = {i[0], i[1], o[2] + rz};
-        q[3] = src3(A, g);
-        li[3] = l3(tx, ty, rz);
+        T.q[3] = src3(A, g);
+        T.li[3] = l3(tx, ty, rz);
+    }
+    {
+        const R zlo = R(2) * (A.Tb - A.k.ref_g), zhi = R(2) * (A.Tt - A.k.ref_g);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            T.zw[k] = (T.q[k].flags & SRC_ZLO) ? zlo : (T.q[k].flags & SRC_ZHI) ? zhi : R(0);
     }
     Stage3<R> v[T3PD];
-    fetch_first<R, TH, 0>(A, q, v);
-    // own record (f~n in the corrector, else the stage input), macroscopic
-    // state and the flux weights of the cell along each axis
-    const int64_t c = mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
-    R df[19], dg[19], w[3][8];
-    Mac3<R, TH> m{};
-    if (mine) {
-        load3<R, S, TH>(static_cast<const S*>(CORR ? A.aux : A.src), A.cells, c, df, dg);
-        m = macro3<R, TH>(df, dg, A.k, A.az);
+    fetch_first<R, TH, 0>(A, T.q, T.xh, v);
+    // own record, macroscopic state and the flux weights of the cell along
+    // each axis (threads outside the domain read cell 0 and the last
+    // weights, without branches, and store nothing)
+    T.c = T.mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
+    load3<R, S, TH>(static_cast<const S*>(CORR ? A.aux : A.src), A.cells, T.c, T.bf, T.bg);
+    if constexpr (!TH)
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 19; ++a) T.bg[a] = R(0);
+    {
+        const Mac3<R, TH> m = macro3<R, TH>(T.bf, T.bg, A.k, A.az);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[d][j] = A.coef[d][int64_t(i[d]) * 8 + j];
-    } else {
+        for (int d = 0; d < 3; ++d) {
+            const int64_t id = i[d] < A.n[d] ? i[d] : A.n[d] - 1;
 #pragma unroll
-        for (int a = 0; a < 19; ++a) df[a] = dg[a] = R(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) w[d][j] = R(0);
-        m.rho = R(1);
+            for (int j = 0; j < 8; ++j) T.w[d][j] = A.coef[d][id * 8 + j];
+        }
+        tile_bases<R, S, TH, CORR, 0>(A, T, m, std::make_integer_sequence<int, 19>{});
+        if constexpr (TH) tile_bases<R, S, TH, CORR, 1>(A, T, m, std::make_integer_sequence<int, 19>{});
     }
-    tiled_species<R, S, TH, CORR, 0>(A, lds, q, li, xh, v, mine, c, df, dg, m, w,
-                                     std::make_integer_sequence<int, 19>{});
-    if constexpr (TH)
-        tiled_species<R, S, TH, CORR, 1>(A, lds, q, li, xh, v, mine, c, df, dg, m, w,
-                                         std::make_integer_sequence<int, 19>{});
+    constexpr int NG = 18 * (TH ? 2 : 1) / T3G;
+    tile_groups<R, S, TH, CORR>(A, lds, T, v, std::make_integer_sequence<int, NG>{});
+    if (T.mine) {
+        tile_stores<R, S, TH, 0>(A, T, std::make_integer_sequence<int, 19>{});
+        if constexpr (TH) tile_stores<R, S, TH, 1>(A, T, std::make_integer_sequence<int, 19>{});
+        if (A.phi_next) {
+            const Mac3<R, TH> m = macro3<R, TH>(T.bf, T.bg, A.k, A.az);
+            brackets3<R, TH>(A.k, T.bf, T.bg, m, A.phi_next, A.cells, T.c, std::make_integer_sequence<int, 18>{});
+        }
+    }
 }
 
 template <class R, class S, bool TH, bool CORR>
@@ -440,11 +521,11 @@ static hipError_t fv3_typed(bool thermal, bool corrector, const void* args, hipS
     const Fv3Args<R>& A = *static_cast<const Fv3Args<R>*>(args);
     const dim3 grid(unsigned((A.cells + 255) / 256)), block(256);
     if (thermal) {
-        hipLaunchKernelGGL((fv3_stage<R, S, true>), grid, block, 0, st, A);
+        if (A.stage) hipLaunchKernelGGL((fv3_stage<R, S, true>), grid, block, 0, st, A);
         if (corrector) launch_update3<R, S, true, true>(A, st);
         else launch_update3<R, S, true, false>(A, st);
     } else {
-        hipLaunchKernelGGL((fv3_stage<R, S, false>), grid, block, 0, st, A);
+        if (A.stage) hipLaunchKernelGGL((fv3_stage<R, S, false>), grid, block, 0, st, A);
         if (corrector) launch_update3<R, S, false, true>(A, st);
         else launch_update3<R, S, false, false>(A, st);
     }

@@ -136,7 +136,9 @@ struct Fv3Args {
     const void* src;   // state read by the stage and at the own cell (f~n, or f~* in the corrector)
     void* dst;         // new state
     const void* aux;   // corrector: f~n at the own cell; NULL otherwise
-    R* phi;            // scratch: [nsp * 18][cells] brackets
+    R* phi;            // scratch: [nsp * 18][cells] brackets of src
+    R* phi_next;       // tiled update: where to put the brackets of dst for the next pass, or NULL
+    int stage;         // 1: compute phi from src first (stage kernel); 0: phi already holds them
     int n[3];
     int wall[3];       // per axis: 0 periodic, 1 wall
     int64_t cells;
