@@ -265,7 +265,8 @@ void lb_group_destroy(lb_group* group);
  * LB_EINVAL for a non-Heun member or a storage/thermal mismatch, LB_ESTATE
  * without a state, LB_ENOMEM when all slots are taken.  Synchronises. */
 int lb_group_add(lb_group* group, lb_sim* sim, int64_t steps, int32_t* slot);
-/* Leave (finished or not); the slot becomes free.  Synchronises. */
+/* Leave (finished or not); the slot becomes free and the simulation takes
+ * its own automatic item height again.  Synchronises. */
 int lb_group_remove(lb_group* group, int32_t slot);
 /* Rows per work item of the members' launches: 0 (the default) chooses them
  * at each membership change from the members' strips and the number of

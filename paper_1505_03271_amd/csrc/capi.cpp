@@ -1103,6 +1103,7 @@ int lb_group_remove(lb_group* g, int32_t slot) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     const int64_t zero = 0;
     HIP_TRY(hipMemcpy(g->d_left + slot, &zero, sizeof zero, hipMemcpyHostToDevice));
+    g->sims[slot]->chunk_h = 0;   // alone again: its own automatic item height
     g->sims[slot] = nullptr;
     g->dirty = true;
     bool any = false;
