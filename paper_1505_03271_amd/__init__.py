@@ -107,6 +107,7 @@ def lib():
             "lb_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
             "lb_set_fv_chunk": ([h, ctypes.c_int], ctypes.c_int),
             "lb_set_fv_lanes": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_set_st_pairs": ([h, ctypes.c_int], ctypes.c_int),
             "lb_rebase": ([h], ctypes.c_int),
             "lb_set_rebase": ([h, ctypes.c_int64], ctypes.c_int),
             "lb_device_bytes": ([h], ctypes.c_size_t),
@@ -311,6 +312,9 @@ class Sim:
 
     def set_fv_lanes(self, lanes):
         _check(lib().lb_set_fv_lanes(self.h, int(lanes)))
+
+    def set_st_pairs(self, on):
+        _check(lib().lb_set_st_pairs(self.h, int(bool(on))))
 
     def set_fv_chunk(self, rows):
         _check(lib().lb_set_fv_chunk(self.h, int(rows)))

@@ -156,6 +156,7 @@ struct lb_sim {
     std::vector<double> xf, yf;
     int chunk_h = 0;
     int lanes = 0;            // FV item width: 0 chosen from nx, or FV_LANES / FV_NARROW
+    int st_pairs = 1;         // ST, 16-bit storage: two cells per thread where nx is even
     // timing
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -361,6 +362,7 @@ int st_launch(lb_sim* s) {
     a.ref_f = s->p.storage == LB_F64 ? 0.0 : s->p.rho_ref;
     a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
     a.tref = s->tref;
+    a.pairs = s->st_pairs;
     int rc = record_event(s, 2);
     if (rc) return rc;
     hipError_t e = launch_st(s->p.storage, s->p.thermal, (s->p.flags & LB_FLAG_STREAM_ONLY) != 0, a, s->stream);
@@ -891,6 +893,13 @@ int lb_set_rebase(lb_sim* s, int64_t every) {
     if (every < 0) return fail(LB_EINVAL, "lb_set_rebase: negative interval");
     s->rebase_every = every;
     s->since_rebase = 0;
+    return LB_OK;
+}
+
+int lb_set_st_pairs(lb_sim* s, int on) {
+    if (int rc = check_sim(s)) return rc;
+    if (on != 0 && on != 1) return fail(LB_EINVAL, "lb_set_st_pairs: on must be 0 or 1");
+    s->st_pairs = on;
     return LB_OK;
 }
 

@@ -62,7 +62,10 @@ __device__ inline uint16_t float_to_bf16_bits(float x) {
 template <> struct Codec<bf16_t> {
     static constexpr bool offset = true;
     template <class R> __device__ static R load(const bf16_t* p) { return R(bf16_bits_to_float(p->bits)); }
-    template <class R> __device__ static void store(bf16_t* p, R v) { p->bits = float_to_bf16_bits(float(v)); }
+    // v_cvt_pk_bf16_f32: round to nearest even, as float_to_bf16_bits for finite values
+    template <class R> __device__ static void store(bf16_t* p, R v) {
+        p->bits = __builtin_bit_cast(uint16_t, (__bf16)float(v));
+    }
 };
 
 template <> struct Codec<f16_t> {

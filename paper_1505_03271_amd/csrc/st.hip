@@ -13,55 +13,34 @@
 
 namespace lbk {
 
-template <class R, class S, bool TH, bool RAW>
-__global__ void __launch_bounds__(256) st_step(StArgs A) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= A.nx) return;
-    const int64_t plane = A.plane;
+// destination slot of population a of the cell (i, j): the neighbour's slot,
+// or the opposite slot of the cell itself beyond a wall; yhit = -1 / +1 for a
+// bottom / top wall hit (the thermal anti-bounce-back), drow the row written
+struct StDest {
+    int64_t slot;
+    int yhit, drow;
+};
+__device__ inline StDest st_dest(const StArgs& A, const int i, const int j, const int a) {
+    int ti = i + cx(a), tj = j + cy(a);
+    bool hit = false;
+    StDest d;
+    d.yhit = 0;
+    if (tj < 0 || tj >= A.ny) {
+        if (A.wall_y) { hit = true; d.yhit = tj < 0 ? -1 : 1; } else tj = tj < 0 ? tj + A.ny : tj - A.ny;
+    }
+    if (ti < 0 || ti >= A.nx) {
+        if (A.wall_x) hit = true; else ti = ti < 0 ? ti + A.nx : ti - A.nx;
+    }
     const int64_t cell = int64_t(j) * A.nx + i;
-    const S* src = static_cast<const S*>(A.src);
-    S* dst = static_cast<S*>(A.dst);
+    d.slot = hit ? int64_t(opp(a)) * A.plane + cell : int64_t(a) * A.plane + int64_t(tj) * A.nx + ti;
+    d.drow = hit ? j : tj;
+    return d;
+}
 
-    // destination slot of each population
-    int64_t slot[9];
-    int yhit[9], drow[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        int ti = i + cx(a), tj = j + cy(a);
-        bool hit = false;
-        yhit[a] = 0;
-        if (tj < 0 || tj >= A.ny) {
-            if (A.wall_y) { hit = true; yhit[a] = tj < 0 ? -1 : 1; } else tj = tj < 0 ? tj + A.ny : tj - A.ny;
-        }
-        if (ti < 0 || ti >= A.nx) {
-            if (A.wall_x) hit = true; else ti = ti < 0 ? ti + A.nx : ti - A.nx;
-        }
-        slot[a] = hit ? int64_t(opp(a)) * plane + cell : int64_t(a) * plane + int64_t(tj) * A.nx + ti;
-        drow[a] = hit ? j : tj;
-    }
-
-    if (RAW) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            dst[slot[a]] = src[int64_t(a) * plane + cell];
-            if (TH) dst[9 * plane + slot[a]] = src[9 * plane + int64_t(a) * plane + cell];
-        }
-        return;
-    }
-
-    // g is stored relative to the row's thermal reference when one is kept
-    const R rf = R(A.ref_f), rg = A.tref ? R(A.tref[j]) : R(A.ref_g);
-    R f[9], g[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        R x = Codec<S>::template load<R>(src + a * plane + cell);
-        f[a] = Codec<S>::offset ? x + wt<R>(a) * rf : x;
-        if (TH) {
-            R y = Codec<S>::template load<R>(src + (9 + a) * plane + cell);
-            g[a] = Codec<S>::offset ? y + wt<R>(a) * rg : y;
-        }
-    }
+// the collision of one cell from its decoded populations: f' and g' of
+// every population before the wall rules and the storage offsets
+template <class R, bool TH>
+__device__ __forceinline__ void st_collide(const StArgs& A, const R* f, const R* g, R* fp, R* gp) {
     StageConst<R> k;
     k.hdt = R(0.5);
     k.ax = R(A.ax);
@@ -74,19 +53,130 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
     Macro<R> m = macro<R, TH>(f, g, k);
     EqForce<R> e;
     eq_force(m, e);
-    const R Tb = R(A.T_bottom), Tt = R(A.T_top);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const R wr = wt<R>(a) * m.rho;
-        R fp = f[a] + kc * (wr * e.poly[a] - f[a]) + kf * wr * e.frc[a];
-        R x = Codec<S>::offset ? fp - wt<R>(a) * rf : fp;
-        Codec<S>::template store<R>(dst + slot[a], x);
+        fp[a] = f[a] + kc * (wr * e.poly[a] - f[a]) + kf * wr * e.frc[a];
+        if (TH) gp[a] = g[a] + kcg * (wt<R>(a) * m.T * e.poly[a] - g[a]);
+    }
+}
+
+// the values stored for population a of a collided cell at its destination
+template <class R, class S, bool TH>
+__device__ inline R st_out_f(const StArgs& A, const int a, const R fp) {
+    const R rf = R(A.ref_f);
+    return Codec<S>::offset ? fp - wt<R>(a) * rf : fp;
+}
+template <class R, class S, bool TH>
+__device__ inline R st_out_g(const StArgs& A, const int a, R gp, const StDest& d, const R rg) {
+    if (d.yhit != 0) gp = R(2) * wt<R>(a) * (d.yhit < 0 ? R(A.T_bottom) : R(A.T_top)) - gp;
+    const R rgd = A.tref ? R(A.tref[d.drow]) : rg;
+    return Codec<S>::offset ? gp - wt<R>(a) * rgd : gp;
+}
+
+template <class R, class S, bool TH, bool RAW>
+__global__ void __launch_bounds__(256) st_step(StArgs A) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= A.nx) return;
+    const int64_t plane = A.plane;
+    const int64_t cell = int64_t(j) * A.nx + i;
+    const S* src = static_cast<const S*>(A.src);
+    S* dst = static_cast<S*>(A.dst);
+
+    StDest d[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = st_dest(A, i, j, a);
+
+    if (RAW) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            dst[d[a].slot] = src[int64_t(a) * plane + cell];
+            if (TH) dst[9 * plane + d[a].slot] = src[9 * plane + int64_t(a) * plane + cell];
+        }
+        return;
+    }
+
+    // g is stored relative to the row's thermal reference when one is kept
+    const R rf = R(A.ref_f), rg = A.tref ? R(A.tref[j]) : R(A.ref_g);
+    R f[9], g[9], fp[9], gp[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        R x = Codec<S>::template load<R>(src + a * plane + cell);
+        f[a] = Codec<S>::offset ? x + wt<R>(a) * rf : x;
         if (TH) {
-            R gp = g[a] + kcg * (wt<R>(a) * m.T * e.poly[a] - g[a]);
-            if (yhit[a] != 0) gp = R(2) * wt<R>(a) * (yhit[a] < 0 ? Tb : Tt) - gp;
-            const R rgd = A.tref ? R(A.tref[drow[a]]) : rg;
-            R y = Codec<S>::offset ? gp - wt<R>(a) * rgd : gp;
-            Codec<S>::template store<R>(dst + 9 * plane + slot[a], y);
+            R y = Codec<S>::template load<R>(src + (9 + a) * plane + cell);
+            g[a] = Codec<S>::offset ? y + wt<R>(a) * rg : y;
+        }
+    }
+    st_collide<R, TH>(A, f, g, fp, gp);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        Codec<S>::template store<R>(dst + d[a].slot, st_out_f<R, S, TH>(A, a, fp[a]));
+        if (TH) Codec<S>::template store<R>(dst + 9 * plane + d[a].slot, st_out_g<R, S, TH>(A, a, gp[a], d[a], rg));
+    }
+}
+
+// 16-bit storage on grids of even width: a thread takes two neighbouring
+// cells of a row, reads each population of both as one 32-bit word and
+// writes the populations that stay in their column (c_x = 0: rest, up,
+// down, and their wall bounce-backs) as one word too; the others move to
+// different words and are written one by one.  The arithmetic of each cell
+// is that of st_step.
+template <class R, class S, bool TH>
+__global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
+    const int i0 = 2 * (blockIdx.x * 256 + threadIdx.x);
+    const int j = blockIdx.y;
+    if (i0 >= A.nx) return;
+    const int64_t plane = A.plane;
+    const int64_t cell = int64_t(j) * A.nx + i0;   // even: the pair is one aligned word
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const S*>(A.src));
+    S* dst = static_cast<S*>(A.dst);
+    uint32_t* dstw = reinterpret_cast<uint32_t*>(dst);
+    const R rf = R(A.ref_f), rg = A.tref ? R(A.tref[j]) : R(A.ref_g);
+    R f[2][9], g[2][9], fp[2][9], gp[2][9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const uint32_t w = src[(int64_t(a) * plane + cell) >> 1];
+        const uint32_t v = TH ? src[(int64_t(9 + a) * plane + cell) >> 1] : 0u;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const S x{uint16_t(w >> (16 * q))};
+            const R xr = Codec<S>::template load<R>(&x);
+            f[q][a] = xr + wt<R>(a) * rf;
+            if (TH) {
+                const S y{uint16_t(v >> (16 * q))};
+                const R yr = Codec<S>::template load<R>(&y);
+                g[q][a] = yr + wt<R>(a) * rg;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) st_collide<R, TH>(A, f[q], g[q], fp[q], gp[q]);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const StDest d0 = st_dest(A, i0, j, a), d1 = st_dest(A, i0 + 1, j, a);
+        S of[2], og[2];
+        of[0] = S{0};
+        of[1] = S{0};
+        og[0] = S{0};
+        og[1] = S{0};
+        Codec<S>::template store<R>(&of[0], st_out_f<R, S, TH>(A, a, fp[0][a]));
+        Codec<S>::template store<R>(&of[1], st_out_f<R, S, TH>(A, a, fp[1][a]));
+        if (TH) {
+            Codec<S>::template store<R>(&og[0], st_out_g<R, S, TH>(A, a, gp[0][a], d0, rg));
+            Codec<S>::template store<R>(&og[1], st_out_g<R, S, TH>(A, a, gp[1][a], d1, rg));
+        }
+        if (cx(a) == 0) {   // both land in one aligned word (d1.slot = d0.slot + 1)
+            dstw[d0.slot >> 1] = uint32_t(of[0].bits) | (uint32_t(of[1].bits) << 16);
+            if (TH) dstw[(9 * plane + d0.slot) >> 1] = uint32_t(og[0].bits) | (uint32_t(og[1].bits) << 16);
+        } else {
+            dst[d0.slot] = of[0];
+            dst[d1.slot] = of[1];
+            if (TH) {
+                dst[9 * plane + d0.slot] = og[0];
+                dst[9 * plane + d1.slot] = og[1];
+            }
         }
     }
 }
@@ -94,6 +184,14 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
 template <class R, class S>
 static hipError_t st_typed(bool thermal, bool raw, const StArgs& a, hipStream_t s) {
     dim3 grid((a.nx + 255) / 256, a.ny), block(256);
+    if constexpr (sizeof(S) == 2) {
+        if (!raw && a.pairs && a.nx % 2 == 0) {
+            const dim3 gp((a.nx / 2 + 255) / 256, a.ny);
+            if (thermal) hipLaunchKernelGGL((st_step_pair<R, S, true>), gp, block, 0, s, a);
+            else hipLaunchKernelGGL((st_step_pair<R, S, false>), gp, block, 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (thermal) {
         if (raw) hipLaunchKernelGGL((st_step<R, S, true, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((st_step<R, S, true, false>), grid, block, 0, s, a);

@@ -77,6 +77,7 @@ def test_null_handle_is_rejected():
     assert lb.lib().lb_sync(None) == 1
     assert lb.lib().lb_group_step(None, 1) == 1
     assert lb.lib().lb_group_set_chunk(None, 0) == 1
+    assert lb.lib().lb_set_st_pairs(None, 1) == 1
     lb.lib().lb_destroy(None)  # no-op
     lb.lib().lb_group_destroy(None)
 

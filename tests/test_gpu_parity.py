@@ -378,6 +378,29 @@ def test_narrow_and_wide_strips_are_bit_identical(storage, wall_x):
     assert np.array_equal(states[0], states[1])
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("thermal,walls", [(True, (False, True)), (True, (True, True)), (False, (False, False))])
+def test_st_paired_and_single_cells_are_bit_identical(storage, thermal, walls):
+    """The 16-bit ST step with two cells per thread (32-bit words) and with
+    one cell per thread give the same state bit for bit, on an even width
+    that leaves a ragged last block (nx = 300, periodic or walled in x)."""
+    nx, ny = 300, 53
+    say(f"ST pairs vs single cells {storage} thermal={thermal} walls={walls}")
+    kw = dict(thermal=thermal, wall_x=walls[0], wall_y=walls[1], tau=0.3, tau_g=0.25, ax=1e-5,
+              beta_g=1e-3 if thermal else 0.0, T_bottom=0.5, T_top=-0.5)
+    fields = random_fields(nx, ny, 9)
+    if not thermal:
+        fields = fields[:3]
+    xf, yf = workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny)
+    states = []
+    for pairs in (1, 0):
+        sim, _ = make_pair(nx, ny, "st", storage, xf, yf, fields, **kw)
+        sim.set_st_pairs(pairs)
+        sim.step(9)
+        states.append(sim.get_state())
+    assert np.array_equal(states[0], states[1])
+
+
 def test_nonfinite_population_is_reported():
     nx, ny = 64, 32
     say("non-finite detection")

@@ -45,6 +45,38 @@ def test_codec_round_trip_and_ties_to_even(storage, bits):
     assert np.array_equal(f, 1.0 + (even + 2) * ulp)
 
 
+def _bf16_rne(bits):
+    """Round float32 bit patterns (finite) to bfloat16, ties to even, as
+    float32 values."""
+    u = bits.astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_storage_rounds_float32_patterns_to_nearest_even():
+    """Plain bfloat16 storage of float32 values across the whole finite range
+    (normal and subnormal, both signs, with exact ties planted): the stored
+    word is the round-to-nearest-even bfloat16 of the value."""
+    nx, ny = 128, 96
+    say("bf16 codec over float32 patterns")
+    r = np.random.default_rng(17)
+    n = 9 * nx * ny
+    bits = r.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    bits = bits[(bits & 0x7F800000) != 0x7F800000]                       # finite
+    sub = r.integers(0, 2 ** 23, size=n // 8, dtype=np.uint64).astype(np.uint32)   # subnormals
+    tie = (r.integers(0, 2 ** 32, size=n // 8, dtype=np.uint64).astype(np.uint32) & 0xFFFF0000) | 0x8000
+    tie = tie[(tie & 0x7F800000) != 0x7F800000]
+    pats = np.concatenate([bits, sub, sub | 0x80000000, tie])[:n]
+    vals = pats.view(np.float32).astype(np.float64)
+    sim = lb.Sim(nx, ny, scheme="heun", storage="bf16", dt=0.5, tau=0.3, rho_ref=0.0, stream=lb.current_stream())
+    sim.set_grid(workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny))
+    sim.init(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+    sim.set_populations(vals.reshape(9, ny, nx))
+    f, _ = sim.populations()
+    want = _bf16_rne(pats).astype(np.float64).reshape(9, ny, nx)
+    assert np.array_equal(f, want)
+
+
 def perturbation_energy(m):
     """Kinetic energy of the x-varying part of the flow.  The conductive state
     carries a steady x-independent u_y(y) of order 1e-5 (the discrete
