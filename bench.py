@@ -309,7 +309,7 @@ def main():
                     help="run only the 3D 256^3 step with this update kernel (for profiling) and print its timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                                    "(a multi-GPU slab decomposition is described in the design notes)"}))
         sys.exit(2)
 
