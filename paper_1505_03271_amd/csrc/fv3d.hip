@@ -25,6 +25,7 @@
 //
 // Storage: FP64 (parity path) or FP32 offsets p - w_a ref, populations as
 // (s * 19 + a) * cells + cell, x fastest.
+#include <type_traits>
 #include <utility>
 
 #include "lb_kernels.h"
@@ -309,11 +310,15 @@ __device__ inline R staged3(const Src3& q, const R zw, const R v) {
 template <class R>
 struct Stage3 {
     R own, x, y, z;
+    R star;   // Heun corrector: f~* of the population at the own cell
 };
 template <class R, int s, int a>
-__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const bool xh) {
+__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const bool xh, const int64_t c,
+                                      const bool corr) {
     Stage3<R> v;
     v.own = fetch3<R, s, a>(A, q[0]);
+    // (the stage input of the corrector is f~*, stored in the state's own precision R)
+    v.star = corr ? static_cast<const R*>(A.src)[int64_t(s * 19 + a) * A.cells + c] : R(0);
     v.x = c3(a, 0) && xh ? fetch3<R, s, a>(A, q[1]) : R(0);
     v.y = c3(a, 1) ? fetch3<R, s, a>(A, q[2]) : R(0);
     v.z = c3(a, 2) ? fetch3<R, s, a>(A, q[3]) : R(0);
@@ -322,10 +327,11 @@ __device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const 
 
 // the first T3PD moving populations' staged values
 template <class R, bool TH, int p>
-__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, Stage3<R>* v) {
+__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, const int64_t c,
+                                            const bool corr, Stage3<R>* v) {
     if constexpr (p < T3PD && p < 18 * (TH ? 2 : 1)) {
-        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh);
-        fetch_first<R, TH, p + 1>(A, q, xh, v);
+        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh, c, corr);
+        fetch_first<R, TH, p + 1>(A, q, xh, c, corr, v);
     }
 }
 
@@ -354,7 +360,10 @@ __device__ __forceinline__ void tile_base(const Fv3Args<R>& A, Tile3<R, TH>& T, 
     R& d = s == 0 ? T.bf[a] : T.bg[a];
     R b = s == 0 ? k.omkc * d + w3<R>(a) * (k.kc * m.rho_p + m.rho * (k.kc * pm1 + k.kf * frc))
                  : k.omkcg * d + k.kcg * w3<R>(a) * (m.T_p + m.T * pm1);
-    if (CORR) b = R(0.5) * (b + R(Store3<S>::ld(static_cast<const S*>(A.src) + int64_t(s * 19 + a) * A.cells + T.c)));
+    // the corrector's f~* term of a moving population is added when the
+    // population is staged (its load travels with the staged brackets)
+    if (CORR && a == 0)
+        b = R(0.5) * (b + R(Store3<S>::ld(static_cast<const S*>(A.src) + int64_t(s * 19 + a) * A.cells + T.c)));
     d = b;
 }
 template <class R, class S, bool TH, bool CORR, int s, int... as>
@@ -374,8 +383,8 @@ __device__ __forceinline__ void tile_stores(const Fv3Args<R>& A, const Tile3<R, 
 // Moving populations are staged T3G at a time (one barrier per group):
 // write the group's staged values, synchronise, put the loads of later
 // populations in flight, then apply the group's fluxes.
-template <class R, bool TH, int p>
-__device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3N], const Tile3<R, TH>& T,
+template <class R, bool TH, bool CORR, int p>
+__device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3N], Tile3<R, TH>& T,
                                            const Stage3<R>* v) {
     constexpr int s = p / 18, a = p % 18 + 1;
     R* L = lds[(p / T3G) & 1][p % T3G];
@@ -384,13 +393,17 @@ __device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3
     if (c3(a, 0) && T.xh) L[T.li[1]] = staged3<R, s, a>(T.q[1], T.zw[1], u.x);
     if (c3(a, 1)) L[T.li[2]] = staged3<R, s, a>(T.q[2], T.zw[2], u.y);
     if (c3(a, 2)) L[T.li[3]] = staged3<R, s, a>(T.q[3], T.zw[3], u.z);
+    if (CORR) {
+        R& b = s == 0 ? T.bf[a] : T.bg[a];
+        b = R(0.5) * (b + u.star);
+    }
 }
 
-template <class R, bool TH, int p>
+template <class R, bool TH, bool CORR, int p>
 __device__ __forceinline__ void tile_prefetch(const Fv3Args<R>& A, const Tile3<R, TH>& T, Stage3<R>* v) {
     if constexpr (p + T3PD < 18 * (TH ? 2 : 1)) {
         constexpr int p2 = p + T3PD;
-        v[p % T3PD] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh);
+        v[p % T3PD] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh, T.c, CORR);
     }
 }
 
@@ -417,9 +430,9 @@ __device__ __forceinline__ void tile_update(const Fv3Args<R>& A, R (*lds)[T3G][L
 template <class R, class S, bool TH, bool CORR, int g, int... js>
 __device__ __forceinline__ void tile_group(const Fv3Args<R>& A, R (*lds)[T3G][L3N], Tile3<R, TH>& T,
                                            Stage3<R>* v, std::integer_sequence<int, js...>) {
-    (tile_write<R, TH, g * T3G + js>(A, lds, T, v), ...);
+    (tile_write<R, TH, CORR, g * T3G + js>(A, lds, T, v), ...);
     __syncthreads();
-    (tile_prefetch<R, TH, g * T3G + js>(A, T, v), ...);
+    (tile_prefetch<R, TH, CORR, g * T3G + js>(A, T, v), ...);
     (tile_update<R, S, TH, CORR, g * T3G + js>(A, lds, T), ...);
 }
 
@@ -441,6 +454,7 @@ constexpr int T3_WAVES_PER_SIMD = (sizeof(R) == 4 && !CORR) ? 4 : 1;
 
 template <class R, class S, bool TH, bool CORR>
 __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_tiled(Fv3Args<R> A) {
+    static_assert(std::is_same<R, S>::value, "3D states are stored in their arithmetic type");
     __shared__ R lds[2][T3G][L3N];
     const int t = threadIdx.x;
     const int tx = t % T3X, ty = (t / T3X) % T3Y, tz = t / (T3X * T3Y);
@@ -478,12 +492,12 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
         for (int k = 0; k < 4; ++k)
             T.zw[k] = (T.q[k].flags & SRC_ZLO) ? zlo : (T.q[k].flags & SRC_ZHI) ? zhi : R(0);
     }
+    T.c = T.mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
     Stage3<R> v[T3PD];
-    fetch_first<R, TH, 0>(A, T.q, T.xh, v);
+    fetch_first<R, TH, 0>(A, T.q, T.xh, T.c, CORR, v);
     // own record, macroscopic state and the flux weights of the cell along
     // each axis (threads outside the domain read cell 0 and the last
     // weights, without branches, and store nothing)
-    T.c = T.mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
     load3<R, S, TH>(static_cast<const S*>(CORR ? A.aux : A.src), A.cells, T.c, T.bf, T.bg);
     if constexpr (!TH)
 #pragma unroll
