@@ -244,7 +244,10 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
 // cell.  The arithmetic is that of fv3_update, in the same order.
 constexpr int T3X = 32, T3Y = 4, T3Z = 4, T3N = T3X * T3Y * T3Z;
 constexpr int T3G = 1;    // moving populations staged per barrier
-constexpr int T3PD = 3;   // populations whose staged loads are in flight ahead of the one being updated
+// populations whose staged loads are in flight ahead of the one being
+// updated: three in the predictor, two in the corrector (whose staged values
+// carry f~* as well; two keep it within 128 VGPRs, see below)
+template <bool CORR> constexpr int T3PD = CORR ? 2 : 3;
 constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
 static_assert(T3Y == 4 && T3Z == 4, "one thread per halo cell: the four halo rows / planes map to the tile's four");
 static_assert(4 * T3Y * T3Z == 64, "the x-halo cells are one wave");
@@ -326,14 +329,25 @@ __device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const 
 }
 
 // the first T3PD moving populations' staged values
-template <class R, bool TH, int p>
+template <class R, bool TH, bool CORR, int p>
 __device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, const int64_t c,
-                                            const bool corr, Stage3<R>* v) {
-    if constexpr (p < T3PD && p < 18 * (TH ? 2 : 1)) {
-        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh, c, corr);
-        fetch_first<R, TH, p + 1>(A, q, xh, c, corr, v);
+                                            Stage3<R>* v) {
+    if constexpr (p < T3PD<CORR> && p < 18 * (TH ? 2 : 1)) {
+        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh, c, CORR);
+        fetch_first<R, TH, CORR, p + 1>(A, q, xh, c, v);
     }
 }
+
+// a value the whole wave holds alike, kept in a scalar register
+__device__ inline float wave_uniform(const float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ inline double wave_uniform(const double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u)), hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+static_assert((T3X * T3Y) % 64 == 0, "a wave lies in one z plane of the tile");
 
 // Everything a thread of the tiled kernel carries from population to population.
 template <class R, bool TH>
@@ -388,7 +402,7 @@ __device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3
                                            const Stage3<R>* v) {
     constexpr int s = p / 18, a = p % 18 + 1;
     R* L = lds[(p / T3G) & 1][p % T3G];
-    const Stage3<R>& u = v[p % T3PD];
+    const Stage3<R>& u = v[p % T3PD<CORR>];
     L[T.li[0]] = staged3<R, s, a>(T.q[0], T.zw[0], u.own);
     if (c3(a, 0) && T.xh) L[T.li[1]] = staged3<R, s, a>(T.q[1], T.zw[1], u.x);
     if (c3(a, 1)) L[T.li[2]] = staged3<R, s, a>(T.q[2], T.zw[2], u.y);
@@ -401,9 +415,9 @@ __device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3
 
 template <class R, bool TH, bool CORR, int p>
 __device__ __forceinline__ void tile_prefetch(const Fv3Args<R>& A, const Tile3<R, TH>& T, Stage3<R>* v) {
-    if constexpr (p + T3PD < 18 * (TH ? 2 : 1)) {
-        constexpr int p2 = p + T3PD;
-        v[p % T3PD] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh, T.c, CORR);
+    if constexpr (p + T3PD<CORR> < 18 * (TH ? 2 : 1)) {
+        constexpr int p2 = p + T3PD<CORR>;
+        v[p % T3PD<CORR>] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh, T.c, CORR);
     }
 }
 
@@ -445,12 +459,11 @@ __device__ __forceinline__ void tile_groups(const Fv3Args<R>& A, R (*lds)[T3G][L
 // The tile's new state and, when phi_next is set, the brackets of that state
 // for the next stage (the stage kernel's arithmetic on the same values), so
 // that the next pass needs no stage kernel.
-// The FP32 predictor is held to 128 VGPRs (two blocks per CU; a few values
-// spill): 12% faster at 256^3 than with 138 VGPRs and one block.  The
-// corrector keeps its registers (with the same bound it spills 33 values
-// and runs 16% slower).
+// FP32 passes are held to 128 VGPRs, two blocks per CU (the corrector
+// spills a few values): at 256^3, 2.63 / 3.28 ms per pass against 2.80 /
+// 3.35 with one block.
 template <class R, bool CORR>
-constexpr int T3_WAVES_PER_SIMD = (sizeof(R) == 4 && !CORR) ? 4 : 1;
+constexpr int T3_WAVES_PER_SIMD = sizeof(R) == 4 ? 4 : 1;
 
 template <class R, class S, bool TH, bool CORR>
 __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_tiled(Fv3Args<R> A) {
@@ -493,8 +506,8 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
             T.zw[k] = (T.q[k].flags & SRC_ZLO) ? zlo : (T.q[k].flags & SRC_ZHI) ? zhi : R(0);
     }
     T.c = T.mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
-    Stage3<R> v[T3PD];
-    fetch_first<R, TH, 0>(A, T.q, T.xh, T.c, CORR, v);
+    Stage3<R> v[T3PD<CORR>];
+    fetch_first<R, TH, CORR, 0>(A, T.q, T.xh, T.c, v);
     // own record, macroscopic state and the flux weights of the cell along
     // each axis (threads outside the domain read cell 0 and the last
     // weights, without branches, and store nothing)
@@ -508,7 +521,8 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
         for (int d = 0; d < 3; ++d) {
             const int64_t id = i[d] < A.n[d] ? i[d] : A.n[d] - 1;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) T.w[d][j] = A.coef[d][id * 8 + j];
+            for (int j = 0; j < 8; ++j)   // a wave shares its z plane: z weights are wave-uniform
+                T.w[d][j] = d == 2 ? wave_uniform(A.coef[d][id * 8 + j]) : A.coef[d][id * 8 + j];
         }
         tile_bases<R, S, TH, CORR, 0>(A, T, m, std::make_integer_sequence<int, 19>{});
         if constexpr (TH) tile_bases<R, S, TH, CORR, 1>(A, T, m, std::make_integer_sequence<int, 19>{});
