@@ -248,6 +248,7 @@ constexpr int T3G = 1;    // moving populations staged per barrier
 // updated: three in the predictor, two in the corrector (whose staged values
 // carry f~* as well; two keep it within 128 VGPRs, see below)
 template <bool CORR> constexpr int T3PD = CORR ? 2 : 3;
+constexpr int T3S = 8;   // tiles per z column of the block order (see fv3_update_tiled)
 constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
 static_assert(T3Y == 4 && T3Z == 4, "one thread per halo cell: the four halo rows / planes map to the tile's four");
 static_assert(4 * T3Y * T3Z == 64, "the x-halo cells are one wave");
@@ -471,7 +472,19 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
     __shared__ R lds[2][T3G][L3N];
     const int t = threadIdx.x;
     const int tx = t % T3X, ty = (t / T3X) % T3Y, tz = t / (T3X * T3Y);
-    const int o[3] = {int(blockIdx.x) * T3X, int(blockIdx.y) * T3Y, int(blockIdx.z) * T3Z};
+    // one tile per block.  Blocks are dealt to the eight XCDs round robin;
+    // block b takes unit (b % 8) * per + b / 8 of the tiles ordered z fastest
+    // within columns of T3S tiles, then x, then y, then column, so that the
+    // blocks an XCD runs at once are z and x neighbours and meet in its L2 on
+    // the halo planes and columns they share
+    const int nxt = (A.n[0] + T3X - 1) / T3X, nyt = (A.n[1] + T3Y - 1) / T3Y;
+    const int nzt = (A.n[2] + T3Z - 1) / T3Z, ncol = (nzt + T3S - 1) / T3S;
+    const int per = (T3S * nxt * nyt * ncol + 7) / 8;
+    const int u = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
+    if (u >= T3S * nxt * nyt * ncol) return;   // the whole block
+    const int zt = (u / (T3S * nxt * nyt)) * T3S + u % T3S;
+    if (zt >= nzt) return;                     // a short last column: the whole block
+    const int o[3] = {((u / T3S) % nxt) * T3X, ((u / (T3S * nxt)) % nyt) * T3Y, zt * T3Z};
     const int i[3] = {o[0] + tx, o[1] + ty, o[2] + tz};
     Tile3<R, TH> T;
     T.mine = i[0] < A.n[0] && i[1] < A.n[1] && i[2] < A.n[2];
@@ -545,8 +558,9 @@ static void launch_update3(const Fv3Args<R>& A, hipStream_t st) {
         const dim3 grid(unsigned((A.cells + 255) / 256)), block(256);
         hipLaunchKernelGGL((fv3_update<R, S, TH, CORR>), grid, block, 0, st, A);
     } else {
-        const dim3 grid(unsigned((A.n[0] + T3X - 1) / T3X), unsigned((A.n[1] + T3Y - 1) / T3Y),
-                        unsigned((A.n[2] + T3Z - 1) / T3Z));
+        const int nxt = (A.n[0] + T3X - 1) / T3X, nyt = (A.n[1] + T3Y - 1) / T3Y;
+        const int ncol = ((A.n[2] + T3Z - 1) / T3Z + T3S - 1) / T3S;
+        const dim3 grid(unsigned(8 * ((T3S * nxt * nyt * ncol + 7) / 8)));   // as the kernel's unit count
         hipLaunchKernelGGL((fv3_update_tiled<R, S, TH, CORR>), grid, dim3(T3N), 0, st, A);
     }
 }
