@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
 // no edges or corners) are staged in LDS, so a bracket is read from the
 // scratch buffer about once per tile rather than four times per axis and
 // cell.  The arithmetic is that of fv3_update, in the same order.
+// (tiles 8 deep in z, 1024 threads, ran at the same rate at 256^3)
 constexpr int T3X = 32, T3Y = 4, T3Z = 4, T3N = T3X * T3Y * T3Z;
 constexpr int T3G = 1;    // moving populations staged per barrier
 // populations whose staged loads are in flight ahead of the one being
@@ -250,8 +251,10 @@ constexpr int T3G = 1;    // moving populations staged per barrier
 template <bool CORR> constexpr int T3PD = CORR ? 2 : 3;
 constexpr int T3S = 8;   // tiles per z column of the block order (see fv3_update_tiled)
 constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
-static_assert(T3Y == 4 && T3Z == 4, "one thread per halo cell: the four halo rows / planes map to the tile's four");
-static_assert(4 * T3Y * T3Z == 64, "the x-halo cells are one wave");
+static_assert(T3Y == 4 && (T3Z == 4 || T3Z == 8),
+              "one thread per y-halo cell (the four halo rows map to the tile's four); the z-halo planes "
+              "map to the first four planes of the tile");
+static_assert((4 * T3Y * T3Z) % 64 == 0 && (T3X * T3Y * 4) % 64 == 0, "halo-staging threads are whole waves");
 static_assert(18 % T3G == 0, "groups of populations divide a species");
 __device__ constexpr int l3(int x, int y, int z) { return ((z + 2) * L3Y + (y + 2)) * L3X + (x + 2); }
 
@@ -317,25 +320,25 @@ struct Stage3 {
     R star;   // Heun corrector: f~* of the population at the own cell
 };
 template <class R, int s, int a>
-__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const bool xh, const int64_t c,
-                                      const bool corr) {
+__device__ inline Stage3<R> fetch_pop(const Fv3Args<R>& A, const Src3* q, const bool xh, const bool zh,
+                                      const int64_t c, const bool corr) {
     Stage3<R> v;
     v.own = fetch3<R, s, a>(A, q[0]);
     // (the stage input of the corrector is f~*, stored in the state's own precision R)
     v.star = corr ? static_cast<const R*>(A.src)[int64_t(s * 19 + a) * A.cells + c] : R(0);
     v.x = c3(a, 0) && xh ? fetch3<R, s, a>(A, q[1]) : R(0);
     v.y = c3(a, 1) ? fetch3<R, s, a>(A, q[2]) : R(0);
-    v.z = c3(a, 2) ? fetch3<R, s, a>(A, q[3]) : R(0);
+    v.z = c3(a, 2) && zh ? fetch3<R, s, a>(A, q[3]) : R(0);
     return v;
 }
 
 // the first T3PD moving populations' staged values
 template <class R, bool TH, bool CORR, int p>
-__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, const int64_t c,
-                                            Stage3<R>* v) {
+__device__ __forceinline__ void fetch_first(const Fv3Args<R>& A, const Src3* q, const bool xh, const bool zh,
+                                            const int64_t c, Stage3<R>* v) {
     if constexpr (p < T3PD<CORR> && p < 18 * (TH ? 2 : 1)) {
-        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh, c, CORR);
-        fetch_first<R, TH, CORR, p + 1>(A, q, xh, c, v);
+        v[p] = fetch_pop<R, p / 18, p % 18 + 1>(A, q, xh, zh, c, CORR);
+        fetch_first<R, TH, CORR, p + 1>(A, q, xh, zh, c, v);
     }
 }
 
@@ -355,7 +358,8 @@ template <class R, bool TH>
 struct Tile3 {
     Src3 q[4];        // staged positions: own, x halo, y halo, z halo
     int li[4];        // their LDS indices
-    bool xh, mine;    // stages an x-halo cell (wave 0); owns a cell of the domain
+    bool xh, zh;      // stages an x-halo cell / a z-halo cell (whole waves)
+    bool mine;        // owns a cell of the domain
     R zw[4];          // 2 (T_w - ref_g) at the z wall a staged position mirrors (else 0)
     int64_t c;        // own cell (cell 0 for threads outside the domain)
     R bf[19], bg[19]; // own record, then its collision bases, then the new values
@@ -407,7 +411,7 @@ __device__ __forceinline__ void tile_write(const Fv3Args<R>& A, R (*lds)[T3G][L3
     L[T.li[0]] = staged3<R, s, a>(T.q[0], T.zw[0], u.own);
     if (c3(a, 0) && T.xh) L[T.li[1]] = staged3<R, s, a>(T.q[1], T.zw[1], u.x);
     if (c3(a, 1)) L[T.li[2]] = staged3<R, s, a>(T.q[2], T.zw[2], u.y);
-    if (c3(a, 2)) L[T.li[3]] = staged3<R, s, a>(T.q[3], T.zw[3], u.z);
+    if (c3(a, 2) && T.zh) L[T.li[3]] = staged3<R, s, a>(T.q[3], T.zw[3], u.z);
     if (CORR) {
         R& b = s == 0 ? T.bf[a] : T.bg[a];
         b = R(0.5) * (b + u.star);
@@ -418,7 +422,7 @@ template <class R, bool TH, bool CORR, int p>
 __device__ __forceinline__ void tile_prefetch(const Fv3Args<R>& A, const Tile3<R, TH>& T, Stage3<R>* v) {
     if constexpr (p + T3PD<CORR> < 18 * (TH ? 2 : 1)) {
         constexpr int p2 = p + T3PD<CORR>;
-        v[p % T3PD<CORR>] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh, T.c, CORR);
+        v[p % T3PD<CORR>] = fetch_pop<R, p2 / 18, p2 % 18 + 1>(A, T.q, T.xh, T.zh, T.c, CORR);
     }
 }
 
@@ -492,9 +496,10 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
     // (wave 0 only), a y-halo cell and a z-halo cell
     T.q[0] = src3(A, i);
     T.li[0] = l3(tx, ty, tz);
-    T.xh = __builtin_amdgcn_readfirstlane(t) < 4 * T3Y * T3Z;   // a uniform branch
+    T.xh = __builtin_amdgcn_readfirstlane(t) < 4 * T3Y * T3Z;   // uniform branches
+    T.zh = __builtin_amdgcn_readfirstlane(t) < 4 * T3X * T3Y;
     {
-        const int h = t & 3, hy = (t >> 2) & 3, hz = (t >> 4) & 3;
+        const int h = t & 3, hy = (t >> 2) % T3Y, hz = ((t >> 2) / T3Y) % T3Z;
         const int rx = h < 2 ? h - 2 : T3X + h - 2;
         const int g[3] = {o[0] + rx, o[1] + hy, o[2] + hz};
         T.q[1] = T.xh ? src3(A, g) : Src3{0, 0};
@@ -507,7 +512,7 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
         T.li[2] = l3(tx, ry, tz);
     }
     {
-        const int rz = tz < 2 ? tz - 2 : T3Z + tz - 2;
+        const int rz = tz < 2 ? tz - 2 : T3Z + (tz & 3) - 2;   // threads of the first four planes
         const int g[3] = {i[0], i[1], o[2] + rz};
         T.q[3] = src3(A, g);
         T.li[3] = l3(tx, ty, rz);
@@ -520,7 +525,7 @@ __global__ void __launch_bounds__(T3N, (T3_WAVES_PER_SIMD<R, CORR>)) fv3_update_
     }
     T.c = T.mine ? (int64_t(i[2]) * A.n[1] + i[1]) * A.n[0] + i[0] : 0;
     Stage3<R> v[T3PD<CORR>];
-    fetch_first<R, TH, CORR, 0>(A, T.q, T.xh, T.c, v);
+    fetch_first<R, TH, CORR, 0>(A, T.q, T.xh, T.zh, T.c, v);
     // own record, macroscopic state and the flux weights of the cell along
     // each axis (threads outside the domain read cell 0 and the last
     // weights, without branches, and store nothing)
