@@ -124,3 +124,16 @@ def test_stream_probe_rejects_bad_arguments_before_touching_the_device():
     assert L.lb_stream_probe(1 << 20, None, out) == 1
     assert "16 MiB" in L.lb_last_error().decode()
     assert L.lb_stream_probe(64 << 20, None, None) == 1
+
+
+def test_header_is_plain_c():
+    """include/lb.h is a C header (the boundary takes plain pointers and
+    sizes): it compiles as C99 and as C++ on its own."""
+    import shutil
+    import subprocess
+    for cc, std, lang in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "c++")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} is not installed")
+        r = subprocess.run([cc, "-fsyntax-only", std, "-Wall", "-Werror", "-x", lang,
+                            os.path.join(ROOT, "include", "lb.h")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
