@@ -137,3 +137,28 @@ def test_fv3d_tiled_and_per_cell_updates_are_bit_identical(storage, walls, therm
     for a, b in zip(out["tiled"], out["gather"]):
         if a is not None:
             assert np.array_equal(a, b)
+
+
+def test_fv3d_benchmark_shape_tiled_equals_per_cell():
+    """The benchmark's 3D workload and launch shape (256^3 thermal RB, FP32,
+    tanh z grid; tiles dealt to XCDs in z columns): two Heun steps with the
+    tiled update and with the per-cell update give the same moments bit for
+    bit and the same FP64 diagnostics."""
+    cfg = workloads.rb3d_config(256, 1e8, 2.0)
+    say("3D 256^3 tiled vs per-cell")
+    out = {}
+    for kind in ("tiled", "gather"):
+        sim = lb.Sim3(256, 256, 256, scheme="heun", storage="f32", thermal=True, walls=(False, False, True),
+                      dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"], T0=cfg["T0"],
+                      T_bottom=cfg["T_bottom"], T_top=cfg["T_top"], stream=lb.current_stream())
+        sim.set_update(kind)
+        sim.set_grid(cfg["xf"], cfg["yf"], cfg["zf"])
+        sim.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["uz"], cfg["T"])
+        sim.step(2)
+        out[kind] = (sim.moments(), sim.diagnostics())
+        sim.close()
+    (mt, dt_), (mg, dg) = out["tiled"], out["gather"]
+    for k in mt:
+        assert np.array_equal(mt[k], mg[k]), k
+    assert dt_ == dg
+    assert dt_["nonfinite"] == 0
