@@ -401,6 +401,29 @@ def test_st_paired_and_single_cells_are_bit_identical(storage, thermal, walls):
     assert np.array_equal(states[0], states[1])
 
 
+def test_st_paired_and_single_cells_at_the_benchmark_shape():
+    """The ST comparison workload of the benchmark (4096^2 thermal, BF16,
+    walls in y): two cells per thread and one cell per thread give the same
+    state bit for bit after three steps."""
+    n = 4096
+    say("ST pairs vs single cells, 4096^2 bf16")
+    H = float(n)
+    beta_g = 0.01 / H
+    xf = workloads.faces_uniform(n, H)
+    rho, ux, uy, T = workloads.rb_fields(n, xf, 1.0, 0.0, beta_g, seed_index=6)
+    states = []
+    for pairs in (1, 0):
+        sim = lb.Sim(n, n, scheme="st", storage="bf16", thermal=True, wall_y=True, tau=0.5, tau_g=0.5,
+                     beta_g=beta_g, T_bottom=0.5, T_top=-0.5, stream=lb.current_stream())
+        sim.set_st_pairs(pairs)
+        sim.set_grid(xf, xf)
+        sim.init(rho, ux, uy, T)
+        sim.step(3)
+        states.append(sim.get_state())
+        sim.close()
+    assert np.array_equal(states[0], states[1])
+
+
 def test_nonfinite_population_is_reported():
     nx, ny = 64, 32
     say("non-finite detection")
