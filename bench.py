@@ -13,13 +13,16 @@ One "step" is one full FV time step (predictor + corrector kernels) of the
 whole grid.  value = cells * steps / time in MLUPS.
 
 Also reported: the same grid with FP32, FP16S and plain BF16 storage, the ST
-step on a uniform grid of the same size, per-kernel durations (HIP events on
-the library's stream), the roofline of the dominant kernel, the accuracy of
-every storage format against the FP64 oracle at a steady convective state,
-the serving loop (p50/p99 latency) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+step on a uniform grid of the same size, the 3D D3Q19 step on 256^3, the
+smaller configurations (tgv64, channel, rb1024), per-kernel durations (HIP
+events on the library's stream), the roofline of the dominant kernel, the
+accuracy of every storage format against the FP64 oracle at a steady
+convective state, the serving loop (p50/p99 latency under both scheduling
+policies) and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants] [--no-accuracy]
+                    [--serve-requests N] [--storage S] [--calibrate] [--only-3d tiled|gather]
 """
 import argparse
 import hashlib
