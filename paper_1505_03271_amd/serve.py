@@ -11,12 +11,14 @@ Which admitted requests run in the next launch is the policy:
 
 * "all": every admitted request (processor sharing: each advances one step
   per group step, whatever its size);
-* "srpt": shortest remaining work first, preemptive.  Admitted requests are
-  ranked by cells x remaining steps and the shortest run, as many as it
-  takes to hold `min_cells` cells (enough work to fill the device; fewer
-  cells per launch lower the throughput); the others wait resident in HBM
-  and resume later exactly where they stopped (leaving and re-joining a
-  group does not change a member's result).
+* "srpt": shortest remaining work first, preemptive, with aging.  Admitted
+  requests are ranked by cells x remaining steps, divided by 1 + (time
+  since admission) / age_s so that a long request that has waited is not
+  starved, and the first run, as many as it takes to hold `min_cells`
+  cells (enough work to fill the device; fewer cells per launch lower the
+  throughput); the others wait resident in HBM and resume later exactly
+  where they stopped (leaving and re-joining a group does not change a
+  member's result).
 
     from paper_1505_03271_amd.serve import Server
     stats = Server(storage="bf16", hbm_budget=16e9).run(trace)
@@ -43,7 +45,7 @@ def request_bytes(n, storage, thermal=True):
 
 class Server:
     def __init__(self, storage="bf16", hbm_budget=16e9, max_sims=128, graph_steps=100, stream=None,
-                 stretch=2.0, policy="srpt", min_cells=8e6, max_resident=None):
+                 stretch=2.0, policy="srpt", min_cells=8e6, age_s=5.0, max_resident=None):
         """max_sims: group slots (requests running in one launch);
         max_resident: admitted requests held in HBM (default max_sims; with
         "all" every resident request runs, so it is at most max_sims)."""
@@ -55,6 +57,7 @@ class Server:
         self.stretch = stretch
         self.policy = policy
         self.min_cells = float(min_cells)
+        self.age_s = float(age_s)
         self.stream = stream if stream is not None else current_stream()
         self.group = Group(max_sims, self.stream)
         self.max_sims = max_sims
@@ -73,12 +76,18 @@ class Server:
         sim.init(rho, ux, uy, T)
         return sim
 
-    def _choose(self, resident):
-        """Request ids to run in the next launch."""
+    def _choose(self, resident, now):
+        """Request ids to run in the next launch (now: the server clock)."""
         ids = sorted(resident, key=lambda k: resident[k]["admitted"])
         if self.policy == "all":
             return ids[:self.max_sims]
-        ids.sort(key=lambda k: (resident[k]["req"]["n"] ** 2 * resident[k]["left"], resident[k]["admitted"]))
+
+        def rank(k):
+            r = resident[k]
+            work = r["req"]["n"] ** 2 * r["left"]
+            return (work / (1.0 + max(now - r["admitted"], 0.0) / self.age_s), r["admitted"])
+
+        ids.sort(key=rank)
         run, cells = [], 0
         for k in ids[:self.max_sims]:
             run.append(k)
@@ -124,7 +133,7 @@ class Server:
                     phase["idle_s"] += clock() - t
                 continue
             # the members of the next launch
-            run = set(self._choose(resident))
+            run = set(self._choose(resident, clock()))
             for k, r in resident.items():
                 if r["slot"] is not None and k not in run:
                     self.group.remove(r["slot"])
@@ -172,7 +181,8 @@ class Server:
                     p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                     aggregate_mlups=cell_steps / makespan / 1e6 if makespan > 0 else None,
                     graph_launches=launches, graph_steps=self.graph_steps, policy=self.policy,
-                    min_cells=self.min_cells if self.policy == "srpt" else None, preemptions=preemptions,
+                    min_cells=self.min_cells if self.policy == "srpt" else None,
+                    age_s=self.age_s if self.policy == "srpt" else None, preemptions=preemptions,
                     phases_s={k: round(v, 3) for k, v in phase.items()})
 
     def close(self):
