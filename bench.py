@@ -425,7 +425,7 @@ def main():
                             "phases_s": st["phases_s"]}
             log(f"serving ({policy}): p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, "
                 f"{st['aggregate_mlups']:.0f} MLUPS")
-        out["serving"] = dict(requests=len(trace), policy="srpt", min_cells=8e6, **runs["srpt"],
+        out["serving"] = dict(requests=len(trace), policy="srpt", min_cells=8e6, age_s=5.0, **runs["srpt"],
                               graph_steps=100, hbm_budget_bytes=16e9, storage=args.storage,
                               trace="Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
                                     "steps U{2000..20000}, seed 150503275",
