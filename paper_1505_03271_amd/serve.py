@@ -51,6 +51,8 @@ class Server:
         "all" every resident request runs, so it is at most max_sims)."""
         if policy not in POLICIES:
             raise ValueError(f"policy must be one of {POLICIES}")
+        if not age_s > 0:
+            raise ValueError("age_s must be > 0")
         self.storage = storage
         self.hbm_budget = float(hbm_budget)
         self.graph_steps = int(graph_steps)

@@ -45,6 +45,8 @@ def test_policy_names_and_request_bytes():
     assert POLICIES == ("all", "srpt")
     with pytest.raises(ValueError):
         Server(policy="fifo")
+    with pytest.raises(ValueError):
+        Server(age_s=0.0)
     # two population states plus the per-row metric and a small fixed part
     assert request_bytes(1000, "bf16s") == 2 * 1000 * 1000 * 44 + 64 * 1000 + 4096
     assert cell_bytes("f32") == 72 and cell_bytes("bf16") == 36 and cell_bytes("bf16s", thermal=False) == 24
