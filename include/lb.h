@@ -237,11 +237,11 @@ int lb_set_rebase(lb_sim* sim, int64_t every);
  * lb_set_fv_chunk.  LB_EINVAL for other values. */
 int lb_set_fv_lanes(lb_sim* sim, int lanes);
 
-/* ST with 16-bit storage on grids of even nx (a launch-shape knob): 1 (the
- * default) two cells of a row per thread, each population of both read as
- * one 32-bit word and those that stay in their column written as one; 0
- * one cell per thread.  Results are identical either way.  LB_EINVAL for
- * other values. */
+/* ST with FP32 or 16-bit storage on grids of even nx (a launch-shape
+ * knob): 1 (the default) two cells of a row per thread, each population of
+ * both read as one 64- or 32-bit word and those that stay in their column
+ * written as one; 0 one cell per thread.  Results are identical either
+ * way.  LB_EINVAL for other values. */
 int lb_set_st_pairs(lb_sim* sim, int on);
 
 /* Rows per work item of the FV kernels (a launch-shape knob for tuning).

@@ -66,7 +66,7 @@ struct StArgs {
     double ax, ay, bg, T0, T_bottom, T_top;
     double ref_f, ref_g;
     const float* tref;   // per-row thermal reference of the stored g, or NULL
-    int pairs;           // 16-bit storage, even nx: two cells per thread (st_step_pair)
+    int pairs;           // FP32 or 16-bit storage, even nx: two cells per thread (st_step_pair)
 };
 
 // Host launchers (defined in the .hip files).  `storage` selects the

@@ -9,6 +9,8 @@
 // (anti-bounce-back).  Every destination slot is written exactly once, so
 // the step is a permutation of the collided values.  With RAW the collision
 // is skipped and the stored words are moved unchanged.
+#include <type_traits>
+
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -117,35 +119,51 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
     }
 }
 
-// 16-bit storage on grids of even width: a thread takes two neighbouring
-// cells of a row, reads each population of both as one 32-bit word and
-// writes the populations that stay in their column (c_x = 0: rest, up,
-// down, and their wall bounce-backs) as one word too; the others move to
-// different words and are written one by one.  The arithmetic of each cell
-// is that of st_step.
+// 16-bit or FP32 storage on grids of even width: a thread takes two
+// neighbouring cells of a row, reads each population of both as one word
+// (32 or 64 bits) and writes the populations that stay in their column
+// (c_x = 0: rest, up, down, and their wall bounce-backs) as one word too; the
+// others move to different words and are written one by one.  The
+// arithmetic of each cell is that of st_step.
+template <class S> struct PairWord;
+template <> struct PairWord<bf16_t> { using W = uint32_t; };
+template <> struct PairWord<f16_t> { using W = uint32_t; };
+template <> struct PairWord<float> { using W = uint64_t; };
+
+template <class S> __device__ inline S pair_part(const typename PairWord<S>::W w, const int q) {
+    if constexpr (sizeof(S) == 2) return S{uint16_t(w >> (16 * q))};
+    else return __builtin_bit_cast(S, uint32_t(w >> (32 * q)));
+}
+template <class S> __device__ inline typename PairWord<S>::W pair_word(const S lo, const S hi) {
+    using W = typename PairWord<S>::W;
+    if constexpr (sizeof(S) == 2) return W(lo.bits) | (W(hi.bits) << 16);
+    else return W(__builtin_bit_cast(uint32_t, lo)) | (W(__builtin_bit_cast(uint32_t, hi)) << 32);
+}
+
 template <class R, class S, bool TH>
 __global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
+    using W = typename PairWord<S>::W;
     const int i0 = 2 * (blockIdx.x * 256 + threadIdx.x);
     const int j = blockIdx.y;
     if (i0 >= A.nx) return;
     const int64_t plane = A.plane;
     const int64_t cell = int64_t(j) * A.nx + i0;   // even: the pair is one aligned word
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const S*>(A.src));
+    const W* src = reinterpret_cast<const W*>(static_cast<const S*>(A.src));
     S* dst = static_cast<S*>(A.dst);
-    uint32_t* dstw = reinterpret_cast<uint32_t*>(dst);
+    W* dstw = reinterpret_cast<W*>(dst);
     const R rf = R(A.ref_f), rg = A.tref ? R(A.tref[j]) : R(A.ref_g);
     R f[2][9], g[2][9], fp[2][9], gp[2][9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const uint32_t w = src[(int64_t(a) * plane + cell) >> 1];
-        const uint32_t v = TH ? src[(int64_t(9 + a) * plane + cell) >> 1] : 0u;
+        const W w = src[(int64_t(a) * plane + cell) >> 1];
+        const W v = TH ? src[(int64_t(9 + a) * plane + cell) >> 1] : W(0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const S x{uint16_t(w >> (16 * q))};
+            const S x = pair_part<S>(w, q);
             const R xr = Codec<S>::template load<R>(&x);
             f[q][a] = xr + wt<R>(a) * rf;
             if (TH) {
-                const S y{uint16_t(v >> (16 * q))};
+                const S y = pair_part<S>(v, q);
                 const R yr = Codec<S>::template load<R>(&y);
                 g[q][a] = yr + wt<R>(a) * rg;
             }
@@ -157,10 +175,6 @@ __global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
     for (int a = 0; a < 9; ++a) {
         const StDest d0 = st_dest(A, i0, j, a), d1 = st_dest(A, i0 + 1, j, a);
         S of[2], og[2];
-        of[0] = S{0};
-        of[1] = S{0};
-        og[0] = S{0};
-        og[1] = S{0};
         Codec<S>::template store<R>(&of[0], st_out_f<R, S, TH>(A, a, fp[0][a]));
         Codec<S>::template store<R>(&of[1], st_out_f<R, S, TH>(A, a, fp[1][a]));
         if (TH) {
@@ -168,8 +182,8 @@ __global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
             Codec<S>::template store<R>(&og[1], st_out_g<R, S, TH>(A, a, gp[1][a], d1, rg));
         }
         if (cx(a) == 0) {   // both land in one aligned word (d1.slot = d0.slot + 1)
-            dstw[d0.slot >> 1] = uint32_t(of[0].bits) | (uint32_t(of[1].bits) << 16);
-            if (TH) dstw[(9 * plane + d0.slot) >> 1] = uint32_t(og[0].bits) | (uint32_t(og[1].bits) << 16);
+            dstw[d0.slot >> 1] = pair_word<S>(of[0], of[1]);
+            if (TH) dstw[(9 * plane + d0.slot) >> 1] = pair_word<S>(og[0], og[1]);
         } else {
             dst[d0.slot] = of[0];
             dst[d1.slot] = of[1];
@@ -184,7 +198,7 @@ __global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
 template <class R, class S>
 static hipError_t st_typed(bool thermal, bool raw, const StArgs& a, hipStream_t s) {
     dim3 grid((a.nx + 255) / 256, a.ny), block(256);
-    if constexpr (sizeof(S) == 2) {
+    if constexpr (!std::is_same<S, double>::value) {
         if (!raw && a.pairs && a.nx % 2 == 0) {
             const dim3 gp((a.nx / 2 + 255) / 256, a.ny);
             if (thermal) hipLaunchKernelGGL((st_step_pair<R, S, true>), gp, block, 0, s, a);

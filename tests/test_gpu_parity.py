@@ -378,10 +378,10 @@ def test_narrow_and_wide_strips_are_bit_identical(storage, wall_x):
     assert np.array_equal(states[0], states[1])
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("storage", ["bf16", "f16", "f32"])
 @pytest.mark.parametrize("thermal,walls", [(True, (False, True)), (True, (True, True)), (False, (False, False))])
 def test_st_paired_and_single_cells_are_bit_identical(storage, thermal, walls):
-    """The 16-bit ST step with two cells per thread (32-bit words) and with
+    """The ST step with two cells per thread (one 32- or 64-bit word) and with
     one cell per thread give the same state bit for bit, on an even width
     that leaves a ragged last block (nx = 300, periodic or walled in x)."""
     nx, ny = 300, 53
