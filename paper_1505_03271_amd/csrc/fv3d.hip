@@ -246,9 +246,9 @@ __global__ void __launch_bounds__(256) fv3_update(Fv3Args<R> A) {
 constexpr int T3X = 32, T3Y = 4, T3Z = 4, T3N = T3X * T3Y * T3Z;
 constexpr int T3G = 1;    // moving populations staged per barrier
 // populations whose staged loads are in flight ahead of the one being
-// updated: three in the predictor, two in the corrector (whose staged values
+// updated: four in the predictor, two in the corrector (whose staged values
 // carry f~* as well; two keep it within 128 VGPRs, see below)
-template <bool CORR> constexpr int T3PD = CORR ? 2 : 3;
+template <bool CORR> constexpr int T3PD = CORR ? 2 : 4;
 constexpr int T3S = 8;   // tiles per z column of the block order (see fv3_update_tiled)
 constexpr int L3X = T3X + 4, L3Y = T3Y + 4, L3Z = T3Z + 4, L3N = L3X * L3Y * L3Z;
 static_assert(T3Y == 4 && (T3Z == 4 || T3Z == 8),
