@@ -256,6 +256,8 @@ static_assert(T3Y == 4 && (T3Z == 4 || T3Z == 8),
               "map to the first four planes of the tile");
 static_assert((4 * T3Y * T3Z) % 64 == 0 && (T3X * T3Y * 4) % 64 == 0, "halo-staging threads are whole waves");
 static_assert(18 % T3G == 0, "groups of populations divide a species");
+static_assert(T3G <= T3PD<true> && T3G <= T3PD<false>,
+              "a group's staged values are all in flight before its first write");
 __device__ constexpr int l3(int x, int y, int z) { return ((z + 2) * L3Y + (y + 2)) * L3X + (x + 2); }
 
 // Source of one staged bracket: the cell it is read at, whether that is a
@@ -464,9 +466,8 @@ __device__ __forceinline__ void tile_groups(const Fv3Args<R>& A, R (*lds)[T3G][L
 // The tile's new state and, when phi_next is set, the brackets of that state
 // for the next stage (the stage kernel's arithmetic on the same values), so
 // that the next pass needs no stage kernel.
-// FP32 passes are held to 128 VGPRs, two blocks per CU (the corrector
-// spills a few values): at 256^3, 2.63 / 3.28 ms per pass against 2.80 /
-// 3.35 with one block.
+// FP32 passes are held to 128 VGPRs, two blocks per CU, without spills
+// (one block per CU with more registers was the slower of the two).
 template <class R, bool CORR>
 constexpr int T3_WAVES_PER_SIMD = sizeof(R) == 4 ? 4 : 1;
 
