@@ -118,7 +118,8 @@ typedef struct lb_sim lb_sim;
  * LB_ENOMEM, LB_EDEVICE. */
 int lb_create(const lb_params* p, lb_sim** out);
 
-/* Release the handle and its device memory (NULL is a no-op). */
+/* Release the handle and its device memory (NULL is a no-op).  A group
+ * member leaves its group first (as lb_group_remove). */
 void lb_destroy(lb_sim* sim);
 
 /* Grid (sec. 3, eq:grids; sec. 2.2.3).  x_faces[0..nx] and y_faces[0..ny]
@@ -127,7 +128,8 @@ void lb_destroy(lb_sim* sim);
  * 1/dy and the QUICK coefficients gamma_1..4 of every face, with mirrored
  * ghost centres at walls and periodic images otherwise.  LB_ST requires unit
  * spacing (faces 0, 1, ..., n up to a common offset) or returns LB_EINVAL.
- * Must precede lb_init. */
+ * Must precede lb_init.  May be called again, between steps, for a new
+ * grid; if that call fails the previous grid stays in use. */
 int lb_set_grid(lb_sim* sim, const double* x_faces, int64_t n_xf,
                 const double* y_faces, int64_t n_yf);
 
@@ -263,14 +265,20 @@ size_t lb_device_bytes(const lb_sim* sim);
  * membership or nsteps changes).  Each member carries its own remaining
  * step count and stops exactly there, so a member's state after its steps
  * is bit-identical to running it alone with lb_step.  Members stay owned by
- * the caller and must not be stepped, reset or destroyed while in a group.
+ * the caller.  While it is in a group, a member is advanced only by the
+ * group: lb_step, lb_init, lb_set_grid, lb_set_state, lb_set_populations,
+ * lb_rebase, lb_set_fv_lanes and lb_set_fv_chunk on it return LB_ESTATE, and
+ * so does adding it to a second group; reading it (lb_moments, lb_nusselt,
+ * lb_get_state, ...) is allowed once the group's stream has been
+ * synchronised (lb_group_sync or lb_group_remaining).
  * stream: hipStream_t to use, or NULL to create one. */
 typedef struct lb_group lb_group;
 int lb_group_create(int32_t max_sims, void* stream, lb_group** out);
 void lb_group_destroy(lb_group* group);
 /* Join with `steps` steps to do; *slot receives the member's slot.
- * LB_EINVAL for a non-Heun member or a storage/thermal mismatch, LB_ESTATE
- * without a state, LB_ENOMEM when all slots are taken.  Synchronises. */
+ * LB_EINVAL for a non-Heun member, a storage/thermal mismatch or a second
+ * add to the same group, LB_ESTATE without a state or for a member of
+ * another group, LB_ENOMEM when all slots are taken.  Synchronises. */
 int lb_group_add(lb_group* group, lb_sim* sim, int64_t steps, int32_t* slot);
 /* Leave (finished or not); the slot becomes free and the simulation takes
  * its own automatic item height again.  Synchronises. */
@@ -336,7 +344,8 @@ typedef struct lb3_sim lb3_sim;
 
 int lb3_create(const lb3_params* p, lb3_sim** out);
 void lb3_destroy(lb3_sim* sim);
-/* faces per axis, n+1 each, strictly increasing (copied) */
+/* faces per axis, n+1 each, strictly increasing (copied); as lb_set_grid,
+ * a failed later call leaves the previous grid in use */
 int lb3_set_grid(lb3_sim* sim, const double* x_faces, int64_t n_xf, const double* y_faces, int64_t n_yf,
                  const double* z_faces, int64_t n_zf);
 /* equilibrium start from host fields [nz][ny][nx]; T may be NULL unless thermal */

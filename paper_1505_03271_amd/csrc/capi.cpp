@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -157,6 +158,8 @@ struct lb_sim {
     int chunk_h = 0;
     int lanes = 0;            // FV item width: 0 chosen from nx, or FV_LANES / FV_NARROW
     int st_pairs = 1;         // ST, 16-bit storage: two cells per thread where nx is even
+    lb_group* group = nullptr;  // the group this simulation is a member of, if any
+    int group_slot = -1;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -171,6 +174,34 @@ namespace {
 int check_sim(const lb_sim* s) {
     if (!s) return fail(LB_EINVAL, "NULL handle");
     return LB_OK;
+}
+
+// A group's captured launches hold the member's buffers and item layout, so
+// a member is neither stepped nor changed except through its group.
+int check_free(const lb_sim* s, const char* fn) {
+    if (int rc = check_sim(s)) return rc;
+    if (s->group) return fail(LB_ESTATE, "%s: the simulation is a group member (slot %d)", fn, s->group_slot);
+    return LB_OK;
+}
+
+// Copy host arrays to new device buffers: all of them, or none (on failure
+// the ones already made are freed and every *dst is left null).
+struct Upload {
+    void** dst;
+    const void* src;
+    size_t bytes;
+};
+int upload_all(std::initializer_list<Upload> ups, const char* fn) {
+    hipError_t e = hipSuccess;
+    for (const Upload& u : ups) {
+        *u.dst = nullptr;
+        if (e == hipSuccess) e = hipMalloc(u.dst, u.bytes);
+        if (e == hipSuccess) e = hipMemcpy(*u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) return LB_OK;
+    for (const Upload& u : ups)
+        if (*u.dst) { (void)hipFree(*u.dst); *u.dst = nullptr; }
+    return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
 }
 
 // Release every device allocation of a handle (safe on partial creation).
@@ -563,13 +594,14 @@ int lb_create(const lb_params* p, lb_sim** out) {
 
 void lb_destroy(lb_sim* s) {
     if (!s) return;
+    if (s->group) (void)lb_group_remove(s->group, s->group_slot);
     (void)hipStreamSynchronize(s->stream);
     release(s);
     delete s;
 }
 
 int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_faces, int64_t n_yf) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_set_grid")) return rc;
     try {
         if (!x_faces || !y_faces) return fail(LB_EINVAL, "lb_set_grid: NULL faces");
         if (n_xf != s->p.nx + 1 || n_yf != s->p.ny + 1)
@@ -584,36 +616,41 @@ int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_
             for (int64_t i = 0; i < n_yf; ++i)
                 if (std::fabs(y_faces[i] - y_faces[0] - double(i)) > 1e-12) return fail(LB_EINVAL, "lb_set_grid: ST needs unit spacing in y");
         }
-        s->xf.assign(x_faces, x_faces + n_xf);
-        s->yf.assign(y_faces, y_faces + n_yf);
+        std::vector<double> xf(x_faces, x_faces + n_xf), yf(y_faces, y_faces + n_yf);
         const int nx = s->p.nx, ny = s->p.ny;
-        std::vector<double> xw = quick_weights(s->xf, s->p.bc_x == LB_PERIODIC);
-        std::vector<double> yw = quick_weights(s->yf, s->p.bc_y == LB_PERIODIC);
+        std::vector<double> xw = quick_weights(xf, s->p.bc_x == LB_PERIODIC);
+        std::vector<double> yw = quick_weights(yf, s->p.bc_y == LB_PERIODIC);
         // pass 0: predictor / single pass (factor dt); pass 1: Heun corrector (dt/2)
         std::vector<double> m;
         for (double factor : {s->p.dt, 0.5 * s->p.dt}) {
-            std::vector<double> a = flux_stencils(s->xf, xw, factor), b = flux_stencils(s->yf, yw, factor);
+            std::vector<double> a = flux_stencils(xf, xw, factor), b = flux_stencils(yf, yw, factor);
             m.insert(m.end(), a.begin(), a.end());
             m.insert(m.end(), b.begin(), b.end());
         }
         std::vector<double> dxy(size_t(nx) + ny);
-        for (int i = 0; i < nx; ++i) dxy[i] = s->xf[i + 1] - s->xf[i];
-        for (int j = 0; j < ny; ++j) dxy[nx + j] = s->yf[j + 1] - s->yf[j];
-        if (s->metric) { (void)hipFree(s->metric); s->metric = nullptr; }
-        if (s->dxy) { (void)hipFree(s->dxy); s->dxy = nullptr; }
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        if (s->p.storage == LB_F64) {
-            s->metric_bytes = m.size() * sizeof(double);
-            HIP_TRY(hipMalloc(&s->metric, s->metric_bytes));
-            HIP_TRY(hipMemcpy(s->metric, m.data(), s->metric_bytes, hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> mf(m.begin(), m.end());
-            s->metric_bytes = mf.size() * sizeof(float);
-            HIP_TRY(hipMalloc(&s->metric, s->metric_bytes));
-            HIP_TRY(hipMemcpy(s->metric, mf.data(), s->metric_bytes, hipMemcpyHostToDevice));
+        for (int i = 0; i < nx; ++i) dxy[i] = xf[i + 1] - xf[i];
+        for (int j = 0; j < ny; ++j) dxy[nx + j] = yf[j + 1] - yf[j];
+        std::vector<float> mf;
+        if (s->p.storage != LB_F64) mf.assign(m.begin(), m.end());
+        const void* mh = s->p.storage == LB_F64 ? static_cast<const void*>(m.data()) : mf.data();
+        const size_t mbytes = s->p.storage == LB_F64 ? m.size() * sizeof(double) : mf.size() * sizeof(float);
+        // the new grid goes to new buffers; the old one stays in use if this fails
+        void* metric = nullptr;
+        void* dxy_d = nullptr;
+        if (int rc = upload_all({{&metric, mh, mbytes}, {&dxy_d, dxy.data(), dxy.size() * sizeof(double)}}, "lb_set_grid"))
+            return rc;
+        if (hipError_t e = hipStreamSynchronize(s->stream); e != hipSuccess) {
+            (void)hipFree(metric);
+            (void)hipFree(dxy_d);
+            return fail(LB_EDEVICE, "set_grid: %s", hipGetErrorString(e));
         }
-        HIP_TRY(hipMalloc(&s->dxy, dxy.size() * sizeof(double)));
-        HIP_TRY(hipMemcpy(s->dxy, dxy.data(), dxy.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (s->metric) (void)hipFree(s->metric);
+        if (s->dxy) (void)hipFree(s->dxy);
+        s->metric = metric;
+        s->dxy = static_cast<double*>(dxy_d);
+        s->metric_bytes = mbytes;
+        s->xf.swap(xf);
+        s->yf.swap(yf);
         s->has_grid = true;
         return LB_OK;
     } catch (...) {
@@ -622,7 +659,7 @@ int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_
 }
 
 int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, const double* T) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_init")) return rc;
     if (!s->has_grid) return fail(LB_ESTATE, "lb_init: call lb_set_grid first");
     if (!rho || !ux || !uy || (s->p.thermal && !T)) return fail(LB_EINVAL, "lb_init: NULL field");
     const size_t n = size_t(s->plane);
@@ -657,7 +694,7 @@ int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, co
 }
 
 int lb_step(lb_sim* s, int64_t nsteps) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_step")) return rc;
     if (!s->has_init) return fail(LB_ESTATE, "lb_step: call lb_init (or lb_set_state) first");
     if (nsteps < 0) return fail(LB_EINVAL, "lb_step: negative step count");
     if (s->unstable) return fail(LB_EUNSTABLE, "lb_step: non-finite populations were detected");
@@ -796,7 +833,7 @@ int lb_get_populations(lb_sim* s, double* f, double* g) {
 }
 
 int lb_set_populations(lb_sim* s, const double* f, const double* g) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_set_populations")) return rc;
     if (!f || (s->p.thermal && !g)) return fail(LB_EINVAL, "lb_set_populations: NULL input");
     if (!s->has_grid) return fail(LB_ESTATE, "lb_set_populations: call lb_set_grid first");
     const size_t nf = 9 * size_t(s->plane);
@@ -837,7 +874,7 @@ int lb_get_state(lb_sim* s, void* host, size_t bytes) {
 }
 
 int lb_set_state(lb_sim* s, const void* host, size_t bytes) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_set_state")) return rc;
     const size_t need = s->state_bytes + ref_bytes(s);
     if (!host || bytes != need) return fail(LB_EINVAL, "lb_set_state: need %zu bytes", need);
     if (!s->has_grid) return fail(LB_ESTATE, "lb_set_state: call lb_set_grid first");
@@ -879,7 +916,7 @@ size_t lb_device_bytes(const lb_sim* s) {
 }
 
 int lb_rebase(lb_sim* s) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_rebase")) return rc;
     if (!s->has_init) return fail(LB_ESTATE, "lb_rebase: no state");
     if (!s->tref) return LB_OK;
     hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
@@ -904,7 +941,7 @@ int lb_set_st_pairs(lb_sim* s, int on) {
 }
 
 int lb_set_fv_lanes(lb_sim* s, int lanes) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_set_fv_lanes")) return rc;
     if (lanes != 0 && lanes != FV_LANES && lanes != FV_NARROW)
         return fail(LB_EINVAL, "lb_set_fv_lanes: lanes must be 0, %d or %d", FV_NARROW, FV_LANES);
     s->lanes = lanes;
@@ -913,7 +950,7 @@ int lb_set_fv_lanes(lb_sim* s, int lanes) {
 }
 
 int lb_set_fv_chunk(lb_sim* s, int rows) {
-    if (int rc = check_sim(s)) return rc;
+    if (int rc = check_free(s, "lb_set_fv_chunk")) return rc;
     if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
     s->chunk_h = rows;
     return LB_OK;
@@ -1076,6 +1113,8 @@ int lb_group_create(int32_t max_sims, void* stream, lb_group** out) {
 void lb_group_destroy(lb_group* g) {
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (lb_sim* m : g->sims)
+        if (m) { m->group = nullptr; m->group_slot = -1; m->chunk_h = 0; }
     group_drop_graph(g);
     if (g->d_args) (void)hipFree(g->d_args);
     if (g->d_items) (void)hipFree(g->d_items);
@@ -1091,8 +1130,8 @@ int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
     if (!s->has_init) return fail(LB_ESTATE, "lb_group_add: the simulation has no state yet");
     if (g->storage >= 0 && (s->p.storage != g->storage || s->p.thermal != g->thermal))
         return fail(LB_EINVAL, "lb_group_add: members must share storage format and thermal flag");
-    for (lb_sim* m : g->sims)
-        if (m == s) return fail(LB_EINVAL, "lb_group_add: already a member");
+    if (s->group == g) return fail(LB_EINVAL, "lb_group_add: already a member");
+    if (s->group) return fail(LB_ESTATE, "lb_group_add: already a member of another group");
     int k = 0;
     while (k < g->max_sims && g->sims[k]) ++k;
     if (k == g->max_sims) return fail(LB_ENOMEM, "lb_group_add: all %d slots are taken", g->max_sims);
@@ -1102,6 +1141,8 @@ int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
     g->storage = s->p.storage;
     g->thermal = s->p.thermal;
     g->sims[k] = s;
+    s->group = g;
+    s->group_slot = k;
     g->dirty = true;
     *slot = k;
     return LB_OK;
@@ -1112,7 +1153,10 @@ int lb_group_remove(lb_group* g, int32_t slot) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     const int64_t zero = 0;
     HIP_TRY(hipMemcpy(g->d_left + slot, &zero, sizeof zero, hipMemcpyHostToDevice));
-    g->sims[slot]->chunk_h = 0;   // alone again: its own automatic item height
+    lb_sim* s = g->sims[slot];
+    s->chunk_h = 0;   // alone again: its own automatic item height
+    s->group = nullptr;
+    s->group_slot = -1;
     g->sims[slot] = nullptr;
     g->dirty = true;
     bool any = false;
@@ -1399,23 +1443,28 @@ int lb3_set_grid(lb3_sim* s, const double* xf, int64_t nxf, const double* yf, in
                 m.insert(m.end(), st.begin(), st.end());
             }
         }
-        for (int d = 0; d < 3; ++d) {
-            s->faces[d].assign(f[d], f[d] + nf[d]);
+        for (int d = 0; d < 3; ++d)
             for (int i = 0; i < n[d]; ++i) dxyz.push_back(f[d][i + 1] - f[d][i]);
+        std::vector<float> mf;
+        if (s->p.storage != LB_F64) mf.assign(m.begin(), m.end());
+        const void* mh = s->p.storage == LB_F64 ? static_cast<const void*>(m.data()) : mf.data();
+        const size_t mbytes = s->p.storage == LB_F64 ? m.size() * sizeof(double) : mf.size() * sizeof(float);
+        // the new grid goes to new buffers; the old one stays in use if this fails
+        void* metric = nullptr;
+        void* dxyz_d = nullptr;
+        if (int rc = upload_all({{&metric, mh, mbytes}, {&dxyz_d, dxyz.data(), dxyz.size() * sizeof(double)}},
+                                "lb3_set_grid"))
+            return rc;
+        if (hipError_t e = hipStreamSynchronize(s->stream); e != hipSuccess) {
+            (void)hipFree(metric);
+            (void)hipFree(dxyz_d);
+            return fail(LB_EDEVICE, "set_grid: %s", hipGetErrorString(e));
         }
-        if (s->metric) { (void)hipFree(s->metric); s->metric = nullptr; }
-        if (s->dxyz) { (void)hipFree(s->dxyz); s->dxyz = nullptr; }
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        if (s->p.storage == LB_F64) {
-            HIP_TRY(hipMalloc(&s->metric, m.size() * sizeof(double)));
-            HIP_TRY(hipMemcpy(s->metric, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> mf(m.begin(), m.end());
-            HIP_TRY(hipMalloc(&s->metric, mf.size() * sizeof(float)));
-            HIP_TRY(hipMemcpy(s->metric, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice));
-        }
-        HIP_TRY(hipMalloc(&s->dxyz, dxyz.size() * sizeof(double)));
-        HIP_TRY(hipMemcpy(s->dxyz, dxyz.data(), dxyz.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (s->metric) (void)hipFree(s->metric);
+        if (s->dxyz) (void)hipFree(s->dxyz);
+        s->metric = metric;
+        s->dxyz = static_cast<double*>(dxyz_d);
+        for (int d = 0; d < 3; ++d) s->faces[d].assign(f[d], f[d] + nf[d]);
         s->has_grid = true;
         return LB_OK;
     } catch (...) {

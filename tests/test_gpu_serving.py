@@ -96,6 +96,46 @@ def test_group_membership_rules():
     g.close()
 
 
+def test_group_member_changes_only_through_its_group():
+    """While in a group a member is neither stepped, re-initialised,
+    re-gridded nor re-tuned alone (LB_ESTATE) and joins no second group;
+    destroying a member takes it out of its group, whose later launches run
+    the other members as before and give its slot to a new member."""
+    say("group member guards")
+    g, g2 = lb.Group(2, lb.current_stream()), lb.Group(1, lb.current_stream())
+    a = _rb_sim(64, 48, 1e6, 1.0, "bf16s", 5)
+    b = _rb_sim(80, 64, 1e6, 1.0, "bf16s", 6)
+    ref = _rb_sim(80, 64, 1e6, 1.0, "bf16s", 6)
+    sa = g.add(a, 20)
+    g.add(b, 20)
+    P = workloads.rb_params(1e6, 1.0, 64, 48, aspect=64 / 48, stretch=2.0)
+    rho, ux, uy, T = workloads.rb_fields(64, P["yf"], P["dT"], P["T0"], P["beta_g"], seed_index=5)
+    state = a.get_state()
+    calls = [lambda: a.step(1), lambda: a.init(rho, ux, uy, T), lambda: a.set_grid(P["xf"], P["yf"]),
+             lambda: a.set_state(state), lambda: a.rebase(), lambda: a.set_fv_lanes(0),
+             lambda: a.set_fv_chunk(8), lambda: g2.add(a, 5)]
+    for call in calls:
+        with pytest.raises(lb.LBError) as e:
+            call()
+        assert e.value.code == 4
+    g.step(10)
+    assert g.remaining()[sa] == 10
+    a.close()                          # leaves the group first
+    assert g.remaining()[sa] == 0
+    g.step(10)
+    assert g.remaining() == [0, 0]
+    ref.step(20)
+    assert np.array_equal(b.get_state(), ref.get_state())
+    c = _rb_sim(64, 48, 1e6, 1.0, "bf16s", 7)
+    assert g.add(c, 5) == sa
+    g.step(5)
+    assert g.remaining()[sa] == 0
+    g.remove(sa)
+    c.step(1)                          # alone again
+    g.close()
+    g2.close()
+
+
 @pytest.mark.parametrize("policy,min_cells", [("all", 0), ("srpt", 1), ("srpt", 30000)])
 def test_server_serves_a_trace_and_results_equal_alone(policy, min_cells):
     """Every request's Nusselt numbers equal those of the same simulation run
