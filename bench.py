@@ -174,7 +174,7 @@ def run_fv3d(lb, torch, n, steps, warmup, storage="f32", update="tiled"):
     return dict(seconds=wall, kernels=kt, cells=n ** 3, steps=steps, nonfinite=d["nonfinite"])
 
 
-def cpu_baseline(cfg, steps=2):
+def cpu_baseline(cfg, steps=3):
     """The FP64 oracle, as is: `steps` FV steps of the full workload on all
     host threads (the reported value); beside it, the oracle's ST step on the
     same grid size, and both on one thread on a 1024 x 1024 sample, so that
