@@ -176,6 +176,8 @@ int check_sim(const lb_sim* s) {
     return LB_OK;
 }
 
+void group_forget(lb_sim* s);
+
 // A group's captured launches hold the member's buffers and item layout, so
 // a member is neither stepped nor changed except through its group.
 int check_free(const lb_sim* s, const char* fn) {
@@ -594,7 +596,7 @@ int lb_create(const lb_params* p, lb_sim** out) {
 
 void lb_destroy(lb_sim* s) {
     if (!s) return;
-    if (s->group) (void)lb_group_remove(s->group, s->group_slot);
+    if (s->group && lb_group_remove(s->group, s->group_slot) != LB_OK) group_forget(s);
     (void)hipStreamSynchronize(s->stream);
     release(s);
     delete s;
@@ -979,6 +981,17 @@ struct lb_group {
 };
 
 namespace {
+
+// Drop a member from its group's slot table without touching the device
+// (its destruction after a failed lb_group_remove): the group's next step
+// rebuilds its launches without it.
+void group_forget(lb_sim* s) {
+    lb_group* g = s->group;
+    g->sims[s->group_slot] = nullptr;
+    g->dirty = true;
+    s->group = nullptr;
+    s->group_slot = -1;
+}
 
 // Rows per work item for the current members.  All items of one launch have
 // the same height h, so with B(h) blocks and `cap` of them resident at once
