@@ -2,7 +2,8 @@
 
 Requests (grid side n, Ra, Pr, steps) arrive over time.  A request is
 admitted, first come first served, as soon as a group slot is free and its
-device memory fits the HBM budget; it then keeps its state resident in HBM
+device memory fits the HBM budget (one that needs more than the whole budget
+is rejected at once and listed in the result); it then keeps its state resident in HBM
 until it has done exactly its steps, when its Nusselt numbers are read
 (FP64 device reductions) and its memory is released.  Admission, scheduling
 and completion happen only between group launches (graph boundaries).
@@ -105,7 +106,7 @@ class Server:
         pending = deque(sorted(trace, key=lambda r: r["arrival"]))
         queue = deque()
         resident = {}  # request id -> dict(req, sim, need, admitted, left, slot)
-        done = []
+        done, rejected = [], []
         used = 0.0
         cell_steps = 0
         t0 = time.perf_counter()
@@ -121,8 +122,13 @@ class Server:
             while queue and len(resident) < self.max_resident:
                 req = queue[0]
                 need = request_bytes(req["n"], self.storage)
-                if need > self.hbm_budget:
-                    raise ValueError(f"request {req['id']} needs {need:.3e} B, more than the whole budget")
+                if need > self.hbm_budget:   # can never fit: reject, serve the rest
+                    queue.popleft()
+                    rejected.append(dict(id=req["id"], n=req["n"], need_bytes=need))
+                    if log:
+                        log(f"req {req['id']:4d} n={req['n']:5d} rejected: needs {need:.3e} B, "
+                            f"more than the whole budget")
+                    continue
                 if used + need > self.hbm_budget:
                     break
                 queue.popleft()
@@ -178,7 +184,7 @@ class Server:
             phase["completion_s"] += clock() - t3
         makespan = clock()
         lat = np.array([d["latency"] for d in done])
-        return dict(requests=done, n_requests=len(done), makespan_s=makespan,
+        return dict(requests=done, n_requests=len(done), rejected=rejected, makespan_s=makespan,
                     p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
                     p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                     aggregate_mlups=cell_steps / makespan / 1e6 if makespan > 0 else None,

@@ -181,3 +181,16 @@ def test_server_preempts_a_long_request_and_it_resumes_exactly():
         sim.close()
         solo.close()
         assert by_id[req["id"]]["nu"] == nu, req["id"]
+
+
+def test_server_rejects_a_request_larger_than_the_budget():
+    """A request whose memory exceeds the whole HBM budget is rejected and
+    listed; every other request is still served."""
+    say("server rejects oversize request")
+    trace = workloads.serving_trace(n_requests=4, rate=50.0, side=(64, 96), ra=(1e6, 1e7), steps=(20, 40))
+    big = dict(trace[1], id=99, n=2048)
+    server = Server(storage="bf16", hbm_budget=2e8, max_sims=4, graph_steps=20)
+    stats = server.run(trace + [big])
+    server.close()
+    assert [r["id"] for r in stats["rejected"]] == [99]
+    assert sorted(r["id"] for r in stats["requests"]) == sorted(r["id"] for r in trace)
