@@ -160,6 +160,22 @@ struct lb_sim {
     int st_pairs = 1;         // ST, 16-bit storage: two cells per thread where nx is even
     lb_group* group = nullptr;  // the group this simulation is a member of, if any
     int group_slot = -1;
+    // non-finite flag: raised by the kernels on the device (d_bad), copied to
+    // pinned host memory (h_bad) after every lb_step
+    int* d_bad = nullptr;
+    int* h_bad = nullptr;
+    // captured step graphs of STEP_GRAPH_STEPS steps, by the state they start
+    // from (buffer A and steps since the last rebase) and the state they leave
+    struct StepGraph {
+        void* A0;
+        int64_t since0;
+        void* A1;
+        void* B1;
+        int64_t since1;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs;
+    hipStream_t cap = nullptr;   // private stream the graphs are captured on (the handle's may be the null stream)
     // timing
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -206,8 +222,22 @@ int upload_all(std::initializer_list<Upload> ups, const char* fn) {
     return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
 }
 
+// Drop the captured step graphs (their launches hold the handle's buffers,
+// metric, launch shape and rebase schedule).
+void drop_step_graphs(lb_sim* s) {
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+}
+
 // Release every device allocation of a handle (safe on partial creation).
 void release(lb_sim* s) {
+    drop_step_graphs(s);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    s->cap = nullptr;
+    if (s->d_bad) (void)hipFree(s->d_bad);
+    if (s->h_bad) (void)hipHostFree(s->h_bad);
+    s->d_bad = nullptr;
+    s->h_bad = nullptr;
     if (s->A) (void)hipFree(s->A);
     if (s->B) (void)hipFree(s->B);
     if (s->metric) (void)hipFree(s->metric);
@@ -314,6 +344,7 @@ FvArgs<R> fv_args(const lb_sim* s, const void* src, void* dst, void* aux, bool c
     a.rho_x1 = R(s->p.rho_x1);
     a.tref = reinterpret_cast<const R*>(s->tref);  // float rows for FP32 arithmetic, NULL for FP64
     a.qref = reinterpret_cast<const R*>(s->qref);  // split storage only
+    a.bad = s->d_bad;
     return a;
 }
 
@@ -396,6 +427,7 @@ int st_launch(lb_sim* s) {
     a.ref_g = s->p.storage == LB_F64 ? 0.0 : s->p.T_ref;
     a.tref = s->tref;
     a.pairs = s->st_pairs;
+    a.bad = s->d_bad;
     int rc = record_event(s, 2);
     if (rc) return rc;
     hipError_t e = launch_st(s->p.storage, s->p.thermal, (s->p.flags & LB_FLAG_STREAM_ONLY) != 0, a, s->stream);
@@ -437,6 +469,98 @@ int run_diagnostics(lb_sim* s, double* host8) {
     host8[6] = o[D_VOL];
     host8[7] = o[D_BAD];
     if (o[D_BAD] != 0.0) s->unstable = true;
+    return LB_OK;
+}
+
+// Clear the non-finite flag (a new state).
+int clear_flag(lb_sim* s) {
+    HIP_TRY(hipMemsetAsync(s->d_bad, 0, sizeof(int), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    *s->h_bad = 0;
+    s->unstable = false;
+    return LB_OK;
+}
+
+// Wait for the handle's stream and read its non-finite flag.
+int poll_flag(lb_sim* s) {
+    HIP_TRY(hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (*s->h_bad) s->unstable = true;
+    return LB_OK;
+}
+
+bool flagged(lb_sim* s) {
+    if (*static_cast<volatile int*>(s->h_bad)) s->unstable = true;
+    return s->unstable;
+}
+
+// Enqueue n time steps as single launches (the stepping of lb_step).
+int enqueue_steps(lb_sim* s, int64_t nsteps) {
+    for (int64_t n = 0; n < nsteps; ++n) {
+        int rc;
+        switch (s->p.scheme) {
+            case LB_FV_HEUN:
+                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
+                if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
+                break;
+            case LB_FV_SEMI:
+            case LB_FV_EULER:
+                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;
+                std::swap(s->A, s->B);
+                break;
+            default:
+                if ((rc = st_launch(s))) return rc;
+        }
+        if (s->tref && s->rebase_every > 0 && ++s->since_rebase >= s->rebase_every) {
+            hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
+            s->since_rebase = 0;
+        }
+    }
+    return LB_OK;
+}
+
+// The captured graph of STEP_GRAPH_STEPS steps from the handle's current
+// state (capturing it on first use).  Kernel arguments are captured by
+// value, so a graph is valid while the buffers, metric, launch shape and
+// rebase interval it was made with are unchanged; the calls that change
+// them drop the graphs.
+constexpr int64_t STEP_GRAPH_STEPS = 32;
+constexpr size_t STEP_GRAPHS_KEPT = 8;
+int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
+    for (const auto& g : s->graphs)
+        if (g.A0 == s->A && g.since0 == s->since_rebase) { *out = &g; return LB_OK; }
+    if (s->p.scheme != LB_ST && s->chunk_h <= 0) s->chunk_h = auto_chunk(s);
+    if (!s->cap) HIP_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));  // default priority
+    lb_sim::StepGraph g{s->A, s->since_rebase, nullptr, nullptr, 0, nullptr};
+    void* A0 = s->A;
+    void* B0 = s->B;
+    hipStream_t user = s->stream;
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed));
+    s->stream = s->cap;   // the launches below are recorded, not run
+    int rc = enqueue_steps(s, STEP_GRAPH_STEPS);
+    s->stream = user;
+    hipError_t e = hipStreamEndCapture(s->cap, &graph);
+    g.A1 = s->A;
+    g.B1 = s->B;
+    g.since1 = s->since_rebase;
+    s->A = A0;   // the graph has not run yet
+    s->B = B0;
+    s->since_rebase = g.since0;
+    if (rc != LB_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != LB_OK ? rc : fail(LB_EDEVICE, "lb_step: graph capture failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step: graph instantiation failed: %s", hipGetErrorString(e));
+    if (s->graphs.size() >= STEP_GRAPHS_KEPT) {
+        (void)hipGraphExecDestroy(s->graphs.front().exec);
+        s->graphs.erase(s->graphs.begin());
+    }
+    s->graphs.push_back(g);
+    *out = &s->graphs.back();
     return LB_OK;
 }
 
@@ -581,12 +705,16 @@ int lb_create(const lb_params* p, lb_sim** out) {
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess ||
             (p->thermal && p->storage != LB_F64 && (e = hipMalloc(&s->tref, sizeof(float) * p->ny)) != hipSuccess) ||
-            (p->thermal && is_split_storage(p->storage) && (e = hipMalloc(&s->qref, sizeof(float) * p->ny)) != hipSuccess)) {
+            (p->thermal && is_split_storage(p->storage) && (e = hipMalloc(&s->qref, sizeof(float) * p->ny)) != hipSuccess) ||
+            (e = hipMalloc(&s->d_bad, sizeof(int))) != hipSuccess ||
+            (e = hipHostMalloc(&s->h_bad, sizeof(int), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMemset(s->d_bad, 0, sizeof(int))) != hipSuccess) {
             release(s);
             delete s;
             return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, "lb_create: device allocation failed: %s",
                         hipGetErrorString(e));
         }
+        *s->h_bad = 0;
         *out = s;
         return LB_OK;
     } catch (...) {
@@ -646,6 +774,7 @@ int lb_set_grid(lb_sim* s, const double* x_faces, int64_t n_xf, const double* y_
             (void)hipFree(dxy_d);
             return fail(LB_EDEVICE, "set_grid: %s", hipGetErrorString(e));
         }
+        drop_step_graphs(s);
         if (s->metric) (void)hipFree(s->metric);
         if (s->dxy) (void)hipFree(s->dxy);
         s->metric = metric;
@@ -691,7 +820,8 @@ int lb_init(lb_sim* s, const double* rho, const double* ux, const double* uy, co
         else if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) rc = fail(LB_EDEVICE, "init failed: %s", hipGetErrorString(e));
     }
     for (double* p : d) if (p) (void)hipFree(p);
-    if (rc == LB_OK) { s->has_init = true; s->unstable = false; }
+    if (rc == LB_OK) rc = clear_flag(s);
+    if (rc == LB_OK) s->has_init = true;
     return rc;
 }
 
@@ -699,36 +829,34 @@ int lb_step(lb_sim* s, int64_t nsteps) {
     if (int rc = check_free(s, "lb_step")) return rc;
     if (!s->has_init) return fail(LB_ESTATE, "lb_step: call lb_init (or lb_set_state) first");
     if (nsteps < 0) return fail(LB_EINVAL, "lb_step: negative step count");
-    if (s->unstable) return fail(LB_EUNSTABLE, "lb_step: non-finite populations were detected");
-    for (int64_t n = 0; n < nsteps; ++n) {
-        int rc;
-        switch (s->p.scheme) {
-            case LB_FV_HEUN:
-                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
-                if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
-                break;
-            case LB_FV_SEMI:
-            case LB_FV_EULER:
-                if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;
-                std::swap(s->A, s->B);
-                break;
-            default:
-                if ((rc = st_launch(s))) return rc;
-        }
-        if (s->tref && s->rebase_every > 0 && ++s->since_rebase >= s->rebase_every) {
-            hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
-            if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
-            s->since_rebase = 0;
-        }
+    if (flagged(s)) return fail(LB_EUNSTABLE, "lb_step: non-finite populations were detected");
+    if (nsteps == 0) return LB_OK;
+    // Whole blocks of STEP_GRAPH_STEPS steps replay a captured graph, unless
+    // every launch is timed or the caller is capturing the stream itself.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s->stream, &cap));
+    const bool graphs = !s->timing && cap == hipStreamCaptureStatusNone;
+    int64_t left = nsteps;
+    while (graphs && left >= STEP_GRAPH_STEPS) {
+        const lb_sim::StepGraph* g = nullptr;
+        if (int rc = step_graph(s, &g)) return rc;
+        HIP_TRY(hipGraphLaunch(g->exec, s->stream));
+        s->A = g->A1;
+        s->B = g->B1;
+        s->since_rebase = g->since1;
+        left -= STEP_GRAPH_STEPS;
     }
-    if (nsteps > 0)
-        if (int rc = record_event(s, -1)) return rc;
+    if (int rc = enqueue_steps(s, left)) return rc;
+    if (int rc = record_event(s, -1)) return rc;
+    // the flag as of the end of these steps, read by the next call
+    HIP_TRY(hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     return LB_OK;
 }
 
 int lb_sync(lb_sim* s) {
     if (int rc = check_sim(s)) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (flagged(s)) return fail(LB_EUNSTABLE, "lb_sync: non-finite populations were detected");
     return LB_OK;
 }
 
@@ -753,7 +881,8 @@ int lb_diagnostics(lb_sim* s, double* out) {
     if (int rc = check_sim(s)) return rc;
     if (!out) return fail(LB_EINVAL, "lb_diagnostics: NULL output");
     if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics: no state");
-    return run_diagnostics(s, out);
+    if (int rc = run_diagnostics(s, out)) return rc;
+    return poll_flag(s);
 }
 
 int lb_profiles(lb_sim* s, double* out, int64_t n_out) {
@@ -811,9 +940,11 @@ int lb_nusselt(lb_sim* s, double* nu_bottom, double* nu_top, double* nu_vol) {
     if (!s->has_init) return fail(LB_ESTATE, "lb_nusselt: no state");
     double o[8];
     if (int rc = run_diagnostics(s, o)) return rc;
+    if (int rc = poll_flag(s)) return rc;
     if (nu_bottom) *nu_bottom = o[3];
     if (nu_top) *nu_top = o[4];
     if (nu_vol) *nu_vol = o[5];
+    if (s->unstable) return fail(LB_EUNSTABLE, "lb_nusselt: the simulation holds non-finite populations");
     return LB_OK;
 }
 
@@ -839,6 +970,26 @@ int lb_set_populations(lb_sim* s, const double* f, const double* g) {
     if (!f || (s->p.thermal && !g)) return fail(LB_EINVAL, "lb_set_populations: NULL input");
     if (!s->has_grid) return fail(LB_ESTATE, "lb_set_populations: call lb_set_grid first");
     const size_t nf = 9 * size_t(s->plane);
+    try {
+        // the per-row references the state is encoded with, as lb_init sets
+        // them: the row means of T = sum g, and no heat-flux reference
+        if (s->tref) {
+            std::vector<float> tr(s->p.ny);
+            for (int j = 0; j < s->p.ny; ++j) {
+                double m = 0.0;
+                for (int i = 0; i < s->p.nx; ++i)
+                    for (int a = 0; a < 9; ++a) m += g[size_t(a) * size_t(s->plane) + size_t(j) * s->p.nx + i];
+                tr[j] = float(m / s->p.nx);
+            }
+            HIP_TRY(hipMemcpy(s->tref, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice));
+        }
+        if (s->qref) {
+            std::vector<float> z(s->p.ny, 0.0f);
+            HIP_TRY(hipMemcpy(s->qref, z.data(), sizeof(float) * z.size(), hipMemcpyHostToDevice));
+        }
+    } catch (...) {
+        return fail(LB_ENOMEM, "lb_set_populations: out of host memory");
+    }
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, size_t(s->nsp) * nf * sizeof(double)));
     hipError_t e = hipMemcpyAsync(d, f, nf * sizeof(double), hipMemcpyHostToDevice, s->stream);
@@ -847,8 +998,9 @@ int lb_set_populations(lb_sim* s, const double* f, const double* g) {
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_set_populations failed: %s", hipGetErrorString(e));
+    if (int rc = clear_flag(s)) return rc;
+    s->since_rebase = 0;
     s->has_init = true;
-    s->unstable = false;
     return LB_OK;
 }
 
@@ -887,8 +1039,8 @@ int lb_set_state(lb_sim* s, const void* host, size_t bytes) {
     if (s->tref) { HIP_TRY(hipMemcpyAsync(s->tref, h, row, hipMemcpyHostToDevice, s->stream)); h += row; }
     if (s->qref) HIP_TRY(hipMemcpyAsync(s->qref, h, row, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (int rc = clear_flag(s)) return rc;
     s->has_init = true;
-    s->unstable = false;
     return LB_OK;
 }
 
@@ -932,6 +1084,7 @@ int lb_set_rebase(lb_sim* s, int64_t every) {
     if (every < 0) return fail(LB_EINVAL, "lb_set_rebase: negative interval");
     s->rebase_every = every;
     s->since_rebase = 0;
+    drop_step_graphs(s);
     return LB_OK;
 }
 
@@ -939,6 +1092,7 @@ int lb_set_st_pairs(lb_sim* s, int on) {
     if (int rc = check_sim(s)) return rc;
     if (on != 0 && on != 1) return fail(LB_EINVAL, "lb_set_st_pairs: on must be 0 or 1");
     s->st_pairs = on;
+    drop_step_graphs(s);
     return LB_OK;
 }
 
@@ -948,6 +1102,7 @@ int lb_set_fv_lanes(lb_sim* s, int lanes) {
         return fail(LB_EINVAL, "lb_set_fv_lanes: lanes must be 0, %d or %d", FV_NARROW, FV_LANES);
     s->lanes = lanes;
     s->chunk_h = 0;  // re-chosen at the next step for the new item width
+    drop_step_graphs(s);
     return LB_OK;
 }
 
@@ -955,6 +1110,7 @@ int lb_set_fv_chunk(lb_sim* s, int rows) {
     if (int rc = check_free(s, "lb_set_fv_chunk")) return rc;
     if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
     s->chunk_h = rows;
+    drop_step_graphs(s);
     return LB_OK;
 }
 
@@ -975,6 +1131,7 @@ struct lb_group {
     int n_wide = 0;
     int64_t* d_left = nullptr;
     int chunk = 0;              // rows per work item: 0 chosen at each rebuild (group_chunk), else fixed
+    std::vector<int> stale;     // free slots whose remaining-steps counter is to be cleared at the next rebuild
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     int64_t exec_steps = 0;
@@ -988,9 +1145,13 @@ namespace {
 void group_forget(lb_sim* s) {
     lb_group* g = s->group;
     g->sims[s->group_slot] = nullptr;
+    g->stale.push_back(s->group_slot);
     g->dirty = true;
     s->group = nullptr;
     s->group_slot = -1;
+    bool any = false;
+    for (lb_sim* m : g->sims) any = any || m;
+    if (!any) { g->storage = -1; g->thermal = -1; }
 }
 
 // Rows per work item for the current members.  All items of one launch have
@@ -1062,6 +1223,11 @@ int group_rebuild(lb_group* g) {
         }
     HIP_TRY(hipStreamSynchronize(g->stream));
     HIP_TRY(hipMemcpy(g->d_args, host.data(), host.size(), hipMemcpyHostToDevice));
+    for (int k : g->stale) {
+        const int64_t zero = 0;
+        if (!g->sims[k]) HIP_TRY(hipMemcpy(g->d_left + k, &zero, sizeof zero, hipMemcpyHostToDevice));
+    }
+    g->stale.clear();
     if (items.size() > g->items_cap) {
         if (g->d_items) (void)hipFree(g->d_items);
         g->d_items = nullptr;
@@ -1156,6 +1322,7 @@ int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
     g->sims[k] = s;
     s->group = g;
     s->group_slot = k;
+    drop_step_graphs(s);   // the group sets its own item height
     g->dirty = true;
     *slot = k;
     return LB_OK;
@@ -1170,12 +1337,13 @@ int lb_group_remove(lb_group* g, int32_t slot) {
     s->chunk_h = 0;   // alone again: its own automatic item height
     s->group = nullptr;
     s->group_slot = -1;
+    drop_step_graphs(s);
     g->sims[slot] = nullptr;
     g->dirty = true;
     bool any = false;
     for (lb_sim* m : g->sims) any = any || m;
     if (!any) { g->storage = -1; g->thermal = -1; }
-    return LB_OK;
+    return poll_flag(s);   // what the group's launches left in its flag
 }
 
 int lb_group_set_chunk(lb_group* g, int32_t rows) {

@@ -490,9 +490,10 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
 }
 
 // Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
+// Returns m0 + m3, which is finite exactly when the stored moments are.
 template <class R, class S, bool TH>
-__device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
-                                   const R Tr, const R q) {
+__device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
+                                const R Tr, const R q) {
     using IO = Narrow<S>;
     constexpr float rs = split_scale<S>::value;
     R m[4];
@@ -524,6 +525,7 @@ __device__ inline void store_split(Buf b, uint32_t cell, uint32_t G, const R* df
         __builtin_amdgcn_raw_buffer_store_b96(u32x3{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8])}, b.r, v12,
                                               G + G / 2, 0);
     }
+    return m[0] + m[3];
 }
 
 // Make this row's LDS writes visible to the other lanes of the item.  A
@@ -662,11 +664,20 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if constexpr (SPLIT)
             if (CORR) load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
     };
-    // store the offsets of a cell of a row whose thermal reference is trow
+    // store the offsets of a cell of a row whose thermal reference is trow,
+    // and note whether the cell is finite (its moments; otherwise its rest
+    // populations): the item raises the non-finite flag once, at its end
+    bool bad = false;
     auto store_any = [&](const Buf& b, uint32_t cell, const R* f, const R* g, const R trow, const R qrow)
                          __attribute__((always_inline)) {
-        if constexpr (SPLIT) store_split<R, S, TH>(b, cell, gb, f, g, k, trow, qrow);
-        else store_cell<R, S, TH>(b, cell, gb, ro, f, g);
+        R chk;
+        if constexpr (SPLIT) {
+            chk = store_split<R, S, TH>(b, cell, gb, f, g, k, trow, qrow);
+        } else {
+            store_cell<R, S, TH>(b, cell, gb, ro, f, g);
+            chk = TH ? f[0] + g[0] : f[0];
+        }
+        bad = bad || !__builtin_isfinite(chk);
     };
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
@@ -872,6 +883,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         row_step(r + 2, Slot<2>{});
         row_step(r + 3, Slot<3>{});
     }
+    if (A.bad) raise_flag(A.bad, bad);
 }
 
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32
@@ -943,6 +955,7 @@ __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
     for (int q = 0; q < int(sizeof(FvArgs<R>) / 4); ++q) words[q] = src[q];
     FvArgs<R> A;
     __builtin_memcpy(&A, words, sizeof(FvArgs<R>));
+    if (A.bad && *(volatile const int*)A.bad) return;  // a member that blew up is not stepped further
     fv_block<R, S, TH, CORR>(A, it.y, narrow, lds_mem);
 }
 

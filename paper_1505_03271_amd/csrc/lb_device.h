@@ -206,4 +206,17 @@ __device__ inline void eq_force(const Macro<R>& m, EqForce<R>& e) {
     }
 }
 
+// ---- non-finite flag -----------------------------------------------------
+// A lane whose value is not finite raises the simulation's flag: one atomic
+// per wave (its lowest such lane), through the vector memory path.  A
+// blow-up makes every population of a cell non-finite within a step or two
+// (each depends on the cell's density), so checking one value per species
+// and cell suffices.
+__device__ inline void raise_flag(int* flag, bool bad) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(bad);
+    if (m == 0 || !bad) return;
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    if (below == 0) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace lbk

@@ -54,6 +54,8 @@ struct FvArgs {
     const R* tref;     // per-row thermal reference (g stored as g - w_a tref[row]), or NULL: k.ref_g
     const R* qref;     // split thermal storage: per-row heat-flux reference, the stored g residual is
                        // r_a - w_a c_ay qref[row] (NULL: 0)
+    int* bad;          // set to 1 when a stored cell is not finite (NULL: no check); the serving
+                       // kernel skips a simulation whose flag is set
 };
 
 struct StArgs {
@@ -67,6 +69,7 @@ struct StArgs {
     double ref_f, ref_g;
     const float* tref;   // per-row thermal reference of the stored g, or NULL
     int pairs;           // FP32 or 16-bit storage, even nx: two cells per thread (st_step_pair)
+    int* bad;            // set to 1 when a collided cell is not finite (NULL: no check)
 };
 
 // Host launchers (defined in the .hip files).  `storage` selects the
@@ -148,6 +151,7 @@ struct Fv3Args {
     R az;              // constant z acceleration (the Boussinesq term is added along z)
     R Tb, Tt;          // z wall temperatures
     int gather;        // update kernel: 0 tiles staged in LDS, 1 one thread per cell with direct loads
+    int* bad;          // set to 1 when a cell's density or temperature is not finite (NULL: no check)
 };
 // One FV stage (stage + update kernels) of a 3D simulation.
 hipError_t launch_fv3(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);

@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(256) st_step(StArgs A) {
         }
     }
     st_collide<R, TH>(A, f, g, fp, gp);
+    if (A.bad) raise_flag(A.bad, !__builtin_isfinite(TH ? fp[0] + gp[0] : fp[0]));
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         Codec<S>::template store<R>(dst + d[a].slot, st_out_f<R, S, TH>(A, a, fp[a]));
@@ -171,6 +172,8 @@ __global__ void __launch_bounds__(256) st_step_pair(StArgs A) {
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) st_collide<R, TH>(A, f[q], g[q], fp[q], gp[q]);
+    if (A.bad) raise_flag(A.bad, !__builtin_isfinite(TH ? (fp[0][0] + gp[0][0]) + (fp[1][0] + gp[1][0])
+                                                        : fp[0][0] + fp[1][0]));
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const StDest d0 = st_dest(A, i0, j, a), d1 = st_dest(A, i0 + 1, j, a);

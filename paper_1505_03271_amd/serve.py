@@ -5,7 +5,10 @@ admitted, first come first served, as soon as a group slot is free and its
 device memory fits the HBM budget (one that needs more than the whole budget
 is rejected at once and listed in the result); it then keeps its state resident in HBM
 until it has done exactly its steps, when its Nusselt numbers are read
-(FP64 device reductions) and its memory is released.  Admission, scheduling
+(FP64 device reductions) and its memory is released.  A request whose
+populations became non-finite (the kernels raise its flag, and the group
+skips it from then on) is listed as failed, with no result, and is left out
+of the latency and throughput figures.  Admission, scheduling
 and completion happen only between group launches (graph boundaries).
 
 Which admitted requests run in the next launch is the policy:
@@ -34,7 +37,9 @@ from collections import deque
 
 import numpy as np
 
-from . import Group, Sim, current_stream, cell_bytes
+from . import Group, LBError, Sim, current_stream, cell_bytes
+
+LB_EUNSTABLE = 5
 
 POLICIES = ("all", "srpt")
 
@@ -69,7 +74,9 @@ class Server:
     def _make(self, req):
         import workloads
         n = req["n"]
-        P = workloads.rb_params(req["Ra"], req["Pr"], n, n, aspect=1.0, stretch=self.stretch)
+        # cfl (optional, default 1): dt in units of the smallest cell
+        P = workloads.rb_params(req["Ra"], req["Pr"], n, n, aspect=1.0, stretch=self.stretch,
+                                cfl=req.get("cfl", 1.0))
         rho, ux, uy, T = workloads.rb_fields(n, P["yf"], P["dT"], P["T0"], P["beta_g"],
                                             seed_index=1000 + req["id"])
         sim = Sim(n, n, scheme="heun", storage=self.storage, thermal=True, wall_y=True, dt=P["dt"], tau=P["tau"],
@@ -106,7 +113,7 @@ class Server:
         pending = deque(sorted(trace, key=lambda r: r["arrival"]))
         queue = deque()
         resident = {}  # request id -> dict(req, sim, need, admitted, left, slot)
-        done, rejected = [], []
+        done, rejected, failed = [], [], []
         used = 0.0
         cell_steps = 0
         t0 = time.perf_counter()
@@ -168,12 +175,23 @@ class Server:
                 if r["left"] > 0:
                     continue
                 req = r["req"]
-                nu = r["sim"].nusselt()
+                try:
+                    nu = r["sim"].nusselt()   # raises LB_EUNSTABLE if the run blew up
+                except LBError as e:
+                    if e.code != LB_EUNSTABLE:
+                        raise
+                    nu = None
                 t_done = clock()
                 self.group.remove(r["slot"])
                 r["sim"].close()
                 del resident[k]
                 used -= r["need"]
+                if nu is None:   # not a result: listed apart, out of the latency and throughput figures
+                    failed.append(dict(id=req["id"], n=req["n"], steps=req["steps"], Ra=req["Ra"], Pr=req["Pr"],
+                                       finished=t_done, reason="non-finite populations"))
+                    if log:
+                        log(f"req {req['id']:4d} n={req['n']:5d} failed: non-finite populations")
+                    continue
                 cell_steps += req["n"] ** 2 * req["steps"]
                 done.append(dict(id=req["id"], n=req["n"], steps=req["steps"], arrival=req["arrival"] * time_scale,
                                  admitted=r["admitted"], finished=t_done, latency=t_done - req["arrival"] * time_scale,
@@ -184,7 +202,7 @@ class Server:
             phase["completion_s"] += clock() - t3
         makespan = clock()
         lat = np.array([d["latency"] for d in done])
-        return dict(requests=done, n_requests=len(done), rejected=rejected, makespan_s=makespan,
+        return dict(requests=done, n_requests=len(done), rejected=rejected, failed=failed, makespan_s=makespan,
                     p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
                     p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
                     aggregate_mlups=cell_steps / makespan / 1e6 if makespan > 0 else None,

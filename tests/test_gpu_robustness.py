@@ -8,6 +8,7 @@ import pytest
 
 import paper_1505_03271_amd as lb
 import workloads
+from gpu_common import random_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -200,8 +201,10 @@ def test_onset_rates_of_split_storage_with_renewed_references(storage, tol):
 
 def test_explicit_euler_beyond_its_limit_is_reported():
     """eq:euler is stable only for dt <= 2 tau (sec. 2.2.2): at dt = 3 tau a
-    perturbed flow blows up, the diagnostics flag it and the next step is
-    refused with LB_EUNSTABLE."""
+    perturbed flow blows up.  The kernels raise the simulation's non-finite
+    flag themselves, so without any diagnostics call the next
+    synchronisation reports LB_EUNSTABLE and further steps are refused; the
+    diagnostics agree."""
     nx, ny, tau = 32, 32, 0.2
     say("euler beyond 2 tau")
     sim = lb.Sim(nx, ny, scheme="euler", storage="f32", dt=3 * tau, tau=tau, stream=lb.current_stream())
@@ -210,10 +213,79 @@ def test_explicit_euler_beyond_its_limit_is_reported():
     sim.init(1 + 0.01 * r.standard_normal((ny, nx)), 0.02 * r.standard_normal((ny, nx)),
              0.02 * r.standard_normal((ny, nx)))
     sim.step(3000)
-    assert sim.diagnostics()["nonfinite"] == 1.0
+    with pytest.raises(lb.LBError) as e:
+        sim.sync()
+    assert e.value.code == 5
     with pytest.raises(lb.LBError) as e:
         sim.step(1)
     assert e.value.code == 5
+    assert sim.diagnostics()["nonfinite"] == 1.0
+
+
+@pytest.mark.parametrize("scheme,storage", [("heun", "f64"), ("heun", "f32"), ("heun", "bf16"), ("heun", "bf16s"),
+                                            ("heun", "f16s"), ("semi", "f32"), ("st", "bf16"), ("st", "f32")])
+def test_nonfinite_population_raises_the_flag_within_two_steps(scheme, storage):
+    """A single non-finite population at one cell: within two steps the
+    kernels have raised the flag (every population of a cell depends on its
+    density), lb_sync reports LB_EUNSTABLE and lb_step refuses to go on;
+    a new state (lb_init) clears it."""
+    nx, ny = 48, 40
+    say(f"non-finite flag {scheme} {storage}")
+    xf, yf = workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny)
+    kw = dict(thermal=True, wall_y=True, tau=0.3, tau_g=0.4, beta_g=1e-5, T_bottom=0.1, T_top=-0.1)
+    if scheme != "st":
+        kw["dt"] = 0.5
+    sim = lb.Sim(nx, ny, scheme=scheme, storage=storage, stream=lb.current_stream(), **kw)
+    sim.set_grid(xf, yf)
+    fields = random_fields(nx, ny, 3, amp=0.01)
+    sim.init(*fields)
+    sim.step(2)
+    sim.sync()
+    f, g = sim.populations()
+    g[6, 17, 30] = np.inf if storage == "f32" else np.nan
+    sim.set_populations(f, g)
+    sim.sync()                       # a new state: the flag is clear
+    sim.step(2)
+    with pytest.raises(lb.LBError) as e:
+        sim.sync()
+    assert e.value.code == 5
+    with pytest.raises(lb.LBError) as e:
+        sim.step(1)
+    assert e.value.code == 5
+    sim.init(*fields)                # a new state clears the flag
+    sim.step(2)
+    sim.sync()
+    assert sim.diagnostics()["nonfinite"] == 0.0
+    sim.close()
+
+
+def test_set_populations_on_a_fresh_handle():
+    """lb_set_populations without lb_init: the per-row references the state
+    is encoded with come from the given populations, so narrow and split
+    thermal storage give back what was set, to their rounding."""
+    nx, ny = 40, 24
+    say("set_populations on a fresh handle")
+    src = lb.Sim(nx, ny, scheme="heun", storage="f64", thermal=True, wall_y=True, dt=0.5, tau=0.3, tau_g=0.4,
+                 stream=lb.current_stream())
+    src.set_grid(workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny))
+    rho, ux, uy, T = random_fields(nx, ny, 8, amp=0.02)
+    src.init(rho, ux, uy, T + 3.0)   # far from the storage's default reference
+    f, g = src.populations()
+    src.close()
+    for storage, tol in (("bf16", 2.0 ** -8), ("f16", 2.0 ** -10), ("bf16s", 2.0 ** -7), ("f16s", 2.0 ** -9)):
+        sim = lb.Sim(nx, ny, scheme="heun", storage=storage, thermal=True, wall_y=True, dt=0.5, tau=0.3, tau_g=0.4,
+                     stream=lb.current_stream())
+        sim.set_grid(workloads.faces_uniform(nx, nx), workloads.faces_uniform(ny, ny))
+        sim.set_populations(f, g)
+        f2, g2 = sim.populations()
+        assert np.all(np.isfinite(f2)) and np.all(np.isfinite(g2)), storage
+        ef = np.abs(f2 - f).max() / np.abs(f).max()
+        eg = np.abs(g2 - g).max() / np.abs(g).max()
+        say(f"  {storage}: f {ef:.2e} g {eg:.2e}")
+        assert ef < tol and eg < tol, storage
+        sim.step(3)
+        sim.sync()
+        sim.close()
 
 
 def test_stream_probe_reports_plausible_bandwidths():

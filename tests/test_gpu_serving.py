@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import paper_1505_03271_amd as lb
 import workloads
 from paper_1505_03271_amd.serve import Server
@@ -19,9 +20,23 @@ def say(msg):
     sys.stdout.flush()
 
 
-def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
+def _rb_case(n_x, n_y, Ra, Pr, seed, stretch=2.0):
     P = workloads.rb_params(Ra, Pr, n_x, n_y, aspect=n_x / n_y, stretch=stretch)
-    rho, ux, uy, T = workloads.rb_fields(n_x, P["yf"], P["dT"], P["T0"], P["beta_g"], seed_index=seed)
+    return P, workloads.rb_fields(n_x, P["yf"], P["dT"], P["T0"], P["beta_g"], seed_index=seed)
+
+
+def _rb_oracle(n_x, n_y, Ra, Pr, seed, steps, stretch=2.0):
+    """The same Rayleigh-Benard case stepped by the FP64 oracle."""
+    P, fields = _rb_case(n_x, n_y, Ra, Pr, seed, stretch)
+    c = oracle.Case(n_x, n_y, scheme="heun", wall_y=True, thermal=True, dt=P["dt"], tau=P["tau"], tau_g=P["tau_g"],
+                    beta_g=P["beta_g"], T0=P["T0"], T_bottom=P["T_bottom"], T_top=P["T_top"], xf=P["xf"], yf=P["yf"])
+    c.init(*fields)
+    c.step(steps)
+    return c
+
+
+def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
+    P, (rho, ux, uy, T) = _rb_case(n_x, n_y, Ra, Pr, seed, stretch)
     sim = lb.Sim(n_x, n_y, scheme="heun", storage=storage, thermal=True, wall_y=True, dt=P["dt"], tau=P["tau"],
                  tau_g=P["tau_g"], beta_g=P["beta_g"], T0=P["T0"], T_bottom=P["T_bottom"], T_top=P["T_top"],
                  stream=lb.current_stream())
@@ -59,6 +74,15 @@ def test_group_members_match_alone_bit_exact(storage, chunk):
     assert all(left[slots[k]] == 0 for k in slots)
     for k in range(len(CASES)):
         assert np.array_equal(sims[k].get_state(), alone[k]), f"member {k}"
+    if storage == "f64":
+        # the group's result is the method's: each FP64 member equals the
+        # oracle's run of its case (eq:semi-heun) to 1e-12
+        for k, (nx, ny, Ra, Pr, steps) in enumerate(CASES):
+            ref = _rb_oracle(nx, ny, Ra, Pr, 100 + k, steps)
+            f, gg = sims[k].populations()
+            err = max(np.abs(f - ref.f).max() / np.abs(ref.f).max(), np.abs(gg - ref.g).max() / np.abs(ref.g).max())
+            say(f"  member {k} ({nx}x{ny}, {steps} steps) vs oracle: {err:.2e}")
+            assert err < 1e-12, f"member {k}"
     for k in slots:
         g.remove(slots[k])
     assert g.remaining() == [0] * 8
@@ -194,3 +218,20 @@ def test_server_rejects_a_request_larger_than_the_budget():
     server.close()
     assert [r["id"] for r in stats["rejected"]] == [99]
     assert sorted(r["id"] for r in stats["requests"]) == sorted(r["id"] for r in trace)
+
+
+def test_server_lists_a_blown_up_request_as_failed():
+    """A request whose time step is far beyond the scheme's stability limit
+    (four times the smallest cell) blows up in the group: the kernels raise
+    its non-finite flag, the group stops stepping it, and the server lists
+    it as failed, with no Nusselt number and out of the latency and
+    throughput figures; the other requests are served as usual."""
+    say("server lists a blown-up request as failed")
+    trace = workloads.serving_trace(n_requests=3, rate=50.0, side=(64, 96), ra=(1e6, 1e7), steps=(40, 80))
+    bad = dict(trace[1], id=77, n=64, steps=1500, cfl=4.0)
+    server = Server(storage="bf16s", hbm_budget=2e8, max_sims=4, graph_steps=50, policy="all")
+    stats = server.run(trace + [bad])
+    server.close()
+    assert [r["id"] for r in stats["failed"]] == [77]
+    assert sorted(r["id"] for r in stats["requests"]) == sorted(r["id"] for r in trace)
+    assert all(np.all(np.isfinite(r["nu"])) for r in stats["requests"])

@@ -647,3 +647,108 @@ def test_pressure_driven_channel_reaches_poiseuille():
     u_max = (drho / 3.0 / L_x) * L_y ** 2 / (8.0 * nu * 1.0)
     centre = m["ux"][ny // 2 - 1:ny // 2 + 1, nx // 2].mean()
     assert abs(centre / u_max - 1) < 0.03
+
+
+# ------------------------------------------- pins added for the grid, the ---
+# ------------------------------------- thermal energy and the wall rule -----
+
+def test_sinh_grid_printed_formula_and_properties():
+    """eq:grids, hyperbolic sine: two branches that meet at i = N/2 (the
+    low branch up to N/2, the mirrored one from N/2 + 1), evaluated here
+    from the printed expression with s2 = 6.5 (sec. 3.2), and the properties
+    any correct evaluation has: end faces 0 and L, symmetry
+    xi_i + xi_{N-i} = L, the middle face at L/2, monotone faces, and a wall
+    cell of width A sinh(s2 / N) with A = (L/2) / sinh(s2/2)."""
+    L, s2 = 64.0, 6.5
+    for n in (8, 12, 64, 500):
+        xi = oracle.grid_sinh(n, L, s2)
+        A = (L / 2) / math.sinh(s2 / 2)
+        printed = np.array([A * math.sinh(s2 * i / n) if i <= n // 2 else L - A * math.sinh(s2 * (n - i) / n)
+                            for i in range(n + 1)])
+        np.testing.assert_allclose(xi, printed, rtol=0, atol=1e-12 * L)
+        assert xi[0] == 0.0 and abs(xi[-1] - L) < 1e-12 * L
+        np.testing.assert_allclose(xi + xi[::-1], L, atol=1e-12 * L)
+        assert abs(xi[n // 2] - L / 2) < 1e-12 * L
+        d = np.diff(xi)
+        assert np.all(d > 0)
+        assert abs(d[0] - A * math.sinh(s2 / n)) < 1e-12 * L
+        # the cells grow away from each wall up to the middle
+        assert np.all(np.diff(d[: n // 2]) > 0) and np.all(np.diff(d[n // 2:]) < 0)
+    # the library's generator gives the same faces
+    import paper_1505_03271_amd as lb
+    np.testing.assert_allclose(lb.grid_sinh(64, L, s2), oracle.grid_sinh(64, L, s2), rtol=0, atol=1e-12 * L)
+
+
+def test_thermal_energy_sum_of_a_linear_profile():
+    """sum V T over cells is the midpoint rule, exact for a temperature linear
+    in y on any grid: Lx * integral of T dy = Lx * H * (T_b + T_t) / 2 for the
+    conductive profile; the kinetic energy of a uniform flow at uniform
+    density is (1/2) rho |u|^2 Lx H.  Stretched in y, non-uniform in x."""
+    nx, ny = 7, 11
+    xf = np.cumsum(np.r_[0.0, 1.0 + 0.3 * np.sin(np.arange(nx))])
+    yf = workloads.faces_tanh(ny, 40.0, 2.0)
+    Lx, H = xf[-1], yf[-1]
+    Tb, Tt = 0.7, -0.2
+    y = workloads.centres(yf)
+    T = np.repeat((Tb + (Tt - Tb) * y / H)[:, None], nx, 1)
+    u0, v0, rho0 = 0.03, -0.02, 1.1
+    for scheme in ("heun", "euler"):
+        c = oracle.Case(nx, ny, scheme=scheme, wall_y=True, thermal=True, dt=0.5, tau=0.3, tau_g=0.4,
+                        T_bottom=Tb, T_top=Tt, xf=xf, yf=yf)
+        c.init(np.full((ny, nx), rho0), np.full((ny, nx), u0), np.full((ny, nx), v0), T)
+        d = c.diagnostics()
+        assert abs(d["etherm"] - Lx * H * 0.5 * (Tb + Tt)) < 1e-12 * Lx * H
+        assert abs(d["ekin"] / (0.5 * rho0 * (u0 * u0 + v0 * v0) * Lx * H) - 1) < 1e-12
+        assert abs(d["mass"] / (rho0 * Lx * H) - 1) < 1e-13
+        assert abs(d["volume"] / (Lx * H) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["heun", "semi", "st"])
+def test_thermal_energy_conserved_without_walls(scheme):
+    """Periodic axes and no source: the g fluxes telescope and the collision
+    keeps sum g, so sum V T is constant to rounding (sec. 5 model, no
+    thermal boundary)."""
+    nx, ny = 10, 9
+    yf = np.arange(ny + 1.0) if scheme == "st" else workloads.faces_tanh(ny, 25.0, 1.5)
+    c = oracle.Case(nx, ny, scheme=scheme, thermal=True, dt=1.0 if scheme == "st" else 0.6, tau=0.25,
+                    tau_g=0.35, beta_g=2e-3, yf=yf)
+    c.init(*_random_state(ny, nx, 21))
+    e0 = c.diagnostics()["etherm"]
+    c.step(60)
+    e1 = c.diagnostics()["etherm"]
+    assert abs(e1 - e0) < 1e-13 * max(1.0, abs(e0)) * nx * ny
+
+
+@pytest.mark.parametrize("scheme", ["heun", "st"])
+@pytest.mark.parametrize("Tw", [0.0, 0.3])
+def test_isothermal_walls_give_dirichlet_decay(scheme, Tw):
+    """The isothermal wall rule for g, pinned against the heat equation with
+    Dirichlet data: at rest, T = Tw + A sin(pi y / H) between two walls held
+    at Tw is the slowest mode and decays as exp(-kappa (pi/H)^2 t) with
+    kappa = tau_g cs^2, while its shape stays a sine.  A wall that let no
+    heat through (adiabatic) would keep the mean; a wrong sign or shift in the
+    ghost rule moves the wall value away from Tw and changes the rate."""
+    ny, tg = 40, 0.4
+    H = float(ny)
+    dt = 1.0 if scheme == "st" else 0.8
+    c = oracle.Case(2, ny, scheme=scheme, wall_y=True, thermal=True, dt=dt, tau=0.3, tau_g=tg,
+                    T_bottom=Tw, T_top=Tw)
+    y = np.arange(ny) + 0.5
+    mode = np.sin(math.pi * y / H)
+    c.init(np.ones((ny, 2)), np.zeros((ny, 2)), np.zeros((ny, 2)), (Tw + 0.01 * mode)[:, None] * np.ones((1, 2)))
+    per = 50
+    amps, shapes = [], []
+    for k in range(9):
+        dev = c.moments()["T"][:, 0] - Tw
+        amps.append(float(np.sum(dev * mode) / np.sum(mode * mode)))
+        shapes.append(np.abs(dev - amps[-1] * mode).max() / abs(amps[-1]))
+        c.step(int(round(per / dt)))
+    rate = _decay_rate(np.array(amps[1:]), per)
+    exact = (tg / 3.0) * (math.pi / H) ** 2
+    assert abs(rate / exact - 1) < 0.02, (rate, exact)
+    assert max(shapes[1:]) < 0.02
+    # the mean excess temperature is not conserved: heat leaves through the
+    # walls at the same rate (an adiabatic wall would keep it at 0.02 / pi)
+    t_end = 9 * per
+    mean = float(np.mean(c.moments()["T"] - Tw))
+    assert abs(mean / (0.02 / math.pi * math.exp(-exact * t_end)) - 1) < 0.05
