@@ -193,6 +193,21 @@ int lb_profiles(lb_sim* sim, double* out, int64_t n_out);
  * later lb_step calls return LB_EUNSTABLE). */
 int lb_diagnostics(lb_sim* sim, double* out);
 
+/* lb_diagnostics for callers that cannot allocate device memory or wait for
+ * the device (code under HIP graph capture, tight serving loops): the same
+ * eight values, written to out_device, a caller-owned DEVICE array of 8
+ * doubles, by kernels enqueued on the handle's stream; the call returns at
+ * once (no synchronisation, no device-to-host copy) and allocates nothing.
+ * The partial sums go to a file-scope device array of DIAG_BLOCKS x 8
+ * doubles (64 KiB) per GPU, held until the process ends; every grid fits it
+ * (larger grids fold more cells per partial sum), and a call that would need
+ * more is refused with LB_EINVAL.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (other streams, other threads) race, so
+ * order them on one stream.  The handle's device must be current
+ * (LB_EINVAL otherwise).  Unlike lb_diagnostics it leaves the handle's
+ * stability state alone: read the non-finite slot (out[7]) from the output. */
+int lb_diagnostics_noalloc(lb_sim* sim, double* out_device);
+
 /* Decoded populations in double, [9][ny][nx] for f and g (g may be NULL; it
  * is ignored unless thermal). */
 int lb_get_populations(lb_sim* sim, double* f, double* g);

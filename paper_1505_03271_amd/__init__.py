@@ -98,6 +98,7 @@ def lib():
             "lb_moments": ([h, _DP, _DP, _DP, _DP], ctypes.c_int),
             "lb_nusselt": ([h, _DP, _DP, _DP], ctypes.c_int),
             "lb_diagnostics": ([h, _DP], ctypes.c_int),
+            "lb_diagnostics_noalloc": ([h, ctypes.c_void_p], ctypes.c_int),
             "lb_get_populations": ([h, _DP, _DP], ctypes.c_int),
             "lb_set_populations": ([h, _DP, _DP], ctypes.c_int),
             "lb_state_bytes": ([h], ctypes.c_size_t),
@@ -263,6 +264,12 @@ class Sim:
         b, t, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(lib().lb_nusselt(self.h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(v)))
         return b.value, t.value, v.value
+
+    def diagnostics_noalloc(self, out_device_ptr):
+        """lb_diagnostics_noalloc: enqueue the eight values into a device
+        array of 8 doubles at out_device_ptr (an integer address); returns at
+        once."""
+        _check(lib().lb_diagnostics_noalloc(self.h, ctypes.c_void_p(int(out_device_ptr))))
 
     def diagnostics(self):
         out = np.empty(8)

@@ -437,7 +437,7 @@ hipError_t launch_profiles(int storage, const AuxArgs& a, double inv_Lx, double*
     return hipErrorInvalidValue;
 }
 
-__global__ void __launch_bounds__(256) diag_fold(const double* partial, int nblocks, double* out) {
+__global__ void __launch_bounds__(256) diag_fold(const double* partial, int nblocks, double* out, DiagFinal fin) {
     __shared__ double sh[4];
     for (int q = 0; q < D_COUNT; ++q) {
         double acc = 0.0;
@@ -454,6 +454,14 @@ __global__ void __launch_bounds__(256) diag_fold(const double* partial, int nblo
             r = block_sum(acc, sh);
         }
         if (threadIdx.x == 0) out[q] = r;
+    }
+    // the values lb_diagnostics reports: wall Nusselt numbers only with
+    // isothermal walls, and the volume Nusselt number in place of sum V u_y T
+    if (fin.finish && threadIdx.x == 0) {
+        const double ut = out[D_UT], vol = out[D_VOL];
+        out[D_NUB] = fin.walls ? out[D_NUB] : 0.0;
+        out[D_NUT] = fin.walls ? out[D_NUT] : 0.0;
+        out[D_UT] = fin.walls ? 1.0 + fin.H * (ut / vol) / (fin.kappa * fin.dT) : 0.0;
     }
 }
 
@@ -499,9 +507,14 @@ hipError_t launch_set_pops(int storage, const AuxArgs& a, const double* in, hipS
     return aux_dispatch(storage, 3, a, in, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
 }
 
-hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, double* out, hipStream_t s) {
-    const int64_t want = (d.a.plane + 255) / 256;
-    const int nb = int(want < DIAG_BLOCKS ? want : DIAG_BLOCKS);
+int diag_blocks(int64_t cells) {
+    const int64_t want = (cells + 255) / 256;
+    return int(want < DIAG_BLOCKS ? want : DIAG_BLOCKS);
+}
+
+hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, double* out, hipStream_t s,
+                              const DiagFinal& fin) {
+    const int nb = diag_blocks(d.a.plane);
     switch (storage) {
         case ST_F64: hipLaunchKernelGGL(diag_kernel<double>, dim3(nb), dim3(256), 0, s, d, partial); break;
         case ST_F32: hipLaunchKernelGGL(diag_kernel<float>, dim3(nb), dim3(256), 0, s, d, partial); break;
@@ -513,7 +526,7 @@ hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, d
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(diag_fold, dim3(1), dim3(256), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(diag_fold, dim3(1), dim3(256), 0, s, partial, nb, out, fin);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -139,6 +140,7 @@ void d_weights(double x0, double x1, double x2, double* w) {
 
 struct lb_sim {
     lb_params p{};
+    int device = 0;   // the device current at lb_create
     int nsp = 1;
     int64_t plane = 0;
     size_t state_bytes = 0;
@@ -436,7 +438,7 @@ int st_launch(lb_sim* s) {
     return LB_OK;
 }
 
-int run_diagnostics(lb_sim* s, double* host8) {
+DiagArgs diag_args(const lb_sim* s) {
     DiagArgs d{};
     d.a = aux_args(s);
     const int ny = s->p.ny;
@@ -454,7 +456,15 @@ int run_diagnostics(lb_sim* s, double* host8) {
     d.Tb = s->p.T_bottom;
     d.Tt = s->p.T_top;
     d.inv_Lx = 1.0 / (s->xf[s->p.nx] - s->xf[0]);
-    hipError_t e = launch_diagnostics(s->p.storage, d, s->partial, s->dout, s->stream);
+    return d;
+}
+
+int run_diagnostics(lb_sim* s, double* host8) {
+    const DiagArgs d = diag_args(s);
+    const int ny = s->p.ny;
+    const double H = s->yf[ny] - s->yf[0];
+    const double dT = s->p.T_bottom - s->p.T_top;
+    hipError_t e = launch_diagnostics(s->p.storage, d, s->partial, s->dout, s->stream, DiagFinal{});
     if (e != hipSuccess) return fail(LB_EDEVICE, "diagnostics launch failed: %s", hipGetErrorString(e));
     double o[D_COUNT];
     HIP_TRY(hipMemcpyAsync(o, s->dout, sizeof o, hipMemcpyDeviceToHost, s->stream));
@@ -561,6 +571,38 @@ int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
     }
     s->graphs.push_back(g);
     *out = &s->graphs.back();
+    return LB_OK;
+}
+
+}  // namespace
+
+// ---- diagnostics without allocation (lb_diagnostics_noalloc) ------------
+// Its partial sums live in this file-scope device array: one copy per GPU,
+// held until the process ends, shared by every call on that GPU.  Host code
+// never uses the array's name as an address: it takes the address that
+// hipGetSymbolAddress returns with the device current (looked up once per
+// device, on the first call there).
+constexpr int NOALLOC_PARTIALS = DIAG_BLOCKS * D_COUNT;
+constexpr int NOALLOC_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch[NOALLOC_DEVICES] = {};
+
+// Address of this device's scratch array (dev must be the current device).
+int scratch_address(int dev, double** out) {
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return fail(LB_EINVAL, "device %d: at most %d devices", dev, NOALLOC_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LB_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
     return LB_OK;
 }
 
@@ -700,7 +742,11 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->state_bytes = size_t(state_size(p->storage, p->thermal != 0, uint64_t(s->plane)));
         s->stream = static_cast<hipStream_t>(p->stream);
         s->chunk_h = 0;  // chosen at the first FV launch from the occupancy
-        hipError_t e;
+        hipError_t e = hipGetDevice(&s->device);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(LB_EDEVICE, "lb_create: no device: %s", hipGetErrorString(e));
+        }
         if ((e = hipMalloc(&s->A, s->state_bytes)) != hipSuccess || (e = hipMalloc(&s->B, s->state_bytes)) != hipSuccess ||
             (e = hipMalloc(&s->partial, sizeof(double) * DIAG_BLOCKS * D_COUNT)) != hipSuccess ||
             (e = hipMalloc(&s->dout, sizeof(double) * D_COUNT)) != hipSuccess ||
@@ -883,6 +929,32 @@ int lb_diagnostics(lb_sim* s, double* out) {
     if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics: no state");
     if (int rc = run_diagnostics(s, out)) return rc;
     return poll_flag(s);
+}
+
+int lb_diagnostics_noalloc(lb_sim* s, double* out_device) {
+    if (int rc = check_sim(s)) return rc;
+    if (!out_device) return fail(LB_EINVAL, "lb_diagnostics_noalloc: NULL output");
+    if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics_noalloc: no state");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != s->device)
+        return fail(LB_EINVAL, "lb_diagnostics_noalloc: device %d is current, the handle is on device %d", dev, s->device);
+    const int64_t need = int64_t(diag_blocks(s->plane)) * D_COUNT;
+    if (need > NOALLOC_PARTIALS)
+        return fail(LB_EINVAL, "lb_diagnostics_noalloc: %lld partial sums needed, the scratch holds %d",
+                    (long long)need, NOALLOC_PARTIALS);
+    double* partial = nullptr;
+    if (int rc = scratch_address(dev, &partial)) return rc;
+    const DiagArgs d = diag_args(s);
+    DiagFinal fin{};
+    fin.finish = 1;
+    fin.walls = d.walls;
+    fin.H = s->yf[s->p.ny] - s->yf[0];
+    fin.kappa = s->p.tau_g / 3.0;
+    fin.dT = s->p.T_bottom - s->p.T_top;
+    hipError_t e = launch_diagnostics(s->p.storage, d, partial, out_device, s->stream, fin);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_diagnostics_noalloc: launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
 }
 
 int lb_profiles(lb_sim* s, double* out, int64_t n_out) {

@@ -131,8 +131,17 @@ constexpr int DIAG_BLOCKS = 1024;
 // out[q * ny + j], q = 0 <T>, 1 <T^2>, 2 <ux^2>, 3 <uy^2>, 4 <uy T>, weighted by dx / Lx.
 constexpr int PROFILE_ROWS = 5;
 hipError_t launch_profiles(int storage, const AuxArgs& a, double inv_Lx, double* out, hipStream_t s);
+// Post-processing of the folded sums into lb_diagnostics' values, on the
+// device (finish = 1): the wall Nusselt slots are zeroed without isothermal
+// walls, and slot D_UT becomes Nu_vol = 1 + H (sum V u_y T / sum V) / (kappa dT).
+struct DiagFinal {
+    int finish, walls;
+    double H, kappa, dT;
+};
+// Partial sums used for a grid of `cells` cells: diag_blocks(cells) * D_COUNT doubles.
+int diag_blocks(int64_t cells);
 hipError_t launch_diagnostics(int storage, const DiagArgs& d, double* partial, double* out,
-                              hipStream_t s);
+                              hipStream_t s, const DiagFinal& fin);
 
 // ---- three dimensions (D3Q19, fv3d.hip) ----------------------------------
 template <class R>
