@@ -38,13 +38,25 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "FV-LB MLUPS & % HBM roofline (FP32 vs BF16 storage); serving p50/p99 latency"
 KERNEL_SOURCES = ["paper_1505_03271_amd/csrc/fv.hip", "paper_1505_03271_amd/csrc/lb_device.h",
-                  "paper_1505_03271_amd/csrc/lb_kernels.h"]
+                  "paper_1505_03271_amd/csrc/lb_kernels.h"]   # the FV kernels' sources (profile summaries' hash)
 GOLDEN_RB64 = os.path.join(ROOT, "tests", "golden", "rb64_ra1e4_steady.json")
 ACC_STORAGES = ("f64", "f32", "bf16s", "f16s", "bf16")
 
 
 def counters_path(storage):
     return os.path.join(ROOT, "profiles", f"fv_rb4096_{storage}_counters.json")
+
+
+def sq_path(storage):
+    return os.path.join(ROOT, "profiles", f"fv_rb4096_{storage}_sq.json")
+
+
+def algorithmic_bytes_per_cell_step(storage, thermal=True):
+    """The method's minimum traffic: read and write the state once per step,
+    2 Q b bytes per cell (Q = 18 with thermal populations, b = bytes per
+    stored population: 8 / 4 / 2)."""
+    b = {"f64": 8, "f32": 4}.get(storage, 2)
+    return 2 * (18 if thermal else 9) * b
 
 
 def kernel_hash():
@@ -59,13 +71,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_fv(lb, torch, cfg, storage, steps, warmup, diag_every=1000, scheme="heun"):
+def run_fv(lb, torch, cfg, storage, steps, warmup, diag_every=1000, scheme="heun", fused=None):
+    """fused: None keeps the library's default launch shape for the storage."""
     n = cfg["nx"]
     kw = dict(thermal=True, wall_y=True, dt=cfg["dt"], tau=cfg["tau"], tau_g=cfg["tau_g"], beta_g=cfg["beta_g"],
               T0=cfg["T0"], T_bottom=cfg["T_bottom"], T_top=cfg["T_top"])
     sim = lb.Sim(n, n, scheme=scheme, storage=storage, stream=lb.current_stream(), **kw)
     sim.set_grid(cfg["xf"], cfg["yf"])
     sim.init(cfg["rho"], cfg["ux"], cfg["uy"], cfg["T"])
+    if fused is not None:
+        sim.set_fv_fused(fused)
+    is_fused = sim.fv_fused() if fused is None else bool(fused)
     sim.step(warmup)
     torch.cuda.synchronize()
     sim.set_timing(True)
@@ -90,7 +106,7 @@ def run_fv(lb, torch, cfg, storage, steps, warmup, diag_every=1000, scheme="heun
     d = sim.diagnostics()
     sim.close()
     return dict(seconds=max(wall, ev), event_seconds=ev, wall_seconds=wall, kernels=kt, diag=d, nusselt=nus,
-                cells=n * n, steps=steps)
+                cells=n * n, steps=steps, fused=is_fused)
 
 
 def run_st(lb, torch, n, storage, steps, warmup):
@@ -117,11 +133,12 @@ def run_st(lb, torch, n, storage, steps, warmup):
     return dict(seconds=wall, kernels=kt, cells=n * n, steps=steps)
 
 
-def run_config(lb, torch, which, storage, steps, warmup=20):
+def run_config(lb, torch, which, storage, steps, warmup=20, direct=False):
     """A single simulation of one of the smaller synthetic configurations:
     tgv64 (Taylor-Green vortex, periodic, isothermal), channel (256 x 512
     forced channel, tanh walls, isothermal) or rb1024 (Rayleigh-Benard
-    Ra = 1e8, tanh(2.0)); FV semi-implicit + Heun."""
+    Ra = 1e8, tanh(2.0)); FV semi-implicit + Heun.  direct: every kernel
+    launched from the host (kernel timing on) instead of captured graphs."""
     import workloads
     if which == "tgv64":
         cfg = workloads.tgv_config()
@@ -139,6 +156,8 @@ def run_config(lb, torch, which, storage, steps, warmup=20):
     sim = lb.Sim(cfg["nx"], cfg["ny"], scheme="heun", storage=storage, stream=lb.current_stream(), **kw)
     sim.set_grid(cfg["xf"], cfg["yf"])
     sim.init(*fields)
+    if direct:
+        sim.set_timing(True)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -281,18 +300,31 @@ def accuracy_report(lb, torch, storages=ACC_STORAGES, chunk=10000):
     return out
 
 
-def traffic_from_counters(launch_cells, kernel, storage):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size),
-    if it was taken on the current kernel source."""
-    path = counters_path(storage)
+def _profile_json(path, launch_cells):
+    """A committed rocprofv3 summary, if it was taken on the current kernel
+    source and workload size."""
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         c = json.load(fh)
     if c.get("kernel_hash") != kernel_hash() or c.get("cells") != launch_cells:
         return None
-    return c.get("hbm_bytes_per_launch", {}).get(kernel)
+    return c
+
+
+def traffic_from_counters(launch_cells, storage):
+    """HBM bytes per launch of each kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
+    size)."""
+    c = _profile_json(counters_path(storage), launch_cells)
+    return c.get("hbm_bytes_per_launch", {}) if c else {}
+
+
+def valu_from_counters(launch_cells, storage):
+    """VALU busy fraction and VALU instructions per cell of each kernel from
+    the committed rocprofv3 SQ counter summary."""
+    c = _profile_json(sq_path(storage), launch_cells)
+    return c.get("kernels", {}) if c else {}
 
 
 def main():
@@ -304,7 +336,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--storage", default="bf16s")
-    ap.add_argument("--serve-requests", type=int, default=100,
+    ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving trace to replay (0: skip serving)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 512 MiB device to device (a kernel of known traffic for counter scaling)")
@@ -345,36 +377,49 @@ def main():
     mlups = cells * K / head["seconds"] / 1e6
     log(f"FV {args.storage}: {mlups:.0f} MLUPS ({head['seconds']:.3f} s for {K} steps)")
 
-    # roofline of the dominant kernel (per launch: one pass over all cells)
-    b = lb.cell_bytes(args.storage, thermal=True)   # one state, one cell
-    (np_, tp), (nc, tc) = head["kernels"]["fv_first_pass"], head["kernels"]["fv_corrector"]
-    avg_p, avg_c = tp / np_ / 1e3, tc / nc / 1e3
-    # compulsory traffic per cell of each launch: the predictor reads f~n and
-    # writes f~* (2 states); the corrector reads f~* and f~n and writes f~n+1 (3)
-    if tc >= tp:
-        name, avg, per_cell = "fv_pass<corrector>", avg_c, 3 * b
-    else:
-        name, avg, per_cell = "fv_pass<predictor>", avg_p, 2 * b
-    achieved = per_cell * cells / avg / 1e9
+    # Roofline of the dominant kernel against the method's algorithmic
+    # traffic, 2 Q b bytes per cell-step (72 B at 16-bit storage): the whole
+    # step's minimum charged to the launch that takes the most time, and to
+    # the whole step.  The two-pass traffic this design must move (predictor
+    # 2 states, corrector 3) is reported apart.
+    b = lb.cell_bytes(args.storage, thermal=True)   # one stored state, one cell
+    alg = algorithmic_bytes_per_cell_step(args.storage)
+    names = {"fv_first_pass": "fv_pass<predictor>", "fv_corrector": "fv_pass<corrector>", "fv_fused": "fv_fused"}
+    kt = {k: v for k, v in head["kernels"].items() if v[0] > 0 and k in names}
+    dom = max(kt, key=lambda k: kt[k][1])
+    avg = kt[dom][1] / kt[dom][0] / 1e3
+    step_s = head["seconds"] / K
+    achieved = alg * cells / avg / 1e9
+    tr = traffic_from_counters(cells, args.storage)
+    va = valu_from_counters(cells, args.storage)
+    per_step_launches = {k: v[0] / K for k, v in kt.items()}
+    counter_bytes_step = (sum(tr[names[k]] * n for k, n in per_step_launches.items())
+                          if tr and all(names[k] in tr for k in kt) else None)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic_from_counters(cells, name, args.storage),
-            "kernel": name, "avg_launch_ms": round(avg * 1e3, 4), "algorithmic_bytes_per_cell": per_cell}
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": tr.get(names[dom]) if tr else None,
+            "kernel": names[dom], "avg_launch_ms": round(avg * 1e3, 4),
+            "algorithmic_bytes_per_cell_step": alg,
+            "step_frac": round(alg * cells / step_s / 1e9 / HBM_PEAK_GBPS, 4),
+            "counter_bytes_per_step": counter_bytes_step,
+            "counter_over_algorithmic": round(counter_bytes_step / (alg * cells), 3) if counter_bytes_step else None,
+            "valu_busy": {names[k]: va[names[k]]["valu_busy"] for k in kt if names[k] in va} or None,
+            "valu_insts_per_cell_step": (round(sum(va[names[k]]["valu_insts_per_cell"] * n
+                                                   for k, n in per_step_launches.items()), 1)
+                                         if va and all(names[k] in va for k in kt) else None),
+            "two_pass_design_bytes_per_cell_step": 5 * b}
     if not args.no_variants:
-        # what plain streaming sweeps reach on this device for the kernel's
-        # traffic mix (reads : writes 2 : 1 for the corrector, 1 : 1 for the
-        # predictor), measured after the timed region
+        # what plain streaming sweeps reach on this device (reads : writes
+        # 2 : 1 and 1 : 1), measured after the timed region
         ceil = lb.stream_probe(512 << 20)
-        mix = ceil["stream_2r1w"] if name.endswith("corrector>") else ceil["copy_1r1w"]
         roof["stream_ceiling_GBps"] = {k: round(v, 1) for k, v in ceil.items()}
-        roof["frac_of_stream_ceiling"] = round(achieved / mix, 4) if mix > 0 else None
         log(f"streaming ceiling: {ceil}")
 
-    extra = {"storage": args.storage, "state_bytes_per_cell": b, "predictor_avg_ms": round(avg_p * 1e3, 4),
-             "corrector_avg_ms": round(avg_c * 1e3, 4),
-             "predictor_GBps_2states": round(2 * b * cells / avg_p / 1e9, 1),
-             "corrector_GBps_3states": round(3 * b * cells / avg_c / 1e9, 1),
-             "step_effective_GBps_2states": round(2 * b * cells * K / head["seconds"] / 1e9, 1),
-             "step_compulsory_GBps_5states": round(5 * b * cells * K / head["seconds"] / 1e9, 1),
+    extra = {"storage": args.storage, "state_bytes_per_cell": b,
+             "kernel_avg_ms": {names[k]: round(v[1] / v[0], 4) for k, v in kt.items()},
+             "launches_per_step": {names[k]: round(n, 3) for k, n in per_step_launches.items()},
+             "step_GBps_algorithmic": round(alg * cells / step_s / 1e9, 1),
+             "step_GBps_two_pass_design": round(5 * b * cells / step_s / 1e9, 1),
              "nusselt_bottom_top_vol_last": head["nusselt"][-1] if head["nusselt"] else None,
              "nonfinite": head["diag"]["nonfinite"]}
     if not args.no_variants:
@@ -383,10 +428,21 @@ def main():
             if st == args.storage:
                 continue
             r = run_fv(lb, torch, cfg, st, vsteps, 20)
-            extra[f"fv_{st}_mlups"] = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
-            log(f"FV {st}: {extra[f'fv_{st}_mlups']} MLUPS")
+            v = round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
+            if st == "bf16":
+                # plain 16-bit offsets: faster, but they stagnate under the FV
+                # time step and fail the accuracy bar (see the accuracy section)
+                extra["fv_bf16_plain"] = {"mlups": v, "accuracy_bar": "fails: the stored offsets stagnate "
+                                          "(Nu off by 12% after 500 steps at Ra=1e8, 56% at the Ra=1e4 steady roll)"}
+            else:
+                extra[f"fv_{st}_mlups"] = v
+            log(f"FV {st}: {v} MLUPS")
         if "fv_f32_mlups" in extra:
             extra["fv_speedup_vs_f32"] = round(mlups / extra["fv_f32_mlups"], 3)
+        # the other launch shape of the same step (fused passes on/off)
+        r = run_fv(lb, torch, cfg, args.storage, vsteps, 20, fused=not head["fused"])
+        extra[f"fv_{args.storage}_{'fused' if not head['fused'] else 'two_pass'}_mlups"] = round(
+            r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)
         r3 = run_fv3d(lb, torch, 256, max(args.steps // 20, 20), 5)
         extra["fv3d_rb256_f32_mlups"] = round(r3["cells"] * r3["steps"] / r3["seconds"] / 1e6, 1)
         (n1, t1), (n2, t2) = r3["kernels"]["fv_first_pass"], r3["kernels"]["fv_corrector"]
@@ -398,10 +454,15 @@ def main():
             log(f"ST {st}: {extra[f'st_{st}_mlups']} MLUPS")
         # the smaller configurations, one simulation each (they fit in the
         # device's last-level cache, or are bound by launch latency)
+        # (lb_step replays captured graphs of 32 steps; the "direct" figures
+        # launch every kernel from the host, as before graphs were captured)
         for which, st, k in (("tgv64", "f64", 1000), ("channel", "f32", 2000), ("rb1024", "f32", 2000),
                              ("rb1024", "bf16s", 2000)):
             extra[f"fv_{which}_{st}_mlups"] = round(run_config(lb, torch, which, st, k), 1)
             log(f"FV {which} {st}: {extra[f'fv_{which}_{st}_mlups']} MLUPS")
+        for which, st, k in (("tgv64", "f64", 1000), ("channel", "f32", 2000)):
+            extra[f"fv_{which}_{st}_direct_mlups"] = round(run_config(lb, torch, which, st, k, direct=True), 1)
+            log(f"FV {which} {st} direct launches: {extra[f'fv_{which}_{st}_direct_mlups']} MLUPS")
 
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": round(head["seconds"] / K * 1e3, 4), "higher_is_better": True,
@@ -413,6 +474,9 @@ def main():
     if args.serve_requests > 0:
         from paper_1505_03271_amd.serve import Server
         trace = workloads.serving_trace()[:args.serve_requests]
+        # offered load: the trace's cell updates over its arrival window
+        span = max(r["arrival"] for r in trace) - min(r["arrival"] for r in trace)
+        offered = sum(r["n"] ** 2 * r["steps"] for r in trace) / max(span, 1e-9) / 1e6
         runs = {}
         for policy in ("srpt", "all"):
             log(f"serving {len(trace)} requests, policy {policy} ...")
@@ -421,12 +485,15 @@ def main():
             server.close()
             runs[policy] = {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                             "aggregate_mlups": round(st["aggregate_mlups"], 1), "makespan_s": round(st["makespan_s"], 2),
+                            "served": st["n_requests"], "failed": len(st["failed"]), "rejected": len(st["rejected"]),
                             "graph_launches": st["graph_launches"], "preemptions": st["preemptions"],
                             "phases_s": st["phases_s"]}
             log(f"serving ({policy}): p50 {st['p50_s']:.2f} s p99 {st['p99_s']:.2f} s, "
-                f"{st['aggregate_mlups']:.0f} MLUPS")
+                f"{st['aggregate_mlups']:.0f} MLUPS, {len(st['failed'])} failed")
         out["serving"] = dict(requests=len(trace), policy="srpt", min_cells=8e6, age_s=5.0, **runs["srpt"],
                               graph_steps=100, hbm_budget_bytes=16e9, storage=args.storage,
+                              offered_mlups=round(offered, 1),
+                              served_over_offered=round(runs["srpt"]["aggregate_mlups"] / offered, 3),
                               trace="Poisson 20/s, side log-U[128,1024], Ra log-U[1e6,1e9], Pr in {0.7,1,7}, "
                                     "steps U{2000..20000}, seed 150503275",
                               all_members=runs["all"])

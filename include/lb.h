@@ -224,10 +224,11 @@ int lb_get_state(lb_sim* sim, void* host, size_t bytes);
 int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
 
 /* Kernel timing: when enabled, every launch made by lb_step is bracketed by
- * HIP events on the handle's stream.  lb_kernel_times synchronises and
- * returns, per kernel kind (0: FV predictor or single FV pass, 1: FV
- * corrector, 2: ST), the number of launches and their total milliseconds
- * since the last reset (arrays of length 3). */
+ * HIP events on the handle's stream (and lb_step launches every kernel
+ * itself instead of replaying captured graphs).  lb_kernel_times
+ * synchronises and returns, per kernel kind (0: FV predictor or single FV
+ * pass, 1: FV corrector, 2: ST, 3: FV fused pass), the number of launches
+ * and their total milliseconds since the last reset (arrays of length 4). */
 int lb_set_timing(lb_sim* sim, int enable);
 int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
 
@@ -266,6 +267,23 @@ int lb_set_st_pairs(lb_sim* sim, int on);
  * launch is resident at once.  Any height >= 1 gives identical results.
  * LB_EINVAL if rows < 1. */
 int lb_set_fv_chunk(lb_sim* sim, int rows);
+
+/* Fused passes (a launch-shape knob): for the semi-implicit
+ * + Heun scheme with periodic x, a run of m >= 2 steps within one lb_step
+ * call is a predictor launch, m - 1 fused launches and a corrector launch;
+ * a fused launch forms f~n+1 of a step (eq:semi-heun) and f~* of the next
+ * (eq:semi) in one sweep, reading f~* and f~n once and writing both, so a
+ * step moves four states instead of five.  It needs a second pair of state
+ * buffers, allocated at the first such run (if that allocation fails, or
+ * while the caller captures the stream before it was made, the steps use
+ * separate launches).  The results are bit-identical either way.  On by
+ * default for FP32 storage and for isothermal runs, where it is the faster
+ * shape; off for thermal 16-bit and FP64 storage, whose fused kernel holds
+ * both species' rings for two stages and runs one wave per SIMD.  on = 0
+ * frees the second pair.  LB_EINVAL for other values. */
+int lb_set_fv_fused(lb_sim* sim, int on);
+/* The current setting (1 on, 0 off) in *on. */
+int lb_get_fv_fused(const lb_sim* sim, int* on);
 
 /* Number of bytes of device memory held by the handle. */
 size_t lb_device_bytes(const lb_sim* sim);

@@ -108,6 +108,8 @@ def lib():
             "lb_kernel_times": ([h, ctypes.POINTER(ctypes.c_int64), _DP], ctypes.c_int),
             "lb_set_fv_chunk": ([h, ctypes.c_int], ctypes.c_int),
             "lb_set_fv_lanes": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_set_fv_fused": ([h, ctypes.c_int], ctypes.c_int),
+            "lb_get_fv_fused": ([h, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "lb_set_st_pairs": ([h, ctypes.c_int], ctypes.c_int),
             "lb_rebase": ([h], ctypes.c_int),
             "lb_set_rebase": ([h, ctypes.c_int64], ctypes.c_int),
@@ -305,11 +307,19 @@ class Sim:
         _check(lib().lb_set_timing(self.h, int(bool(on))))
 
     def kernel_times(self):
-        n = (ctypes.c_int64 * 3)()
-        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * 4)()
         _check(lib().lb_kernel_times(self.h, n, ms))
-        names = ["fv_first_pass", "fv_corrector", "st"]
-        return {names[k]: (int(n[k]), float(ms[k])) for k in range(3)}
+        names = ["fv_first_pass", "fv_corrector", "st", "fv_fused"]
+        return {names[k]: (int(n[k]), float(ms[k])) for k in range(4)}
+
+    def set_fv_fused(self, on):
+        _check(lib().lb_set_fv_fused(self.h, int(bool(on))))
+
+    def fv_fused(self):
+        on = ctypes.c_int()
+        _check(lib().lb_get_fv_fused(self.h, ctypes.byref(on)))
+        return bool(on.value)
 
     def rebase(self):
         _check(lib().lb_rebase(self.h))

@@ -138,6 +138,10 @@ void d_weights(double x0, double x1, double x2, double* w) {
 
 }  // namespace
 
+// kinds of timed launches: 0 FV predictor or single pass, 1 FV corrector,
+// 2 ST, 3 FV fused pass (corrector of a step and predictor of the next)
+constexpr int TIMED_KINDS = 4;
+
 struct lb_sim {
     lb_params p{};
     int device = 0;   // the device current at lb_create
@@ -147,6 +151,10 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     void* A = nullptr;  // current state
     void* B = nullptr;  // predictor / next state
+    void* A2 = nullptr; // fused passes: the second pair of states (allocated at the first use)
+    void* B2 = nullptr;
+    int fused = 1;      // lb_set_fv_fused: corrector and next predictor in one pass where possible
+    int chunk_f = 0;    // rows per work item of the fused pass (0: chosen at its first launch)
     void* metric = nullptr;   // flux stencils: x pass0, y pass0, x pass1, y pass1 ([n][8] each)
     double* dxy = nullptr;    // dx[nx], dy[ny] in double
     double* partial = nullptr;
@@ -169,10 +177,9 @@ struct lb_sim {
     // captured step graphs of STEP_GRAPH_STEPS steps, by the state they start
     // from (buffer A and steps since the last rebase) and the state they leave
     struct StepGraph {
-        void* A0;
+        void* p0[4];        // A, B, A2, B2 at the start
         int64_t since0;
-        void* A1;
-        void* B1;
+        void* p1[4];        // and at the end
         int64_t since1;
         hipGraphExec_t exec;
     };
@@ -183,8 +190,8 @@ struct lb_sim {
     std::vector<hipEvent_t> events;
     std::vector<int> kinds;  // kind of the launch that starts at event k
     size_t n_rec = 0;
-    int64_t launches[3] = {0, 0, 0};
-    double ms[3] = {0, 0, 0};
+    int64_t launches[TIMED_KINDS] = {};
+    double ms[TIMED_KINDS] = {};
 };
 
 namespace {
@@ -234,6 +241,9 @@ void drop_step_graphs(lb_sim* s) {
 // Release every device allocation of a handle (safe on partial creation).
 void release(lb_sim* s) {
     drop_step_graphs(s);
+    if (s->A2) (void)hipFree(s->A2);
+    if (s->B2) (void)hipFree(s->B2);
+    s->A2 = s->B2 = nullptr;
     if (s->cap) (void)hipStreamDestroy(s->cap);
     s->cap = nullptr;
     if (s->d_bad) (void)hipFree(s->d_bad);
@@ -369,7 +379,7 @@ int fold_timing(lb_sim* s) {
     HIP_TRY(hipEventSynchronize(s->events[s->n_rec - 1]));
     for (size_t k = 0; k + 1 < s->n_rec; ++k) {
         const int kind = s->kinds[k];
-        if (kind < 0 || kind > 2) continue;
+        if (kind < 0 || kind >= TIMED_KINDS) continue;
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, s->events[k], s->events[k + 1]));
         s->ms[kind] += t;
@@ -405,6 +415,77 @@ int fv_launch(lb_sim* s, const void* src, void* dst, void* aux, bool corrector) 
         e = launch_fv_pass(s->p.storage, s->p.thermal, corrector, &a, s->stream);
     }
     if (e != hipSuccess) return fail(LB_EDEVICE, "FV kernel launch failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+// ---- fused passes (x periodic, semi-implicit + Heun) ----
+bool fused_eligible(const lb_sim* s) {
+    return s->p.scheme == LB_FV_HEUN && s->p.bc_x == LB_PERIODIC && s->fused;
+}
+bool narrow_fused(const lb_sim* s) {
+    if (s->lanes) return s->lanes == FV_NARROW;
+    const int64_t nx = s->p.nx, hw = 2 * FV_FUSED_HALO;
+    const int64_t wide = FV_LANES * ((nx + FV_LANES - hw - 1) / (FV_LANES - hw));
+    const int64_t narrow = FV_NARROW * ((nx + FV_NARROW - hw - 1) / (FV_NARROW - hw));
+    return narrow * 104 < wide * 100;
+}
+int strip_width_fused(const lb_sim* s) { return (narrow_fused(s) ? FV_NARROW : FV_LANES) - 2 * FV_FUSED_HALO; }
+int auto_chunk_fused(const lb_sim* s) {
+    const int n_strips = (s->p.nx + strip_width_fused(s) - 1) / strip_width_fused(s);
+    int cap = fv_fused_resident_blocks(s->p.storage, s->p.thermal);
+    if (cap <= 0) cap = 256;
+    if (narrow_fused(s)) cap *= 4;
+    const int chunks = std::max(1, cap / n_strips);
+    int h = (s->p.ny + chunks - 1) / chunks;
+    h = ((h + 3) / 4) * 4;
+    return std::max(8, h);
+}
+// the second pair of states, on first use (not while the caller captures the stream)
+int ensure_fused_states(lb_sim* s, bool capturing, bool* ok) {
+    *ok = false;
+    if (!fused_eligible(s)) return LB_OK;
+    if (!s->A2 || !s->B2) {
+        if (capturing) return LB_OK;
+        void* a = nullptr;
+        void* b = nullptr;
+        hipError_t e = hipMalloc(&a, s->state_bytes);
+        if (e == hipSuccess) e = hipMalloc(&b, s->state_bytes);
+        if (e != hipSuccess) {
+            if (a) (void)hipFree(a);
+            (void)hipGetLastError();
+            return LB_OK;   // no room: separate launches, as before
+        }
+        s->A2 = a;
+        s->B2 = b;
+    }
+    *ok = true;
+    return LB_OK;
+}
+
+template <class R>
+FvArgs<R> fv_args_fused(const lb_sim* s, const void* star, const void* cur, void* next, void* star2) {
+    FvArgs<R> a = fv_args<R>(s, star, next, const_cast<void*>(cur), true);   // the corrector's weights (dt/2)
+    a.dst2 = star2;
+    a.narrow = narrow_fused(s) ? 1 : 0;
+    a.strip_w = strip_width_fused(s);
+    a.chunk_h = s->chunk_f;
+    a.n_strips = (s->p.nx + a.strip_w - 1) / a.strip_w;
+    a.n_items = a.n_strips * ((s->p.ny + a.chunk_h - 1) / a.chunk_h);
+    return a;
+}
+
+int fused_launch(lb_sim* s, const void* star, const void* cur, void* next, void* star2) {
+    if (s->chunk_f <= 0) s->chunk_f = auto_chunk_fused(s);
+    if (int rc = record_event(s, 3)) return rc;
+    hipError_t e;
+    if (s->p.storage == LB_F64) {
+        FvArgs<double> a = fv_args_fused<double>(s, star, cur, next, star2);
+        e = launch_fv_fused(s->p.storage, s->p.thermal, &a, s->stream);
+    } else {
+        FvArgs<float> a = fv_args_fused<float>(s, star, cur, next, star2);
+        e = launch_fv_fused(s->p.storage, s->p.thermal, &a, s->stream);
+    }
+    if (e != hipSuccess) return fail(LB_EDEVICE, "FV fused kernel launch failed: %s", hipGetErrorString(e));
     return LB_OK;
 }
 
@@ -504,9 +585,36 @@ bool flagged(lb_sim* s) {
     return s->unstable;
 }
 
-// Enqueue n time steps as single launches (the stepping of lb_step).
-int enqueue_steps(lb_sim* s, int64_t nsteps) {
-    for (int64_t n = 0; n < nsteps; ++n) {
+// Enqueue n time steps as single launches (the stepping of lb_step).  With
+// fused passes, a run of m >= 2 semi-implicit + Heun steps is a predictor,
+// m - 1 fused passes (each the corrector of a step and the predictor of the
+// next, writing the other pair of states) and a corrector; a rebase ends a
+// run (it re-encodes the state that the next predictor reads).
+int enqueue_steps(lb_sim* s, int64_t nsteps, bool capturing = false) {
+    bool fused = false;
+    if (s->p.scheme == LB_FV_HEUN && nsteps >= 2)
+        if (int rc = ensure_fused_states(s, capturing, &fused)) return rc;
+    int64_t n = 0;
+    while (fused && n < nsteps) {
+        int64_t m = nsteps - n;
+        const bool rebasing = s->tref && s->rebase_every > 0;
+        if (rebasing) m = std::min<int64_t>(m, s->rebase_every - s->since_rebase);
+        int rc;
+        if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;   // f~* -> B
+        for (int64_t q = 1; q < m; ++q) {
+            if ((rc = fused_launch(s, s->B, s->A, s->A2, s->B2))) return rc;  // f~n+1 -> A2, next f~* -> B2
+            std::swap(s->A, s->A2);
+            std::swap(s->B, s->B2);
+        }
+        if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;        // f~n+1 -> A
+        n += m;
+        if (rebasing && (s->since_rebase += m) >= s->rebase_every) {
+            hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
+            s->since_rebase = 0;
+        }
+    }
+    for (; n < nsteps; ++n) {
         int rc;
         switch (s->p.scheme) {
             case LB_FV_HEUN:
@@ -538,13 +646,22 @@ int enqueue_steps(lb_sim* s, int64_t nsteps) {
 constexpr int64_t STEP_GRAPH_STEPS = 32;
 constexpr size_t STEP_GRAPHS_KEPT = 8;
 int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
-    for (const auto& g : s->graphs)
-        if (g.A0 == s->A && g.since0 == s->since_rebase) { *out = &g; return LB_OK; }
+    void** bufs[4] = {&s->A, &s->B, &s->A2, &s->B2};
+    for (const auto& g : s->graphs) {
+        bool same = g.since0 == s->since_rebase;
+        for (int q = 0; q < 4; ++q) same = same && g.p0[q] == *bufs[q];
+        if (same) { *out = &g; return LB_OK; }
+    }
     if (s->p.scheme != LB_ST && s->chunk_h <= 0) s->chunk_h = auto_chunk(s);
+    if (fused_eligible(s)) {
+        bool ok = false;
+        if (int rc = ensure_fused_states(s, false, &ok)) return rc;   // allocated before the capture
+        if (ok && s->chunk_f <= 0) s->chunk_f = auto_chunk_fused(s);
+    }
     if (!s->cap) HIP_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));  // default priority
-    lb_sim::StepGraph g{s->A, s->since_rebase, nullptr, nullptr, 0, nullptr};
-    void* A0 = s->A;
-    void* B0 = s->B;
+    lb_sim::StepGraph g{};
+    for (int q = 0; q < 4; ++q) g.p0[q] = *bufs[q];
+    g.since0 = s->since_rebase;
     hipStream_t user = s->stream;
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed));
@@ -552,11 +669,11 @@ int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
     int rc = enqueue_steps(s, STEP_GRAPH_STEPS);
     s->stream = user;
     hipError_t e = hipStreamEndCapture(s->cap, &graph);
-    g.A1 = s->A;
-    g.B1 = s->B;
+    for (int q = 0; q < 4; ++q) {
+        g.p1[q] = *bufs[q];
+        *bufs[q] = g.p0[q];   // the graph has not run yet
+    }
     g.since1 = s->since_rebase;
-    s->A = A0;   // the graph has not run yet
-    s->B = B0;
     s->since_rebase = g.since0;
     if (rc != LB_OK || e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -738,6 +855,12 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->p = *p;
         if (s->p.scheme == LB_ST) s->p.dt = 1.0;
         s->nsp = p->thermal ? 2 : 1;
+        // fused passes by default where they are the faster launch shape:
+        // FP32 storage, and isothermal runs (two waves per SIMD); the
+        // thermal 16-bit and FP64 instances need one wave per SIMD and are
+        // slower than two launches
+        s->fused = (p->storage == LB_F32 || (!p->thermal && p->storage != LB_F64)) ? 1 : 0;
+
         s->plane = int64_t(p->nx) * p->ny;
         s->state_bytes = size_t(state_size(p->storage, p->thermal != 0, uint64_t(s->plane)));
         s->stream = static_cast<hipStream_t>(p->stream);
@@ -887,12 +1010,14 @@ int lb_step(lb_sim* s, int64_t nsteps) {
         const lb_sim::StepGraph* g = nullptr;
         if (int rc = step_graph(s, &g)) return rc;
         HIP_TRY(hipGraphLaunch(g->exec, s->stream));
-        s->A = g->A1;
-        s->B = g->B1;
+        s->A = g->p1[0];
+        s->B = g->p1[1];
+        s->A2 = g->p1[2];
+        s->B2 = g->p1[3];
         s->since_rebase = g->since1;
         left -= STEP_GRAPH_STEPS;
     }
-    if (int rc = enqueue_steps(s, left)) return rc;
+    if (int rc = enqueue_steps(s, left, cap != hipStreamCaptureStatusNone)) return rc;
     if (int rc = record_event(s, -1)) return rc;
     // the flag as of the end of these steps, read by the next call
     HIP_TRY(hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(int), hipMemcpyDeviceToHost, s->stream));
@@ -1122,7 +1247,7 @@ int lb_set_timing(lb_sim* s, int enable) {
         if (int rc = fold_timing(s)) return rc;
     }
     s->timing = enable != 0;
-    for (int k = 0; k < 3; ++k) { s->launches[k] = 0; s->ms[k] = 0; }
+    for (int k = 0; k < TIMED_KINDS; ++k) { s->launches[k] = 0; s->ms[k] = 0; }
     s->n_rec = 0;
     return LB_OK;
 }
@@ -1131,13 +1256,13 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
     if (int rc = check_sim(s)) return rc;
     if (!launches || !total_ms) return fail(LB_EINVAL, "lb_kernel_times: NULL output");
     if (int rc = fold_timing(s)) return rc;
-    for (int k = 0; k < 3; ++k) { launches[k] = s->launches[k]; total_ms[k] = s->ms[k]; }
+    for (int k = 0; k < TIMED_KINDS; ++k) { launches[k] = s->launches[k]; total_ms[k] = s->ms[k]; }
     return LB_OK;
 }
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return 2 * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return (s->A2 ? 4 : 2) * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
 }
 
@@ -1174,6 +1299,7 @@ int lb_set_fv_lanes(lb_sim* s, int lanes) {
         return fail(LB_EINVAL, "lb_set_fv_lanes: lanes must be 0, %d or %d", FV_NARROW, FV_LANES);
     s->lanes = lanes;
     s->chunk_h = 0;  // re-chosen at the next step for the new item width
+    s->chunk_f = 0;
     drop_step_graphs(s);
     return LB_OK;
 }
@@ -1182,6 +1308,27 @@ int lb_set_fv_chunk(lb_sim* s, int rows) {
     if (int rc = check_free(s, "lb_set_fv_chunk")) return rc;
     if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
     s->chunk_h = rows;
+    s->chunk_f = rows;
+    drop_step_graphs(s);
+    return LB_OK;
+}
+
+int lb_get_fv_fused(const lb_sim* s, int* on) {
+    if (!s || !on) return fail(LB_EINVAL, "lb_get_fv_fused: NULL argument");
+    *on = s->fused;
+    return LB_OK;
+}
+
+int lb_set_fv_fused(lb_sim* s, int on) {
+    if (int rc = check_free(s, "lb_set_fv_fused")) return rc;
+    if (on != 0 && on != 1) return fail(LB_EINVAL, "lb_set_fv_fused: on must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->fused = on;
+    if (!on) {   // release the second pair of states
+        if (s->A2) (void)hipFree(s->A2);
+        if (s->B2) (void)hipFree(s->B2);
+        s->A2 = s->B2 = nullptr;
+    }
     drop_step_graphs(s);
     return LB_OK;
 }

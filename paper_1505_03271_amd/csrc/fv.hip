@@ -49,6 +49,8 @@
 // is the mirror cell's with the opposite population (double reflection); for
 // g on the y walls it is 2 w_a T_w - phi_inv(a) (isothermal anti-reflection).
 // Periodic axes wrap.
+#include <type_traits>
+
 #include "lb_kernels.h"
 
 namespace lbk {
@@ -155,6 +157,11 @@ template <bool BF> struct Io16 {
         return float(__builtin_bit_cast(_Float16, uint16_t(h)));
     }
     __device__ static uint16_t enc(float x) {
+        // x as an FP32 value: without this the compiler may fuse the
+        // conversion with the multiply-add that produced x (v_fma_mixlo_f16,
+        // one rounding from the exact result), so a value stored and the
+        // same value rounded elsewhere could differ in the last bit
+        asm("" : "+v"(x));
         if (BF) return __builtin_bit_cast(uint16_t, (__bf16)x);    // v_cvt_pk_bf16_f32: round to nearest even
         return __builtin_bit_cast(uint16_t, (_Float16)x);          // round to nearest even
     }
@@ -489,11 +496,12 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
     }
 }
 
-// Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
-// Returns m0 + m3, which is finite exactly when the stored moments are.
+// Offsets d of a cell -> its split record: moments (FP32 words) and rounded
+// residuals (16-bit words), as stored.  Returns m0 + m3, which is finite
+// exactly when the moments are.
 template <class R, class S, bool TH>
-__device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
-                                const R Tr, const R q) {
+__device__ inline R encode_split(const R* df, const R* dg, const StageK<R>& k, const R Tr, const R q,
+                                 SplitRaw<TH>& w) {
     using IO = Narrow<S>;
     constexpr float rs = split_scale<S>::value;
     R m[4];
@@ -508,24 +516,48 @@ __device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, c
         if (s == 0) rf[a] = df[a] - e; else rg[a] = dg[a] - e;
     });
     auto e2 = [&](R lo, R hi) __attribute__((always_inline)) { return IO::enc2(float(lo) * rs, float(hi) * rs); };
+    w.m = u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])), __float_as_uint(float(m[2])),
+                __float_as_uint(float(m[3]))};
+    if (TH) {
+        w.p = u32x4{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8]), e2(rg[1], rg[2])};
+        w.t = u32x3{e2(rg[3], rg[4]), e2(rg[5], rg[6]), e2(rg[7], rg[8])};
+    } else {
+        w.p = u32x4{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8]), 0u};
+        w.t = u32x3{0u, 0u, 0u};
+    }
+    return m[0] + m[3];
+}
+
+template <bool TH>
+__device__ inline void store_split_raw(Buf b, uint32_t cell, uint32_t G, const SplitRaw<TH>& w) {
     const uint32_t v12 = cell * 12u;
     if (TH) {
         const uint32_t v16 = cell * 16u;
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
-                                                     __float_as_uint(float(m[2])), __float_as_uint(float(m[3]))},
-                                               b.r, v16, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8]), e2(rg[1], rg[2])},
-                                               b.r, v16, 2 * G, 0);
-        __builtin_amdgcn_raw_buffer_store_b96(u32x3{e2(rg[3], rg[4]), e2(rg[5], rg[6]), e2(rg[7], rg[8])}, b.r, v12,
-                                              4 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(w.m, b.r, v16, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(w.p, b.r, v16, 2 * G, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(w.t, b.r, v12, 4 * G, 0);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b96(u32x3{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])),
-                                                    __float_as_uint(float(m[2]))},
-                                              b.r, v12, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b96(u32x3{e2(rf[3], rf[4]), e2(rf[5], rf[6]), e2(rf[7], rf[8])}, b.r, v12,
-                                              G + G / 2, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{w.m[0], w.m[1], w.m[2]}, b.r, v12, 0u, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(u32x3{w.p[0], w.p[1], w.p[2]}, b.r, v12, G + G / 2, 0);
     }
-    return m[0] + m[3];
+}
+
+// Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
+// Returns m0 + m3, which is finite exactly when the stored moments are.
+template <class R, class S, bool TH>
+__device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
+                                const R Tr, const R q) {
+    SplitRaw<TH> w;
+    const R chk = encode_split<R, S, TH>(df, dg, k, Tr, q, w);
+    store_split_raw<TH>(b, cell, G, w);
+    return chk;
+}
+
+// The value a stored offset reads back as (storage rounding).
+template <class S, class R> __device__ inline R stored_value(R x) {
+    if constexpr (sizeof(S) == 2) return R(Io16<std::is_same<S, bf16_t>::value>::dec(Io16<std::is_same<S, bf16_t>::value>::enc(float(x)), 0));
+    else if constexpr (sizeof(S) == 4) return R(float(x));
+    else return x;
 }
 
 // Make this row's LDS writes visible to the other lanes of the item.  A
@@ -886,6 +918,438 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     if (A.bad) raise_flag(A.bad, bad);
 }
 
+// ---- fused pass: the corrector of step n and the predictor of step n+1 ----
+// One march over a chunk forms, row by row,
+//   f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi(f~*))      (eq:semi-heun, step n)
+//   f~*'  = f~n+1 + C(f~n+1) - dt D(phi(f~n+1))            (eq:semi, step n+1)
+// reading f~* with a halo of four cells (the second stage needs f~n+1 two
+// cells beyond the strip, and f~n+1 there needs phi(f~*) two cells further)
+// and f~n where f~n+1 is formed, and writing f~n+1 and f~*'.  The second
+// stage starts from f~n+1 as it is stored (rounded to the storage format,
+// the split record encoded and decoded in registers), so the pass gives
+// the bits of a corrector launch followed by a predictor launch.  The
+// second stage's weights are the first stage's doubled (dt against dt/2; a
+// power-of-two scaling, so every rounding is the same).
+//
+// Rows: when row r of f~* arrives the first stage finishes row j1 = r - 2
+// and the second stage row j1 - 2.  Each stage keeps its own y rings and
+// partial updates; both exchange x neighbours through LDS (one buffer per
+// stage, a barrier after each write).  At a y wall the first stage's ghost
+// rows come from the stored f~* of the mirror rows (as in fv_item); the
+// second stage's ghost rows are the wall images of its rows 0, 1 (ny - 1,
+// ny - 2), put into its ring when those rows are formed.  x is periodic
+// (with x walls the host uses separate launches).
+template <class R, class S, bool TH, int W>
+__device__ __forceinline__ void fv_item_fused(const FvArgs<R>& A, const int item, const int t,
+                                              R (*lds1)[W], R (*lds2)[W]) {
+    constexpr int NSP = TH ? 2 : 1;
+    constexpr int HF = FV_FUSED_HALO;
+    const int strip = item % A.n_strips, chunk = item / A.n_strips;
+    const int x0 = strip * A.strip_w;
+    const int own = min(A.strip_w, A.nx - x0);
+    const int lanes = own + 2 * HF;
+    if ((t & ~63) >= lanes) return;  // a wave without columns of this strip leaves
+
+    int col = x0 - HF + t;
+    if (col < 0) col += A.nx;
+    else if (col >= A.nx) col -= A.nx;
+    if (t >= lanes) col = 0;                          // idle lane of a live wave
+    const bool owned = t >= HF && t < HF + own;       // f~*' formed and stored, f~n+1 stored
+    const bool formed = t >= 2 && t < lanes - 2;      // f~n+1 formed
+
+    R xc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xc[q] = formed ? A.xcoef[col * 8 + q] : R(0);
+
+    const uint32_t gb = A.group_bytes, ro = A.rest_off;
+    const uint32_t nxu = uint32_t(A.nx), colu = uint32_t(col);
+    const Buf bstar = make_buf(A.src, A.state_bytes);    // f~*
+    const Buf bn = make_buf(A.aux, A.state_bytes);       // f~n
+    const Buf bnext = make_buf(A.dst, A.state_bytes);    // f~n+1
+    const Buf bstar2 = make_buf(A.dst2, A.state_bytes);  // f~*'
+
+    const int y0 = chunk * A.chunk_h;
+    const int y1 = min(y0 + A.chunk_h, A.ny);
+    const StageK<R> k = A.k;
+    typedef const __attribute__((address_space(4))) R CR;
+    constexpr bool SPLIT = is_split<S>::value;
+    constexpr bool AHEAD = sizeof(R) == 4;
+    constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2 && !SPLIT;
+
+    // first stage: phi(f~*) rings and partial updates; second stage: phi(f~n+1)
+    R UP1[4][NSP][3], DN1[4][NSP][3], U1[2][NSP][9];
+    R UP2[4][NSP][3], DN2[4][NSP][3], U2[2][NSP][9];
+    R TR1[4] = {0, 0, 0, 0}, TR2[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) UP1[q][s][p] = DN1[q][s][p] = UP2[q][s][p] = DN2[q][s][p] = R(0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int a = 0; a < 9; ++a) U1[q][s][a] = U2[q][s][a] = R(0);
+
+    auto map_row = [&](const int r) __attribute__((always_inline)) {
+        int row = r;
+        if (r < 0) row = A.wall_y ? -r - 1 : r + A.ny;
+        else if (r >= A.ny) row = A.wall_y ? 2 * A.ny - 1 - r : r - A.ny;
+        return min(max(row, 0), A.ny - 1);
+    };
+    auto row_tref = [&](const int r) __attribute__((always_inline)) {
+        return (TH && A.tref) ? R(((const CR*)A.tref)[map_row(r)]) : k.ref_g;
+    };
+    auto row_qref = [&](const int r) __attribute__((always_inline)) {
+        return (SPLIT && TH && A.qref) ? R(((const CR*)A.qref)[map_row(r)]) : R(0);
+    };
+
+    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
+    SplitRaw<TH> PR[2], AR[2];
+    auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int Q = decltype(slot_tag)::value & 1;
+        const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
+        if constexpr (SPLIT) {
+            load_split_raw<S, TH>(bstar, cell, gb, PR[Q]);
+        } else {
+            load_cell<R, S, TH>(bstar, cell, gb, ro, PF[Q], PG[Q]);
+            if (AHEAD_OWN) load_cell<R, S, TH>(bn, cell, gb, ro, PH[Q], PHG[Q]);
+        }
+    };
+    auto prefetch_own = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int Q = decltype(slot_tag)::value & 1;
+        if constexpr (SPLIT) load_split_raw<S, TH>(bn, uint32_t(map_row(r)) * nxu + colu, gb, AR[Q]);
+    };
+
+    bool bad = false;
+    // y flux of one stage for a row whose weights are yc: rings UP, DN hold
+    // rows j-2 .. j+1 in slots SL .. SL+3, the current row is ph (j+2)
+    auto yflux = [&](auto& out, const auto& UP, const auto& DN, const auto& ph, const R* yc, const R* TRr,
+                     const R trow, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot_tag)::value;
+        R sU = 0, sD = 0;
+        if (TH && A.tref) {
+            const R tj = TRr[(SL + 2) & 3];
+            sU = yc[0] * (TRr[SL] - tj) + yc[1] * (TRr[(SL + 1) & 3] - tj) + yc[3] * (TRr[(SL + 3) & 3] - tj);
+            sD = yc[4] * (TRr[(SL + 1) & 3] - tj) + yc[6] * (TRr[(SL + 3) & 3] - tj) + yc[7] * (trow - tj);
+        }
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                out[s][upop(p)] -= yc[0] * UP[SL][s][p] + yc[1] * UP[(SL + 1) & 3][s][p] +
+                                   yc[2] * UP[(SL + 2) & 3][s][p] + yc[3] * UP[(SL + 3) & 3][s][p];
+                out[s][dpop(p)] -= yc[4] * DN[(SL + 1) & 3][s][p] + yc[5] * DN[(SL + 2) & 3][s][p] +
+                                   yc[6] * DN[(SL + 3) & 3][s][p] + yc[7] * ph[s][dpop(p)];
+                if (TH && s == NSP - 1) {
+                    out[s][upop(p)] -= wt<R>(upop(p)) * sU;
+                    out[s][dpop(p)] -= wt<R>(dpop(p)) * sD;
+                }
+            }
+    };
+    auto ylw = [&](const int j, R* yc) __attribute__((always_inline)) {   // (a periodic row wraps)
+        const CR* yw = (const CR*)(A.ycoef) + int64_t(map_row(j)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) yc[q] = yw[q];
+    };
+    // the brackets of a wall's ghost row from those of its mirror row
+    // (double reflection of f; isothermal anti-reflection of g, with the
+    // ghost row shifted by the mirror's thermal reference trow)
+    auto ghost_up = [&](const auto& DNm, const int s, const int p, const R Tw) __attribute__((always_inline)) {
+        return (TH && s == NSP - 1) ? R(2) * wt<R>(upop(p)) * Tw - DNm[s][p] : DNm[s][p];
+    };
+    auto ghost_dn = [&](const auto& UPm, const int s, const int p, const R Tw) __attribute__((always_inline)) {
+        return (TH && s == NSP - 1) ? R(2) * wt<R>(dpop(p)) * Tw - UPm[s][p] : UPm[s][p];
+    };
+
+    auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot_tag)::value;
+        const int j1 = r - 2, j2 = r - 4;
+        // ================= first stage: phi(f~*) of row r =================
+        const bool my = A.wall_y && (r < 0 || r >= A.ny);
+        const R Tr = row_tref(r), Qr = row_qref(r);
+        const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
+        if (!AHEAD) prefetch(r, Slot<SL>{});
+        R df[9], dg[9], mm[4];
+        if constexpr (SPLIT) {
+            decode_split<R, S, TH>(PR[SL & 1], mm, df, dg);
+            __builtin_amdgcn_sched_barrier(0);
+            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                df[a] = PF[SL & 1][a];
+                if (TH) dg[a] = PG[SL & 1][a];
+            }
+            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+            if (!AHEAD_OWN)
+                load_cell<R, S, TH>(bn, uint32_t(map_row(r)) * nxu + colu, gb, ro, PH[SL & 1], PHG[SL & 1]);
+        }
+        R ph[NSP][9], bs[NSP][9];
+        if constexpr (SPLIT) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, Qr, ph, bs);
+        else stage<R, TH, false>(df, dg, k, Tr, ph, bs);
+        {
+            R tmp[NSP][9];
+#pragma unroll
+            for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                for (int a = 1; a < 9; ++a) tmp[s][a] = ph[s][a];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                ph[0][a] = my ? tmp[0][opp(a)] : tmp[0][a];
+                if (TH) ph[NSP - 1][a] = my ? R(2) * wt<R>(a) * Tw - tmp[NSP - 1][opp(a)] : tmp[NSP - 1][a];
+            }
+        }
+        // ---- first stage: finish row j1 (f~n+1) ----
+        R yc1[8];
+        ylw(j1, yc1);
+        R fn[NSP][9];
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int a = 0; a < 9; ++a) fn[s][a] = U1[SL & 1][s][a];
+        yflux(fn, UP1, DN1, ph, yc1, TR1, Tr, Slot<SL>{});
+        const R Tr1 = TR1[(SL + 2) & 3];   // thermal reference of row j1
+        const R Qr1 = row_qref(j1);
+        // ---- x exchange of phi(f~*), partial update of row r ----
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) lds1[s * 6 + p][t] = ph[s][xpop(p)];
+        lanes_sync<W>();
+        if (SPLIT && AHEAD) {
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch_own(r + 1, Slot<SL + 1>{});
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (formed) {
+            R phn[NSP][9], bsn[NSP][9], base[NSP][9];
+            if constexpr (SPLIT) {
+                R hm[4], hf[9], hg[9];
+                decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
+                stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, Qr, phn, bsn);
+            } else {
+                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bsn);
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                base[0][a] = R(0.5) * (bsn[0][a] + df[a]);
+                if (TH) base[NSP - 1][a] = R(0.5) * (bsn[NSP - 1][a] + dg[a]);
+            }
+#pragma unroll
+            for (int s = 0; s < NSP; ++s) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const int a = xpop(p);
+                    const R* L = lds1[s * 6 + p];
+                    const R v = ph[s][a];
+                    R d;
+                    if (cx(a) > 0) d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
+                    else d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
+                    base[s][a] -= d;
+                }
+#pragma unroll
+                for (int a = 0; a < 9; ++a) U1[SL & 1][s][a] = base[s][a];
+            }
+        }
+        TR1[SL] = Tr;
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                UP1[SL][s][p] = ph[s][upop(p)];
+                DN1[SL][s][p] = ph[s][dpop(p)];
+            }
+
+        // ====== f~n+1 of row j1: stored, then the second stage's input ======
+        const bool in1 = j1 >= y0 && j1 < y1;
+        R dn[NSP][9];   // f~n+1 as stored (offsets)
+        if constexpr (SPLIT) {
+            SplitRaw<TH> w;
+            const R chk = encode_split<R, S, TH>(fn[0], fn[NSP - 1], k, Tr1, Qr1, w);
+            if (owned && in1) {
+                store_split_raw<TH>(bnext, uint32_t(j1) * nxu + colu, gb, w);
+                bad = bad || !__builtin_isfinite(chk);
+            }
+            R m2[4];
+            decode_split<R, S, TH>(w, m2, dn[0], dn[NSP - 1]);
+            stage_split<R, TH, true, false>(m2, dn[0], dn[NSP - 1], k, Tr1, Qr1, ph, bs);
+        } else {
+            if (owned && in1) {
+                store_cell<R, S, TH>(bnext, uint32_t(j1) * nxu + colu, gb, ro, fn[0], fn[NSP - 1]);
+                bad = bad || !__builtin_isfinite(TH ? fn[0][0] + fn[NSP - 1][0] : fn[0][0]);
+            }
+#pragma unroll
+            for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                for (int a = 0; a < 9; ++a) dn[s][a] = stored_value<S>(fn[s][a]);
+            stage<R, TH, true>(dn[0], dn[NSP - 1], k, Tr1, ph, bs);
+        }
+        // ---- second stage's ghost rows at the y walls ----
+        R Tr2 = Tr1;
+        if (A.wall_y) {
+            if (j1 == 0) {          // row -1 is the image of row 0
+                const R Twb = A.Tb - Tr1;
+                R cu[NSP][3], cd[NSP][3];
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) { cu[s][p] = ph[s][upop(p)]; cd[s][p] = ph[s][dpop(p)]; }
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        UP2[(SL + 3) & 3][s][p] = ghost_up(cd, s, p, Twb);
+                        DN2[(SL + 3) & 3][s][p] = ghost_dn(cu, s, p, Twb);
+                    }
+                TR2[(SL + 3) & 3] = Tr1;
+            } else if (j1 == 1) {   // row -2 is the image of row 1
+                const R Twb = A.Tb - Tr1;
+                R cu[NSP][3], cd[NSP][3];
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) { cu[s][p] = ph[s][upop(p)]; cd[s][p] = ph[s][dpop(p)]; }
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        UP2[(SL + 1) & 3][s][p] = ghost_up(cd, s, p, Twb);
+                        DN2[(SL + 1) & 3][s][p] = ghost_dn(cu, s, p, Twb);
+                    }
+                TR2[(SL + 1) & 3] = Tr1;
+            } else if (j1 == A.ny || j1 == A.ny + 1) {
+                // rows ny, ny + 1 are the images of rows ny - 1 (slot SL+3)
+                // and ny - 2 (slot SL+1)
+                const bool first = j1 == A.ny;
+                const R Trm = first ? TR2[(SL + 3) & 3] : TR2[(SL + 1) & 3];
+                const R Twt = A.Tt - Trm;
+                R mu[NSP][3], md[NSP][3];
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        mu[s][p] = first ? UP2[(SL + 3) & 3][s][p] : UP2[(SL + 1) & 3][s][p];
+                        md[s][p] = first ? DN2[(SL + 3) & 3][s][p] : DN2[(SL + 1) & 3][s][p];
+                    }
+#pragma unroll
+                for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        ph[s][upop(p)] = ghost_up(md, s, p, Twt);
+                        ph[s][dpop(p)] = ghost_dn(mu, s, p, Twt);
+                    }
+                Tr2 = Trm;
+            }
+        }
+        // ---- second stage: finish row j2 (f~*'), stored ----
+        {
+            R yc2[8];
+            ylw(j2, yc2);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) yc2[q] = R(2) * yc2[q];
+            R out[NSP][9];
+#pragma unroll
+            for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                for (int a = 0; a < 9; ++a) out[s][a] = U2[SL & 1][s][a];
+            yflux(out, UP2, DN2, ph, yc2, TR2, Tr2, Slot<SL>{});
+            if (owned && j2 >= y0 && j2 < y1) {
+                const R trow = TR2[(SL + 2) & 3];
+                R chk;
+                if constexpr (SPLIT)
+                    chk = store_split<R, S, TH>(bstar2, uint32_t(j2) * nxu + colu, gb, out[0], out[NSP - 1], k, trow,
+                                                row_qref(j2));
+                else {
+                    store_cell<R, S, TH>(bstar2, uint32_t(j2) * nxu + colu, gb, ro, out[0], out[NSP - 1]);
+                    chk = TH ? out[0][0] + out[NSP - 1][0] : out[0][0];
+                }
+                bad = bad || !__builtin_isfinite(chk);
+            }
+        }
+        // ---- x exchange of phi(f~n+1), partial update of row j1 ----
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) lds2[s * 6 + p][t] = ph[s][xpop(p)];
+        lanes_sync<W>();
+        if (owned) {
+#pragma unroll
+            for (int s = 0; s < NSP; ++s) {
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const int a = xpop(p);
+                    const R* L = lds2[s * 6 + p];
+                    const R v = ph[s][a];
+                    R d;
+                    if (cx(a) > 0) d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
+                    else d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
+                    bs[s][a] -= R(2) * d;
+                }
+#pragma unroll
+                for (int a = 0; a < 9; ++a) U2[SL & 1][s][a] = bs[s][a];
+            }
+        }
+        TR2[SL] = Tr2;
+#pragma unroll
+        for (int s = 0; s < NSP; ++s)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                UP2[SL][s][p] = ph[s][upop(p)];
+                DN2[SL][s][p] = ph[s][dpop(p)];
+            }
+    };
+
+    // rows y0-4 .. y1+3 of f~* in trips of four (a chunk of height 4k takes
+    // exactly k+2 trips; the last chunk may run up to three rows further,
+    // whose results are not stored)
+    if (AHEAD) prefetch(y0 - 4, Slot<0>{});
+    if (AHEAD) prefetch_own(y0 - 4, Slot<0>{});
+    for (int r = y0 - 4; r <= y1 + 3; r += 4) {
+        row_step(r, Slot<0>{});
+        row_step(r + 1, Slot<1>{});
+        row_step(r + 2, Slot<2>{});
+        row_step(r + 3, Slot<3>{});
+    }
+    if (A.bad) raise_flag(A.bad, bad);
+}
+
+// Fused pass over one block: one wide item or four narrow ones (as fv_block).
+template <class R, class S, bool TH>
+__device__ __forceinline__ void fv_block_fused(const FvArgs<R>& A, const int item, const bool narrow, R* lds_mem) {
+    constexpr int NSP = TH ? 2 : 1;
+    if (narrow) {
+        R* mine = lds_mem + (threadIdx.x >> 6) * (2 * 6 * NSP * 64);
+        fv_item_fused<R, S, TH, 64>(A, item, threadIdx.x & 63, reinterpret_cast<R(*)[64]>(mine),
+                                    reinterpret_cast<R(*)[64]>(mine + 6 * NSP * 64));
+    } else {
+        fv_item_fused<R, S, TH, FV_LANES>(A, item, threadIdx.x, reinterpret_cast<R(*)[FV_LANES]>(lds_mem),
+                                          reinterpret_cast<R(*)[FV_LANES]>(lds_mem + 6 * NSP * FV_LANES));
+    }
+}
+
+// Register budget of the fused pass: the thermal instances hold two sets of
+// rings for f and g (about 330 registers, one wave per SIMD); the others fit
+// two waves per SIMD.
+template <bool TH> constexpr int FV_FUSED_MIN_BLOCKS = TH ? 1 : 2;
+
+template <class R, class S, bool TH>
+__global__ void __launch_bounds__(FV_LANES, FV_FUSED_MIN_BLOCKS<TH>) fv_fused(FvArgs<R> A) {
+    __shared__ R lds_mem[2 * 6 * (TH ? 2 : 1) * FV_LANES];
+    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
+    const int b = xcd_item(blockIdx.x, nb);
+    if (b >= nb) return;
+    if (A.narrow) {
+        const int item = 4 * b + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (item >= A.n_items) return;
+        fv_block_fused<R, S, TH>(A, item, true, lds_mem);
+    } else {
+        fv_block_fused<R, S, TH>(A, b, false, lds_mem);
+    }
+}
+
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32
 // arithmetic) or one (FP64).
 template <class R> constexpr int FV_MIN_BLOCKS = (sizeof(R) == 4 ? 8 : 4) * 64 / FV_LANES;
@@ -1023,6 +1487,50 @@ static hipError_t launch_typed(bool thermal, bool corrector, const void* args, h
             hipLaunchKernelGGL((fv_pass<R, S, false, false>), grid, block, 0, s, A);
     }
     return hipGetLastError();
+}
+
+template <class R, class S>
+static hipError_t launch_fused_typed(bool thermal, const void* args, hipStream_t s) {
+    const FvArgs<R>& A = *static_cast<const FvArgs<R>*>(args);
+    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
+    dim3 grid(8 * ((nb + 7) / 8)), block(FV_LANES);
+    if (thermal) hipLaunchKernelGGL((fv_fused<R, S, true>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((fv_fused<R, S, false>), grid, block, 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv_fused(int storage, bool thermal, const void* args, hipStream_t s) {
+    switch (storage) {
+        case ST_F64: return launch_fused_typed<double, double>(thermal, args, s);
+        case ST_F32: return launch_fused_typed<float, float>(thermal, args, s);
+        case ST_BF16: return launch_fused_typed<float, bf16_t>(thermal, args, s);
+        case ST_F16: return launch_fused_typed<float, f16_t>(thermal, args, s);
+        case ST_BF16S: return launch_fused_typed<float, bf16s_t>(thermal, args, s);
+        case ST_F16S: return launch_fused_typed<float, f16s_t>(thermal, args, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class R, class S>
+static int fused_resident_typed(bool thermal) {
+    int per_cu = 0, dev = 0, cus = 0;
+    const void* k = thermal ? (const void*)fv_fused<R, S, true> : (const void*)fv_fused<R, S, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, FV_LANES, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+int fv_fused_resident_blocks(int storage, bool thermal) {
+    switch (storage) {
+        case ST_F64: return fused_resident_typed<double, double>(thermal);
+        case ST_F32: return fused_resident_typed<float, float>(thermal);
+        case ST_BF16: return fused_resident_typed<float, bf16_t>(thermal);
+        case ST_F16: return fused_resident_typed<float, f16_t>(thermal);
+        case ST_BF16S: return fused_resident_typed<float, bf16s_t>(thermal);
+        case ST_F16S: return fused_resident_typed<float, f16s_t>(thermal);
+    }
+    return 0;
 }
 
 template <class R, class S>

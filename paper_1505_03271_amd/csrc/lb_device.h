@@ -74,7 +74,9 @@ template <> struct Codec<f16_t> {
         return R(__half2float(__ushort_as_half(p->bits)));
     }
     template <class R> __device__ static void store(f16_t* p, R v) {
-        p->bits = __half_as_ushort(__float2half_rn(float(v)));
+        float x = float(v);
+        asm("" : "+v"(x));   // round the FP32 value (no fused multiply-add-convert)
+        p->bits = __half_as_ushort(__float2half_rn(x));
     }
 };
 

@@ -16,6 +16,9 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3, ST_BF16S = 4, ST
 constexpr int FV_LANES = 256;
 constexpr int FV_NARROW = 64;
 constexpr int FV_HALO = 2;
+// The fused pass (corrector of a step and predictor of the next) forms f~n+1
+// two cells beyond its strip, so it reads f~* with a halo of four.
+constexpr int FV_FUSED_HALO = 4;
 
 // Stage constants of the FV kernel in offset arithmetic (see fv.hip), with
 // d = p - w ref, poly = f_eq/(w rho), frc = F/(w rho):
@@ -34,9 +37,10 @@ struct StageK {
 
 template <class R>
 struct FvArgs {
-    const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector)
-    void* dst;         // output state
-    void* aux;         // corrector: its own-cell input f~n (read only); NULL otherwise
+    const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector, fused pass)
+    void* dst;         // output state (fused pass: f~n+1)
+    void* aux;         // corrector, fused pass: the input f~n (read only); NULL otherwise
+    void* dst2;        // fused pass: f~* of the next step; NULL otherwise
     uint32_t state_bytes;  // whole state (grouped layout, see pop_index; or SplitLayout)
     uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
     uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
@@ -75,6 +79,9 @@ struct StArgs {
 // Host launchers (defined in the .hip files).  `storage` selects the
 // template instance; every launcher returns the hipError_t of the launch.
 hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
+// One fused pass (x periodic): args as for the corrector, plus dst2.
+hipError_t launch_fv_fused(int storage, bool thermal, const void* args, hipStream_t s);
+int fv_fused_resident_blocks(int storage, bool thermal);
 // Serving: one launch over the work items of many simulations.  args holds
 // 2 FvArgs per simulation (predictor, corrector); items are (simulation,
 // local item), the n_wide items of wide-strip members first, then the
