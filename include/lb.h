@@ -242,7 +242,9 @@ int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
  * rounding step).  lb_rebase sets T_ref(row) to the current row means and
  * q(row) to 3 x the row mean of sum_a c_ay r_a, and re-encodes the stored g
  * (one rounding); with lb_set_rebase(every > 0) lb_step does this after
- * every `every` steps (0, the default, never; group steps never do).
+ * every `every` steps (0, the default, never), and so do group steps for a
+ * member (its count of steps since the last renewal goes with it into and
+ * out of the group, so the result is the same alone and in a group).
  * No-ops for FP64 storage or isothermal runs. */
 int lb_rebase(lb_sim* sim);
 int lb_set_rebase(lb_sim* sim, int64_t every);
@@ -276,11 +278,12 @@ int lb_set_fv_chunk(lb_sim* sim, int rows);
  * step moves four states instead of five.  It needs a second pair of state
  * buffers, allocated at the first such run (if that allocation fails, or
  * while the caller captures the stream before it was made, the steps use
- * separate launches).  The results are bit-identical either way.  On by
- * default for FP32 storage and for isothermal runs, where it is the faster
- * shape; off for thermal 16-bit and FP64 storage, whose fused kernel holds
- * both species' rings for two stages and runs one wave per SIMD.  on = 0
- * frees the second pair.  LB_EINVAL for other values. */
+ * separate launches).  The results are bit-identical either way.  Off by
+ * default: the fused kernel holds both stages' rings (one wave per SIMD
+ * with thermal populations), which measured 3% faster than separate
+ * launches on a 4096^2 FP32 grid and slower on thermal 16-bit storage and
+ * on smaller grids.  on = 0 frees the second pair.  LB_EINVAL for other
+ * values. */
 int lb_set_fv_fused(lb_sim* sim, int on);
 /* The current setting (1 on, 0 off) in *on. */
 int lb_get_fv_fused(const lb_sim* sim, int* on);
@@ -294,13 +297,15 @@ size_t lb_device_bytes(const lb_sim* sim);
  * storage format and thermal flag, any sizes, grids and parameters) and
  * advances all of them with one predictor and one corrector launch per
  * step over the work items of every member, captured with the group's
- * counter updates in a HIP graph of nsteps steps (re-captured only when the
+ * counter updates (and the members' renewals of their thermal references,
+ * lb_set_rebase) in a HIP graph of nsteps steps (re-captured only when the
  * membership or nsteps changes).  Each member carries its own remaining
  * step count and stops exactly there, so a member's state after its steps
  * is bit-identical to running it alone with lb_step.  Members stay owned by
  * the caller.  While it is in a group, a member is advanced only by the
  * group: lb_step, lb_init, lb_set_grid, lb_set_state, lb_set_populations,
- * lb_rebase, lb_set_fv_lanes and lb_set_fv_chunk on it return LB_ESTATE, and
+ * lb_rebase, lb_set_rebase, lb_set_fv_lanes, lb_set_fv_chunk and
+ * lb_set_fv_fused on it return LB_ESTATE, and
  * so does adding it to a second group; reading it (lb_moments, lb_nusselt,
  * lb_get_state, ...) is allowed once the group's stream has been
  * synchronised (lb_group_sync or lb_group_remaining).

@@ -250,10 +250,9 @@ __global__ void set_pops_kernel(AuxArgs A, const double* in) {
 // of sum_a c_ay r_a (sum_a w_a c_ay^2 = 1/3), and each stored residual of a
 // population along y moves by w_a c_ay (q_old - q_new) (one rounding).
 template <class S>
-__global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
+__device__ __forceinline__ void rebase_row(const AuxArgs& A, const int j) {
     __shared__ double red[2][4];
     __shared__ float newref, newq;
-    const int j = blockIdx.x;
     S* st = static_cast<S*>(A.state);
     constexpr bool SPLIT = is_split<S>::value;
     const bool with_q = SPLIT && A.qref;
@@ -317,12 +316,53 @@ __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
         const_cast<float*>(A.tref)[j] = nr;
         if (with_q) const_cast<float*>(A.qref)[j] = nq;
     }
+    __syncthreads();   // the shared reduction slots are free for the next row
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
+    rebase_row<S>(A, blockIdx.x);
+}
+
+// Serving: the rows of many simulations (items = (simulation, row)); a
+// simulation's rows are renewed only when due[simulation] is set, which the
+// step counter kernel decides.  Blocks stride over the items.
+template <class S>
+__global__ void __launch_bounds__(256) rebase_multi_kernel(const AuxArgs* args, const int2* items, int n_items,
+                                                           const int* due) {
+    for (int q = blockIdx.x; q < n_items; q += gridDim.x) {
+        const int2 it = items[q];
+        if (!due[it.x]) continue;   // uniform over the block
+        const AuxArgs A = args[it.x];
+        rebase_row<S>(A, it.y);
+    }
 }
 
 template <class S>
 static hipError_t rebase_typed(const AuxArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(rebase_kernel<S>, dim3(a.ny), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+template <class S>
+static hipError_t rebase_multi_typed(const AuxArgs* args, const int2* items, int n_items, const int* due,
+                                     hipStream_t s) {
+    const int blocks = n_items < 2048 ? n_items : 2048;
+    hipLaunchKernelGGL(rebase_multi_kernel<S>, dim3(blocks), dim3(256), 0, s, args, items, n_items, due);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebase_multi(int storage, const AuxArgs* args, const int2* items, int n_items, const int* due,
+                               hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (storage) {
+        case ST_F32: return rebase_multi_typed<float>(args, items, n_items, due, s);
+        case ST_BF16: return rebase_multi_typed<bf16_t>(args, items, n_items, due, s);
+        case ST_F16: return rebase_multi_typed<f16_t>(args, items, n_items, due, s);
+        case ST_BF16S: return rebase_multi_typed<bf16s_t>(args, items, n_items, due, s);
+        case ST_F16S: return rebase_multi_typed<f16s_t>(args, items, n_items, due, s);
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s) {

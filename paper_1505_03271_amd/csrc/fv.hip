@@ -1423,9 +1423,21 @@ __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
     fv_block<R, S, TH, CORR>(A, it.y, narrow, lds_mem);
 }
 
-__global__ void tick_kernel(int64_t* left, int n) {
+// One group step done: every member that stepped has one step less to go,
+// and (every[i] > 0) counts towards its next renewal of the thermal
+// references, due[i] = 1 when the step count reaches it (as lb_step does).
+__global__ void tick_kernel(int64_t* left, int n, const int64_t* every, int64_t* since, int* due) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && left[i] > 0) left[i] -= 1;
+    if (i >= n) return;
+    int d = 0;
+    if (left[i] > 0) {
+        left[i] -= 1;
+        if (every && every[i] > 0 && ++since[i] >= every[i]) {
+            since[i] = 0;
+            d = 1;
+        }
+    }
+    if (due) due[i] = d;
 }
 
 template <class R, class S>
@@ -1462,9 +1474,9 @@ hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tick(int64_t* left, int n, hipStream_t s) {
+hipError_t launch_tick(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tick_kernel, dim3((n + 255) / 256), dim3(256), 0, s, left, n);
+    hipLaunchKernelGGL(tick_kernel, dim3((n + 255) / 256), dim3(256), 0, s, left, n, every, since, due);
     return hipGetLastError();
 }
 

@@ -137,7 +137,7 @@ def test_group_member_changes_only_through_its_group():
     state = a.get_state()
     calls = [lambda: a.step(1), lambda: a.init(rho, ux, uy, T), lambda: a.set_grid(P["xf"], P["yf"]),
              lambda: a.set_state(state), lambda: a.rebase(), lambda: a.set_fv_lanes(0),
-             lambda: a.set_fv_chunk(8), lambda: g2.add(a, 5)]
+             lambda: a.set_fv_chunk(8), lambda: a.set_rebase(5), lambda: a.set_fv_fused(1), lambda: g2.add(a, 5)]
     for call in calls:
         with pytest.raises(lb.LBError) as e:
             call()
@@ -235,3 +235,46 @@ def test_server_lists_a_blown_up_request_as_failed():
     assert [r["id"] for r in stats["failed"]] == [77]
     assert sorted(r["id"] for r in stats["requests"]) == sorted(r["id"] for r in trace)
     assert all(np.all(np.isfinite(r["nu"])) for r in stats["requests"])
+
+
+@pytest.mark.parametrize("storage", ["bf16s", "f32", "f16s"])
+def test_group_members_renew_their_references_as_alone(storage):
+    """Members with a rebase interval (lb_set_rebase) renew their thermal
+    references inside the group's captured steps, on the same schedule as
+    alone: the state after all steps equals the solo run's bit for bit, also
+    for a member that leaves mid-way (its count since the last renewal goes
+    with it) and finishes alone, and for members without renewal."""
+    say(f"group rebase {storage}")
+    cases = [(300, 77, 1e7, 1.0, 57, 10), (128, 128, 1e6, 0.7, 45, 7), (97, 64, 3e6, 1.0, 33, 0),
+             (200, 150, 1e8, 7.0, 40, 3)]
+    alone = []
+    for k, (nx, ny, Ra, Pr, steps, every) in enumerate(cases):
+        s = _rb_sim(nx, ny, Ra, Pr, storage, 300 + k)
+        if every:
+            s.set_rebase(every)
+        s.step(steps)
+        alone.append(s.get_state())
+        s.close()
+    sims = []
+    for k, (nx, ny, Ra, Pr, steps, every) in enumerate(cases):
+        s = _rb_sim(nx, ny, Ra, Pr, storage, 300 + k)
+        if every:
+            s.set_rebase(every)
+        sims.append(s)
+    g = lb.Group(4, lb.current_stream())
+    slots = {k: g.add(sims[k], cases[k][4]) for k in (0, 1, 2)}
+    g.step(6)
+    slots[3] = g.add(sims[3], cases[3][4])
+    g.step(11)
+    left1 = g.remaining()[slots[1]]
+    g.remove(slots[1])                 # leaves with 4 steps since its last renewal ...
+    sims[1].step(int(left1))           # ... and finishes alone
+    for _ in range(10):
+        g.step(6)
+    left = g.remaining()
+    assert all(left[slots[k]] == 0 for k in (0, 2, 3))
+    for k in range(len(cases)):
+        assert np.array_equal(sims[k].get_state(), alone[k]), f"member {k}"
+    g.close()
+    for s in sims:
+        s.close()
