@@ -15,7 +15,9 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB: another build of oracle.c (the sanitizer test loads one built
+# with -fsanitize=address,undefined)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SCHEMES = {"heun": 0, "semi": 1, "euler": 2, "st": 3}
 
 
