@@ -278,14 +278,15 @@ int lb_set_fv_chunk(lb_sim* sim, int rows);
  * step moves four states instead of five.  It needs a second pair of state
  * buffers, allocated at the first such run (if that allocation fails, or
  * while the caller captures the stream before it was made, the steps use
- * separate launches).  The results are bit-identical either way.  Off by
- * default: the fused kernel holds both stages' rings (one wave per SIMD
- * with thermal populations), which measured 3% faster than separate
- * launches on a 4096^2 FP32 grid and slower on thermal 16-bit storage and
- * on smaller grids.  on = 0 frees the second pair.  LB_EINVAL for other
- * values. */
+ * separate launches).  The results are bit-identical either way.
+ * on = 1 uses them wherever they apply, 0 never, -1 (the default) where they
+ * measured faster on MI355X: FP32 storage from about 2048^2 cells with g
+ * (+22 to +30%) and 4096^2 without (+14%), split BF16 storage with g at
+ * 4096^2 (+2%); they are slower on smaller grids and on the other 16-bit
+ * formats.  A setting under which they do not apply frees the second pair.
+ * LB_EINVAL for other values. */
 int lb_set_fv_fused(lb_sim* sim, int on);
-/* The current setting (1 on, 0 off) in *on. */
+/* The current setting (1, 0 or -1) in *on. */
 int lb_get_fv_fused(const lb_sim* sim, int* on);
 
 /* Number of bytes of device memory held by the handle. */

@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "liblb.so")
+# LB_LIB: another build of the library (the sanitizer and tuning builds)
+LIB_PATH = os.environ.get("LB_LIB") or os.path.join(PKG, "liblb.so")
 
 SCHEMES = {"heun": 0, "semi": 1, "euler": 2, "st": 3}
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16s": 4, "f16s": 5}
@@ -314,12 +315,15 @@ class Sim:
         return {names[k]: (int(n[k]), float(ms[k])) for k in range(4)}
 
     def set_fv_fused(self, on):
-        _check(lib().lb_set_fv_fused(self.h, int(bool(on))))
+        """on: 1 (True) fused passes wherever they apply, 0 (False) never,
+        -1 (None) where they pay (the default)."""
+        _check(lib().lb_set_fv_fused(self.h, -1 if on is None else int(on)))
 
     def fv_fused(self):
+        """The setting: 1, 0 or -1 (automatic)."""
         on = ctypes.c_int()
         _check(lib().lb_get_fv_fused(self.h, ctypes.byref(on)))
-        return bool(on.value)
+        return on.value
 
     def rebase(self):
         _check(lib().lb_rebase(self.h))

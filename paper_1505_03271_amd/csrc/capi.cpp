@@ -419,22 +419,30 @@ int fv_launch(lb_sim* s, const void* src, void* dst, void* aux, bool corrector) 
 }
 
 // ---- fused passes (x periodic, semi-implicit + Heun) ----
+// fused passes: semi-implicit + Heun, periodic x, FP32 arithmetic (not
+// FP64 storage), wide strips (not forced narrow)
+// The automatic setting uses them where they measured faster than separate
+// launches on MI355X: FP32 storage from 2048^2 cells with g (22-30%) and from
+// 4096^2 without (14%), split BF16 storage with g at 4096^2 (2%).  They lose
+// on smaller grids and on the other 16-bit formats, whose kernels are bound
+// by arithmetic more than by traffic.
+bool fused_pays(const lb_sim* s) {
+    const int64_t cells = s->plane;
+    switch (s->p.storage) {
+        case LB_F32: return cells >= (s->p.thermal ? (int64_t(3) << 20) : (int64_t(12) << 20));
+        case LB_BF16S: return s->p.thermal && cells >= (int64_t(12) << 20);
+        default: return false;
+    }
+}
 bool fused_eligible(const lb_sim* s) {
-    return s->p.scheme == LB_FV_HEUN && s->p.bc_x == LB_PERIODIC && s->fused;
+    return s->p.scheme == LB_FV_HEUN && s->p.bc_x == LB_PERIODIC && s->p.storage != LB_F64 &&
+           s->lanes != FV_NARROW && (s->fused > 0 || (s->fused < 0 && fused_pays(s)));
 }
-bool narrow_fused(const lb_sim* s) {
-    if (s->lanes) return s->lanes == FV_NARROW;
-    const int64_t nx = s->p.nx, hw = 2 * FV_FUSED_HALO;
-    const int64_t wide = FV_LANES * ((nx + FV_LANES - hw - 1) / (FV_LANES - hw));
-    const int64_t narrow = FV_NARROW * ((nx + FV_NARROW - hw - 1) / (FV_NARROW - hw));
-    return narrow * 104 < wide * 100;
-}
-int strip_width_fused(const lb_sim* s) { return (narrow_fused(s) ? FV_NARROW : FV_LANES) - 2 * FV_FUSED_HALO; }
+int strip_width_fused(const lb_sim*) { return FV_LANES - 2 * FV_FUSED_HALO; }
 int auto_chunk_fused(const lb_sim* s) {
     const int n_strips = (s->p.nx + strip_width_fused(s) - 1) / strip_width_fused(s);
     int cap = fv_fused_resident_blocks(s->p.storage, s->p.thermal);
     if (cap <= 0) cap = 256;
-    if (narrow_fused(s)) cap *= 4;
     const int chunks = std::max(1, cap / n_strips);
     int h = (s->p.ny + chunks - 1) / chunks;
     h = ((h + 3) / 4) * 4;
@@ -465,8 +473,11 @@ int ensure_fused_states(lb_sim* s, bool capturing, bool* ok) {
 template <class R>
 FvArgs<R> fv_args_fused(const lb_sim* s, const void* star, const void* cur, void* next, void* star2) {
     FvArgs<R> a = fv_args<R>(s, star, next, const_cast<void*>(cur), true);   // the corrector's weights (dt/2)
+    const FvArgs<R> p = fv_args<R>(s, cur, star2, nullptr, false);
+    a.xcoef2 = p.xcoef;                                                       // and the predictor's (dt)
+    a.ycoef2 = p.ycoef;
     a.dst2 = star2;
-    a.narrow = narrow_fused(s) ? 1 : 0;
+    a.narrow = 0;
     a.strip_w = strip_width_fused(s);
     a.chunk_h = s->chunk_f;
     a.n_strips = (s->p.nx + a.strip_w - 1) / a.strip_w;
@@ -855,9 +866,7 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->p = *p;
         if (s->p.scheme == LB_ST) s->p.dt = 1.0;
         s->nsp = p->thermal ? 2 : 1;
-        // separate predictor and corrector launches by default: the fused
-        // pass gains 3% only on large FP32 grids and loses elsewhere
-        s->fused = 0;
+        s->fused = -1;   // fused passes where they pay (fused_pays)
 
         s->plane = int64_t(p->nx) * p->ny;
         s->state_bytes = size_t(state_size(p->storage, p->thermal != 0, uint64_t(s->plane)));
@@ -1319,10 +1328,10 @@ int lb_get_fv_fused(const lb_sim* s, int* on) {
 
 int lb_set_fv_fused(lb_sim* s, int on) {
     if (int rc = check_free(s, "lb_set_fv_fused")) return rc;
-    if (on != 0 && on != 1) return fail(LB_EINVAL, "lb_set_fv_fused: on must be 0 or 1");
+    if (on < -1 || on > 1) return fail(LB_EINVAL, "lb_set_fv_fused: on must be -1, 0 or 1");
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->fused = on;
-    if (!on) {   // release the second pair of states
+    if (!fused_eligible(s)) {   // release the second pair of states
         if (s->A2) (void)hipFree(s->A2);
         if (s->B2) (void)hipFree(s->B2);
         s->A2 = s->B2 = nullptr;

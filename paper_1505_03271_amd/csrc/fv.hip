@@ -78,6 +78,7 @@ __device__ inline Buf make_buf(const void* p, uint32_t bytes) {
 // populations a = 1..4 or a = 5..8 of a species at one cell, contiguous; the
 // rest plane holds a = 0 of every species.  Loads return offsets in R.
 typedef __attribute__((ext_vector_type(2))) unsigned u32x2;
+typedef __attribute__((ext_vector_type(3))) unsigned u32x3;
 typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
 
 __device__ inline double as_f64(unsigned lo, unsigned hi) {
@@ -85,6 +86,19 @@ __device__ inline double as_f64(unsigned lo, unsigned hi) {
 }
 __device__ inline unsigned f64_lo(double d) { return unsigned(__builtin_bit_cast(uint64_t, d)); }
 __device__ inline unsigned f64_hi(double d) { return unsigned(__builtin_bit_cast(uint64_t, d) >> 32); }
+
+// Stores wider than 64 bits take their whole byte offset in the VGPR operand
+// and none in the SGPR one.  With an SGPR offset, a store of four dwords has
+// been seen to take lanes 12..15 of every 16 of its first data register from
+// the instruction after it, which overwrote that register (the compiler
+// keeps a wait state between such a store and a write of its data only when
+// the SGPR offset field is unused).  The extra VALU add per store is free.
+__device__ inline void store_x4(Buf b, u32x4 x, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v + s, 0u, 0);
+}
+__device__ inline void store_x3(Buf b, u32x3 x, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b96(x, b.r, v + s, 0u, 0);
+}
 
 template <class S> struct Io;
 template <> struct Io<double> {
@@ -98,8 +112,8 @@ template <> struct Io<double> {
     }
     template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         const double a0 = d[0], a1 = d[1], a2 = d[2], a3 = d[3];
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, b.r, v + 16, s, 0);
+        store_x4(b, u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, v, s);
+        store_x4(b, u32x4{f64_lo(a2), f64_hi(a2), f64_lo(a3), f64_hi(a3)}, v + 16, s);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -115,7 +129,7 @@ template <> struct Io<double> {
         const double a0 = d[0];
         if (N == 2) {
             const double a1 = d[1];
-            __builtin_amdgcn_raw_buffer_store_b128(u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, b.r, v, s, 0);
+            store_x4(b, u32x4{f64_lo(a0), f64_hi(a0), f64_lo(a1), f64_hi(a1)}, v, s);
         } else {
             __builtin_amdgcn_raw_buffer_store_b64(u32x2{f64_lo(a0), f64_hi(a0)}, b.r, v, s, 0);
         }
@@ -130,7 +144,7 @@ template <> struct Io<float> {
     template <class R> __device__ static void st4(Buf b, uint32_t v, uint32_t s, const R* d) {
         u32x4 x{__float_as_uint(float(d[0])), __float_as_uint(float(d[1])), __float_as_uint(float(d[2])),
                 __float_as_uint(float(d[3]))};
-        __builtin_amdgcn_raw_buffer_store_b128(x, b.r, v, s, 0);
+        store_x4(b, x, v, s);
     }
     template <class R, int N> __device__ static void ldr(Buf b, uint32_t v, uint32_t s, R* d) {
         if (N == 2) {
@@ -313,7 +327,6 @@ __device__ inline void stage(const R* df, const R* dg, const StageK<R>& k, const
 template <class S> struct Narrow;
 template <> struct Narrow<bf16s_t> : Io16<true> {};
 template <> struct Narrow<f16s_t> : Io16<false> {};
-typedef __attribute__((ext_vector_type(3))) unsigned u32x3;
 
 // A split record as loaded: the words stay packed (11 or 6 registers) until
 // decode_split, which is placed where the values are used, so the wait for
@@ -533,12 +546,12 @@ __device__ inline void store_split_raw(Buf b, uint32_t cell, uint32_t G, const S
     const uint32_t v12 = cell * 12u;
     if (TH) {
         const uint32_t v16 = cell * 16u;
-        __builtin_amdgcn_raw_buffer_store_b128(w.m, b.r, v16, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(w.p, b.r, v16, 2 * G, 0);
-        __builtin_amdgcn_raw_buffer_store_b96(w.t, b.r, v12, 4 * G, 0);
+        store_x4(b, w.m, v16, 0u);
+        store_x4(b, w.p, v16, 2 * G);
+        store_x3(b, w.t, v12, 4 * G);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b96(u32x3{w.m[0], w.m[1], w.m[2]}, b.r, v12, 0u, 0);
-        __builtin_amdgcn_raw_buffer_store_b96(u32x3{w.p[0], w.p[1], w.p[2]}, b.r, v12, G + G / 2, 0);
+        store_x3(b, u32x3{w.m[0], w.m[1], w.m[2]}, v12, 0u);
+        store_x3(b, u32x3{w.p[0], w.p[1], w.p[2]}, v12, G + G / 2);
     }
 }
 
@@ -584,21 +597,42 @@ __device__ inline int xcd_item(int b, int n_items) {
     return (b % 8) * per_xcd + b / 8;
 }
 
+// Roles of fv_item: a stage launch of its own (the predictor, a single-pass
+// scheme, or the corrector), or one half of a fused pass, which runs the
+// corrector of a step and the predictor of the next side by side in one
+// block (see fv_fused).
+enum { FV_ALONE = 0, FV_FIRST = 1, FV_SECOND = 2 };
+constexpr int FV_RING = 5;   // rows of f~n+1 handed from the first half to the second (LDS)
+
+// Words of one cell's record in the hand-over ring: the split record as
+// stored, or the offsets as read back from storage (FP32).
+template <class S, bool TH> constexpr int ring_words() {
+    return is_split<S>::value ? (TH ? 11 : 6) : (TH ? 18 : 9);
+}
+
 // One FV stage over work item `item` (strip item % n_strips, chunk
 // item / n_strips) of the simulation described by A, on W lanes (lane t;
-// lds: this item's exchange rows).
-template <class R, class S, bool TH, bool CORR, int W>
+// lds: this item's exchange rows).  In a fused pass (MODE != FV_ALONE) the
+// strips carry a halo of four columns; the first half forms f~n+1 on the
+// rows and columns the second half's stencils reach, stores its own cells
+// and hands every formed row to the second half through `ring`; the second
+// half reads its input rows there, `lag` steps of the march after they were
+// formed, and both halves meet at two barriers per step of the march.
+template <class R, class S, bool TH, bool CORR, int W, int MODE = FV_ALONE>
 __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, const int t,
-                                        R (*lds)[6 * (TH ? 2 : 1)][W]) {
+                                        R (*lds)[6 * (TH ? 2 : 1)][W], uint32_t* ring = nullptr) {
+    static_assert(MODE == FV_ALONE || (W == FV_LANES && (MODE == FV_FIRST) == CORR && sizeof(R) == 4),
+                  "fused halves: wide items, FP32 arithmetic, the corrector first");
     constexpr int NSP = TH ? 2 : 1;
+    constexpr int HW = MODE == FV_ALONE ? FV_HALO : FV_FUSED_HALO;
     const int strip = item % A.n_strips, chunk = item / A.n_strips;
     const int x0 = strip * A.strip_w;
     const int own = min(A.strip_w, A.nx - x0);
-    const int lanes = own + 2 * FV_HALO;
+    const int lanes = own + 2 * HW;
     if ((t & ~63) >= lanes) return;  // a wave without columns of this strip leaves (barriers count live waves)
 
     // ---- this lane's column (ghost columns mirror or wrap) ----
-    const int xg = x0 - FV_HALO + t;
+    const int xg = x0 - HW + t;
     int col = xg;
     bool mx = false;   // ghost column of a no-slip wall
     bool dxg = false;  // ghost column of a fixed-density boundary (density rho_S on its face)
@@ -611,22 +645,35 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         else col = xg - A.nx;
     }
     if (t >= lanes) { col = 0; mx = false; dxg = false; }  // idle lane of a live wave
-    const bool owned = t >= FV_HALO && t < FV_HALO + own;
+    const bool owned = t >= HW && t < HW + own;
+    // cells whose new values are formed: the owned ones, and in the first
+    // half of a fused pass every lane whose stencil lies in the strip
+    const bool formed = MODE == FV_FIRST ? (t >= 2 && t < lanes - 2) : owned;
 
     R xc[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xc[q] = owned ? A.xcoef[col * 8 + q] : R(0);
+    for (int q = 0; q < 8; ++q) xc[q] = formed ? A.xcoef[col * 8 + q] : R(0);
 
     const uint32_t gb = A.group_bytes, ro = A.rest_off;
     const uint32_t nxu = uint32_t(A.nx), colu = uint32_t(col);
     const Buf bsrc = make_buf(A.src, A.state_bytes);
-    const Buf bdst = make_buf(A.dst, A.state_bytes);
+    const Buf bdst = make_buf(MODE == FV_SECOND ? A.dst2 : A.dst, A.state_bytes);
     const Buf baux = make_buf(A.aux, A.state_bytes);
 
     const int y0 = chunk * A.chunk_h;
     const int y1 = min(y0 + A.chunk_h, A.ny);
     const StageK<R> k = A.k;
     typedef const __attribute__((address_space(4))) R CR;
+    // rows formed by the first half of a fused pass (those the second
+    // half's stencils reach; at a y wall only the rows inside)
+    const int f_lo = A.wall_y ? max(y0 - 2, 0) : y0 - 2;
+    const int f_hi = A.wall_y ? min(y1 + 2, A.ny) : y1 + 2;
+    // the fused halves' hand-over ring, [FV_RING][ring_words][W] words
+    constexpr int RW = ring_words<S, TH>();
+    auto ring_at = [&](const int row, const int w) __attribute__((always_inline)) -> uint32_t& {
+        const int slot = (row - (y0 - 2) + 4 * FV_RING) % FV_RING;
+        return ring[(slot * RW + w) * W + t];
+    };
 
     // rings: phi of c_y=+1 and c_y=-1 populations of the last four rows,
     // partial updates (all but the y flux) of the last two rows
@@ -677,6 +724,12 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     auto load_any = [&](const Buf& b, uint32_t cell, R* f, R* g) __attribute__((always_inline)) {
         if constexpr (!SPLIT) load_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
+    // row of the corrector's own-cell input (f~n): rows outside the grid are
+    // wrapped in a fused pass (whose first half forms them) and clamped
+    // otherwise (their results are not used)
+    auto own_row = [&](const int r) __attribute__((always_inline)) {
+        return MODE == FV_FIRST ? map_row(r) : min(max(r, 0), A.ny - 1);
+    };
     auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
         const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
@@ -684,8 +737,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             load_split_raw<S, TH>(bsrc, cell, gb, PR[Q]);
         } else {
             load_any(bsrc, cell, PF[Q], PG[Q]);
-            if (CORR && AHEAD_OWN && owned)  // the corrector's own-cell input (f~n)
-                load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PH[Q], PHG[Q]);
+            if (CORR && AHEAD_OWN && formed)  // the corrector's own-cell input (f~n)
+                load_any(baux, uint32_t(own_row(r)) * nxu + colu, PH[Q], PHG[Q]);
         }
     };
     // The corrector's own-cell record of the next row is requested after the
@@ -694,7 +747,36 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     auto prefetch_own = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
         if constexpr (SPLIT)
-            if (CORR) load_split_raw<S, TH>(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, gb, AR[Q]);
+            if (CORR) load_split_raw<S, TH>(baux, uint32_t(own_row(r)) * nxu + colu, gb, AR[Q]);
+    };
+    // The second half of a fused pass reads its input row from the ring, at
+    // the row where it is used (the row after it may still be in the making).
+    // A ghost row at a y wall reads its mirror row.
+    auto ring_read = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+        constexpr int Q = decltype(slot_tag)::value & 1;
+        const int src = (A.wall_y && (r < 0 || r >= A.ny)) ? map_row(r) : r;
+        if constexpr (SPLIT) {
+            SplitRaw<TH> w;
+            if (TH) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w.m[q] = ring_at(src, q);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w.p[q] = ring_at(src, 4 + q);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) w.t[q] = ring_at(src, 8 + q);
+            } else {
+                w.m = u32x4{ring_at(src, 0), ring_at(src, 1), ring_at(src, 2), 0u};
+                w.p = u32x4{ring_at(src, 3), ring_at(src, 4), ring_at(src, 5), 0u};
+                w.t = u32x3{0u, 0u, 0u};
+            }
+            PR[Q] = w;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                PF[Q][a] = __uint_as_float(ring_at(src, a));
+                if (TH) PG[Q][a] = __uint_as_float(ring_at(src, 9 + a));
+            }
+        }
     };
     // store the offsets of a cell of a row whose thermal reference is trow,
     // and note whether the cell is finite (its moments; otherwise its rest
@@ -711,6 +793,41 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         }
         bad = bad || !__builtin_isfinite(chk);
     };
+    // first half of a fused pass: store an owned cell of an owned row, and
+    // hand the formed row's record (as stored) to the second half
+    auto store_hand = [&](const int j, const bool store, const R* f, const R* g, const R trow, const R qrow)
+                          __attribute__((always_inline)) {
+        const uint32_t cell = uint32_t(j) * nxu + colu;
+        if constexpr (SPLIT) {
+            SplitRaw<TH> w;
+            const R chk = encode_split<R, S, TH>(f, g, k, trow, qrow, w);
+            if (store) {
+                store_split_raw<TH>(bdst, cell, gb, w);
+                bad = bad || !__builtin_isfinite(chk);
+            }
+            // words: the moments (4, or 3 without g), the f residuals and,
+            // with g, its residuals, as in the stored record
+            constexpr int NM = TH ? 4 : 3;
+#pragma unroll
+            for (int q = 0; q < NM; ++q) ring_at(j, q) = w.m[q];
+#pragma unroll
+            for (int q = 0; q < (TH ? 4 : 3); ++q) ring_at(j, NM + q) = w.p[q];
+            if (TH) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) ring_at(j, 8 + q) = w.t[q];
+            }
+        } else {
+            if (store) {
+                store_cell<R, S, TH>(bdst, cell, gb, ro, f, g);
+                bad = bad || !__builtin_isfinite(TH ? f[0] + g[0] : f[0]);
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                ring_at(j, a) = __float_as_uint(float(stored_value<S>(f[a])));
+                if (TH) ring_at(j, 9 + a) = __float_as_uint(float(stored_value<S>(g[a])));
+            }
+        }
+    };
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
@@ -722,7 +839,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         // wall temperature for the anti-reflection of the shifted brackets
         const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
 
-        if (!AHEAD) prefetch(r, Slot<SL>{});
+        if (MODE == FV_SECOND) ring_read(r, Slot<SL>{});
+        else if (!AHEAD) prefetch(r, Slot<SL>{});
         R df[9], dg[9], mm[4];
         if constexpr (SPLIT) {
             // While stores are outstanding the compiler waits for all vector
@@ -731,16 +849,16 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             // requested right after it.
             decode_split<R, S, TH>(PR[SL & 1], mm, df, dg);
             __builtin_amdgcn_sched_barrier(0);
-            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
+            if (AHEAD && MODE != FV_SECOND) prefetch(r + 1, Slot<SL + 1>{});
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 df[a] = PF[SL & 1][a];
                 if (TH) dg[a] = PG[SL & 1][a];
             }
-            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
-            if (CORR && !AHEAD_OWN && owned)  // own-cell input of this row, used after the stage
-                load_any(baux, uint32_t(min(max(r, 0), A.ny - 1)) * nxu + colu, PH[SL & 1], PHG[SL & 1]);
+            if (AHEAD && MODE != FV_SECOND) prefetch(r + 1, Slot<SL + 1>{});
+            if (CORR && !AHEAD_OWN && formed)  // own-cell input of this row, used after the stage
+                load_any(baux, uint32_t(own_row(r)) * nxu + colu, PH[SL & 1], PHG[SL & 1]);
         }
 
         R ph[NSP][9], bs[NSP][9];
@@ -801,7 +919,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         // space) in uniform control flow, so no vector-memory wait is needed
         R yc[8];
         {
-            const CR* yw = (const CR*)(A.ycoef) + int64_t(min(max(j, 0), A.ny - 1)) * 8;
+            const CR* yw = (const CR*)(A.ycoef) + int64_t(map_row(j)) * 8;   // (a periodic row wraps)
 #pragma unroll
             for (int q = 0; q < 8; ++q) yc[q] = yw[q];
         }
@@ -816,7 +934,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             sU = yc[0] * (TRg[SL] - tj) + yc[1] * (TRg[(SL + 1) & 3] - tj) + yc[3] * (TRg[(SL + 3) & 3] - tj);
             sD = yc[4] * (TRg[(SL + 1) & 3] - tj) + yc[6] * (TRg[(SL + 3) & 3] - tj) + yc[7] * (Tr - tj);
         }
-        if (owned && j >= y0 && j < y1) {
+        if (MODE == FV_FIRST ? (formed && j >= f_lo && j < f_hi) : (owned && j >= y0 && j < y1)) {
             R out[NSP][9];
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
@@ -836,7 +954,10 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                     }
                 }
             }
-            store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
+            if (MODE == FV_FIRST)
+                store_hand(j, owned && j >= y0 && j < y1, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
+            else
+                store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
         }
 
         // ---- x flux and partial update (all but the y flux) of row r ----
@@ -851,7 +972,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             prefetch_own(r + 1, Slot<SL + 1>{});
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (owned) {
+        if (formed) {
             R base[NSP][9];
             if (CORR) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
@@ -902,454 +1023,74 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 UP[SL][s][p] = ph[s][upop(p)];
                 DN[SL][s][p] = ph[s][dpop(p)];
             }
+        // fused halves: the hand-over of this step is complete for both
+        if (MODE != FV_ALONE) lanes_sync<W>();
     };
 
     // Rows y0-2 .. y1+1 in trips of four; the trip may run up to three rows
     // past y1+1 (their results are never stored).  A chunk of height 4k
-    // needs exactly k+1 trips.
-    if (AHEAD) prefetch(y0 - 2, Slot<0>{});
-    if (AHEAD) prefetch_own(y0 - 2, Slot<0>{});
-    for (int r = y0 - 2; r <= y1 + 1; r += 4) {
+    // needs exactly k+1 trips.  The first half of a fused pass marches two
+    // rows further each way (rows y0-4 .. y1+3 of f~*).  The second half
+    // starts when the first has formed row y0-2 and `lag` - 1 rows after it
+    // (at a bottom wall: rows 0 and 1, whose images are its first two
+    // rows), and both halves end on the same count of barriers.
+    const int r0 = MODE == FV_FIRST ? y0 - 4 : y0 - 2;
+    const int r1 = MODE == FV_FIRST ? y1 + 3 : y1 + 1;
+    const int lag = (A.wall_y && y0 < 2) ? 4 : 1;
+    const int steps1 = ((y1 + 3) - (y0 - 4) + 4) / 4 * 4;      // march steps of the first half
+    const int steps2 = ((y1 + 1) - (y0 - 2) + 4) / 4 * 4;      // of the second
+    const int before = MODE == FV_SECOND ? 4 + lag : 0;         // idle steps before the march
+    const int total = max(steps1, 4 + lag + steps2);
+    for (int q = 0; q < before; ++q) {
+        lanes_sync<W>();
+        lanes_sync<W>();
+    }
+    if (AHEAD && MODE != FV_SECOND) prefetch(r0, Slot<0>{});
+    if (AHEAD) prefetch_own(r0, Slot<0>{});
+    for (int r = r0; r <= r1; r += 4) {
         row_step(r, Slot<0>{});
         row_step(r + 1, Slot<1>{});
         row_step(r + 2, Slot<2>{});
         row_step(r + 3, Slot<3>{});
+    }
+    if (MODE != FV_ALONE) {
+        for (int q = before + (MODE == FV_FIRST ? steps1 : steps2); q < total; ++q) {
+            lanes_sync<W>();
+            lanes_sync<W>();
+        }
     }
     if (A.bad) raise_flag(A.bad, bad);
 }
 
 // ---- fused pass: the corrector of step n and the predictor of step n+1 ----
-// One march over a chunk forms, row by row,
-//   f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi(f~*))      (eq:semi-heun, step n)
-//   f~*'  = f~n+1 + C(f~n+1) - dt D(phi(f~n+1))            (eq:semi, step n+1)
-// reading f~* with a halo of four cells (the second stage needs f~n+1 two
-// cells beyond the strip, and f~n+1 there needs phi(f~*) two cells further)
-// and f~n where f~n+1 is formed, and writing f~n+1 and f~*'.  The second
-// stage starts from f~n+1 as it is stored (rounded to the storage format,
-// the split record encoded and decoded in registers), so the pass gives
-// the bits of a corrector launch followed by a predictor launch.  The
-// second stage's weights are the first stage's doubled (dt against dt/2; a
-// power-of-two scaling, so every rounding is the same).
-//
-// Rows: when row r of f~* arrives the first stage finishes row j1 = r - 2
-// and the second stage row j1 - 2.  Each stage keeps its own y rings and
-// partial updates; both exchange x neighbours through LDS (one buffer per
-// stage, a barrier after each write).  At a y wall the first stage's ghost
-// rows come from the stored f~* of the mirror rows (as in fv_item); the
-// second stage's ghost rows are the wall images of its rows 0, 1 (ny - 1,
-// ny - 2), put into its ring when those rows are formed.  x is periodic
-// (with x walls the host uses separate launches).
-template <class R, class S, bool TH, int W>
-__device__ __forceinline__ void fv_item_fused(const FvArgs<R>& A, const int item, const int t,
-                                              R (*lds1)[W], R (*lds2)[W]) {
-    constexpr int NSP = TH ? 2 : 1;
-    constexpr int HF = FV_FUSED_HALO;
-    const int strip = item % A.n_strips, chunk = item / A.n_strips;
-    const int x0 = strip * A.strip_w;
-    const int own = min(A.strip_w, A.nx - x0);
-    const int lanes = own + 2 * HF;
-    if ((t & ~63) >= lanes) return;  // a wave without columns of this strip leaves
-
-    int col = x0 - HF + t;
-    if (col < 0) col += A.nx;
-    else if (col >= A.nx) col -= A.nx;
-    if (t >= lanes) col = 0;                          // idle lane of a live wave
-    const bool owned = t >= HF && t < HF + own;       // f~*' formed and stored, f~n+1 stored
-    const bool formed = t >= 2 && t < lanes - 2;      // f~n+1 formed
-
-    R xc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xc[q] = formed ? A.xcoef[col * 8 + q] : R(0);
-
-    const uint32_t gb = A.group_bytes, ro = A.rest_off;
-    const uint32_t nxu = uint32_t(A.nx), colu = uint32_t(col);
-    const Buf bstar = make_buf(A.src, A.state_bytes);    // f~*
-    const Buf bn = make_buf(A.aux, A.state_bytes);       // f~n
-    const Buf bnext = make_buf(A.dst, A.state_bytes);    // f~n+1
-    const Buf bstar2 = make_buf(A.dst2, A.state_bytes);  // f~*'
-
-    const int y0 = chunk * A.chunk_h;
-    const int y1 = min(y0 + A.chunk_h, A.ny);
-    const StageK<R> k = A.k;
-    typedef const __attribute__((address_space(4))) R CR;
-    constexpr bool SPLIT = is_split<S>::value;
-    constexpr bool AHEAD = sizeof(R) == 4;
-    constexpr bool AHEAD_OWN = AHEAD && sizeof(S) == 2 && !SPLIT;
-
-    // first stage: phi(f~*) rings and partial updates; second stage: phi(f~n+1)
-    R UP1[4][NSP][3], DN1[4][NSP][3], U1[2][NSP][9];
-    R UP2[4][NSP][3], DN2[4][NSP][3], U2[2][NSP][9];
-    R TR1[4] = {0, 0, 0, 0}, TR2[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) UP1[q][s][p] = DN1[q][s][p] = UP2[q][s][p] = DN2[q][s][p] = R(0);
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int a = 0; a < 9; ++a) U1[q][s][a] = U2[q][s][a] = R(0);
-
-    auto map_row = [&](const int r) __attribute__((always_inline)) {
-        int row = r;
-        if (r < 0) row = A.wall_y ? -r - 1 : r + A.ny;
-        else if (r >= A.ny) row = A.wall_y ? 2 * A.ny - 1 - r : r - A.ny;
-        return min(max(row, 0), A.ny - 1);
-    };
-    auto row_tref = [&](const int r) __attribute__((always_inline)) {
-        return (TH && A.tref) ? R(((const CR*)A.tref)[map_row(r)]) : k.ref_g;
-    };
-    auto row_qref = [&](const int r) __attribute__((always_inline)) {
-        return (SPLIT && TH && A.qref) ? R(((const CR*)A.qref)[map_row(r)]) : R(0);
-    };
-
-    R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
-    SplitRaw<TH> PR[2], AR[2];
-    auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
-        constexpr int Q = decltype(slot_tag)::value & 1;
-        const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
-        if constexpr (SPLIT) {
-            load_split_raw<S, TH>(bstar, cell, gb, PR[Q]);
-        } else {
-            load_cell<R, S, TH>(bstar, cell, gb, ro, PF[Q], PG[Q]);
-            if (AHEAD_OWN) load_cell<R, S, TH>(bn, cell, gb, ro, PH[Q], PHG[Q]);
-        }
-    };
-    auto prefetch_own = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
-        constexpr int Q = decltype(slot_tag)::value & 1;
-        if constexpr (SPLIT) load_split_raw<S, TH>(bn, uint32_t(map_row(r)) * nxu + colu, gb, AR[Q]);
-    };
-
-    bool bad = false;
-    // y flux of one stage for a row whose weights are yc: rings UP, DN hold
-    // rows j-2 .. j+1 in slots SL .. SL+3, the current row is ph (j+2)
-    auto yflux = [&](auto& out, const auto& UP, const auto& DN, const auto& ph, const R* yc, const R* TRr,
-                     const R trow, auto slot_tag) __attribute__((always_inline)) {
-        constexpr int SL = decltype(slot_tag)::value;
-        R sU = 0, sD = 0;
-        if (TH && A.tref) {
-            const R tj = TRr[(SL + 2) & 3];
-            sU = yc[0] * (TRr[SL] - tj) + yc[1] * (TRr[(SL + 1) & 3] - tj) + yc[3] * (TRr[(SL + 3) & 3] - tj);
-            sD = yc[4] * (TRr[(SL + 1) & 3] - tj) + yc[6] * (TRr[(SL + 3) & 3] - tj) + yc[7] * (trow - tj);
-        }
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                out[s][upop(p)] -= yc[0] * UP[SL][s][p] + yc[1] * UP[(SL + 1) & 3][s][p] +
-                                   yc[2] * UP[(SL + 2) & 3][s][p] + yc[3] * UP[(SL + 3) & 3][s][p];
-                out[s][dpop(p)] -= yc[4] * DN[(SL + 1) & 3][s][p] + yc[5] * DN[(SL + 2) & 3][s][p] +
-                                   yc[6] * DN[(SL + 3) & 3][s][p] + yc[7] * ph[s][dpop(p)];
-                if (TH && s == NSP - 1) {
-                    out[s][upop(p)] -= wt<R>(upop(p)) * sU;
-                    out[s][dpop(p)] -= wt<R>(dpop(p)) * sD;
-                }
-            }
-    };
-    auto ylw = [&](const int j, R* yc) __attribute__((always_inline)) {   // (a periodic row wraps)
-        const CR* yw = (const CR*)(A.ycoef) + int64_t(map_row(j)) * 8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) yc[q] = yw[q];
-    };
-    // the brackets of a wall's ghost row from those of its mirror row
-    // (double reflection of f; isothermal anti-reflection of g, with the
-    // ghost row shifted by the mirror's thermal reference trow)
-    auto ghost_up = [&](const auto& DNm, const int s, const int p, const R Tw) __attribute__((always_inline)) {
-        return (TH && s == NSP - 1) ? R(2) * wt<R>(upop(p)) * Tw - DNm[s][p] : DNm[s][p];
-    };
-    auto ghost_dn = [&](const auto& UPm, const int s, const int p, const R Tw) __attribute__((always_inline)) {
-        return (TH && s == NSP - 1) ? R(2) * wt<R>(dpop(p)) * Tw - UPm[s][p] : UPm[s][p];
-    };
-
-    auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
-        constexpr int SL = decltype(slot_tag)::value;
-        const int j1 = r - 2, j2 = r - 4;
-        // ================= first stage: phi(f~*) of row r =================
-        const bool my = A.wall_y && (r < 0 || r >= A.ny);
-        const R Tr = row_tref(r), Qr = row_qref(r);
-        const R Tw = (r < 0 ? A.Tb : A.Tt) - Tr;
-        if (!AHEAD) prefetch(r, Slot<SL>{});
-        R df[9], dg[9], mm[4];
-        if constexpr (SPLIT) {
-            decode_split<R, S, TH>(PR[SL & 1], mm, df, dg);
-            __builtin_amdgcn_sched_barrier(0);
-            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                df[a] = PF[SL & 1][a];
-                if (TH) dg[a] = PG[SL & 1][a];
-            }
-            if (AHEAD) prefetch(r + 1, Slot<SL + 1>{});
-            if (!AHEAD_OWN)
-                load_cell<R, S, TH>(bn, uint32_t(map_row(r)) * nxu + colu, gb, ro, PH[SL & 1], PHG[SL & 1]);
-        }
-        R ph[NSP][9], bs[NSP][9];
-        if constexpr (SPLIT) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, Qr, ph, bs);
-        else stage<R, TH, false>(df, dg, k, Tr, ph, bs);
-        {
-            R tmp[NSP][9];
-#pragma unroll
-            for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                for (int a = 1; a < 9; ++a) tmp[s][a] = ph[s][a];
-#pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                ph[0][a] = my ? tmp[0][opp(a)] : tmp[0][a];
-                if (TH) ph[NSP - 1][a] = my ? R(2) * wt<R>(a) * Tw - tmp[NSP - 1][opp(a)] : tmp[NSP - 1][a];
-            }
-        }
-        // ---- first stage: finish row j1 (f~n+1) ----
-        R yc1[8];
-        ylw(j1, yc1);
-        R fn[NSP][9];
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int a = 0; a < 9; ++a) fn[s][a] = U1[SL & 1][s][a];
-        yflux(fn, UP1, DN1, ph, yc1, TR1, Tr, Slot<SL>{});
-        const R Tr1 = TR1[(SL + 2) & 3];   // thermal reference of row j1
-        const R Qr1 = row_qref(j1);
-        // ---- x exchange of phi(f~*), partial update of row r ----
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 6; ++p) lds1[s * 6 + p][t] = ph[s][xpop(p)];
-        lanes_sync<W>();
-        if (SPLIT && AHEAD) {
-            __builtin_amdgcn_sched_barrier(0);
-            prefetch_own(r + 1, Slot<SL + 1>{});
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (formed) {
-            R phn[NSP][9], bsn[NSP][9], base[NSP][9];
-            if constexpr (SPLIT) {
-                R hm[4], hf[9], hg[9];
-                decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
-                stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, Qr, phn, bsn);
-            } else {
-                stage<R, TH, true>(PH[SL & 1], PHG[SL & 1], k, Tr, phn, bsn);
-            }
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                base[0][a] = R(0.5) * (bsn[0][a] + df[a]);
-                if (TH) base[NSP - 1][a] = R(0.5) * (bsn[NSP - 1][a] + dg[a]);
-            }
-#pragma unroll
-            for (int s = 0; s < NSP; ++s) {
-#pragma unroll
-                for (int p = 0; p < 6; ++p) {
-                    const int a = xpop(p);
-                    const R* L = lds1[s * 6 + p];
-                    const R v = ph[s][a];
-                    R d;
-                    if (cx(a) > 0) d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
-                    else d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
-                    base[s][a] -= d;
-                }
-#pragma unroll
-                for (int a = 0; a < 9; ++a) U1[SL & 1][s][a] = base[s][a];
-            }
-        }
-        TR1[SL] = Tr;
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                UP1[SL][s][p] = ph[s][upop(p)];
-                DN1[SL][s][p] = ph[s][dpop(p)];
-            }
-
-        // ====== f~n+1 of row j1: stored, then the second stage's input ======
-        const bool in1 = j1 >= y0 && j1 < y1;
-        R dn[NSP][9];   // f~n+1 as stored (offsets)
-        if constexpr (SPLIT) {
-            SplitRaw<TH> w;
-            const R chk = encode_split<R, S, TH>(fn[0], fn[NSP - 1], k, Tr1, Qr1, w);
-            if (owned && in1) {
-                store_split_raw<TH>(bnext, uint32_t(j1) * nxu + colu, gb, w);
-                bad = bad || !__builtin_isfinite(chk);
-            }
-            R m2[4];
-            decode_split<R, S, TH>(w, m2, dn[0], dn[NSP - 1]);
-            stage_split<R, TH, true, false>(m2, dn[0], dn[NSP - 1], k, Tr1, Qr1, ph, bs);
-        } else {
-            if (owned && in1) {
-                store_cell<R, S, TH>(bnext, uint32_t(j1) * nxu + colu, gb, ro, fn[0], fn[NSP - 1]);
-                bad = bad || !__builtin_isfinite(TH ? fn[0][0] + fn[NSP - 1][0] : fn[0][0]);
-            }
-#pragma unroll
-            for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                for (int a = 0; a < 9; ++a) dn[s][a] = stored_value<S>(fn[s][a]);
-            stage<R, TH, true>(dn[0], dn[NSP - 1], k, Tr1, ph, bs);
-        }
-        // ---- second stage's ghost rows at the y walls ----
-        R Tr2 = Tr1;
-        if (A.wall_y) {
-            if (j1 == 0) {          // row -1 is the image of row 0
-                const R Twb = A.Tb - Tr1;
-                R cu[NSP][3], cd[NSP][3];
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) { cu[s][p] = ph[s][upop(p)]; cd[s][p] = ph[s][dpop(p)]; }
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        UP2[(SL + 3) & 3][s][p] = ghost_up(cd, s, p, Twb);
-                        DN2[(SL + 3) & 3][s][p] = ghost_dn(cu, s, p, Twb);
-                    }
-                TR2[(SL + 3) & 3] = Tr1;
-            } else if (j1 == 1) {   // row -2 is the image of row 1
-                const R Twb = A.Tb - Tr1;
-                R cu[NSP][3], cd[NSP][3];
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) { cu[s][p] = ph[s][upop(p)]; cd[s][p] = ph[s][dpop(p)]; }
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        UP2[(SL + 1) & 3][s][p] = ghost_up(cd, s, p, Twb);
-                        DN2[(SL + 1) & 3][s][p] = ghost_dn(cu, s, p, Twb);
-                    }
-                TR2[(SL + 1) & 3] = Tr1;
-            } else if (j1 == A.ny || j1 == A.ny + 1) {
-                // rows ny, ny + 1 are the images of rows ny - 1 (slot SL+3)
-                // and ny - 2 (slot SL+1)
-                const bool first = j1 == A.ny;
-                const R Trm = first ? TR2[(SL + 3) & 3] : TR2[(SL + 1) & 3];
-                const R Twt = A.Tt - Trm;
-                R mu[NSP][3], md[NSP][3];
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        mu[s][p] = first ? UP2[(SL + 3) & 3][s][p] : UP2[(SL + 1) & 3][s][p];
-                        md[s][p] = first ? DN2[(SL + 3) & 3][s][p] : DN2[(SL + 1) & 3][s][p];
-                    }
-#pragma unroll
-                for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        ph[s][upop(p)] = ghost_up(md, s, p, Twt);
-                        ph[s][dpop(p)] = ghost_dn(mu, s, p, Twt);
-                    }
-                Tr2 = Trm;
-            }
-        }
-        // ---- second stage: finish row j2 (f~*'), stored ----
-        {
-            R yc2[8];
-            ylw(j2, yc2);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) yc2[q] = R(2) * yc2[q];
-            R out[NSP][9];
-#pragma unroll
-            for (int s = 0; s < NSP; ++s)
-#pragma unroll
-                for (int a = 0; a < 9; ++a) out[s][a] = U2[SL & 1][s][a];
-            yflux(out, UP2, DN2, ph, yc2, TR2, Tr2, Slot<SL>{});
-            if (owned && j2 >= y0 && j2 < y1) {
-                const R trow = TR2[(SL + 2) & 3];
-                R chk;
-                if constexpr (SPLIT)
-                    chk = store_split<R, S, TH>(bstar2, uint32_t(j2) * nxu + colu, gb, out[0], out[NSP - 1], k, trow,
-                                                row_qref(j2));
-                else {
-                    store_cell<R, S, TH>(bstar2, uint32_t(j2) * nxu + colu, gb, ro, out[0], out[NSP - 1]);
-                    chk = TH ? out[0][0] + out[NSP - 1][0] : out[0][0];
-                }
-                bad = bad || !__builtin_isfinite(chk);
-            }
-        }
-        // ---- x exchange of phi(f~n+1), partial update of row j1 ----
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 6; ++p) lds2[s * 6 + p][t] = ph[s][xpop(p)];
-        lanes_sync<W>();
-        if (owned) {
-#pragma unroll
-            for (int s = 0; s < NSP; ++s) {
-#pragma unroll
-                for (int p = 0; p < 6; ++p) {
-                    const int a = xpop(p);
-                    const R* L = lds2[s * 6 + p];
-                    const R v = ph[s][a];
-                    R d;
-                    if (cx(a) > 0) d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
-                    else d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
-                    bs[s][a] -= R(2) * d;
-                }
-#pragma unroll
-                for (int a = 0; a < 9; ++a) U2[SL & 1][s][a] = bs[s][a];
-            }
-        }
-        TR2[SL] = Tr2;
-#pragma unroll
-        for (int s = 0; s < NSP; ++s)
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                UP2[SL][s][p] = ph[s][upop(p)];
-                DN2[SL][s][p] = ph[s][dpop(p)];
-            }
-    };
-
-    // rows y0-4 .. y1+3 of f~* in trips of four (a chunk of height 4k takes
-    // exactly k+2 trips; the last chunk may run up to three rows further,
-    // whose results are not stored)
-    if (AHEAD) prefetch(y0 - 4, Slot<0>{});
-    if (AHEAD) prefetch_own(y0 - 4, Slot<0>{});
-    for (int r = y0 - 4; r <= y1 + 3; r += 4) {
-        row_step(r, Slot<0>{});
-        row_step(r + 1, Slot<1>{});
-        row_step(r + 2, Slot<2>{});
-        row_step(r + 3, Slot<3>{});
-    }
-    if (A.bad) raise_flag(A.bad, bad);
-}
-
-// Fused pass over one block: one wide item or four narrow ones (as fv_block).
+// A block of 2 x FV_LANES lanes: the first FV_LANES run the corrector of step
+// n over a strip (eq:semi-heun), forming f~n+1 on the strip and two cells
+// beyond it (rows and columns) and storing the strip's cells; the others run
+// the predictor of step n+1 (eq:semi) over the same strip, reading the rows
+// of f~n+1 that the first half hands over through an LDS ring instead of
+// loading them, and store f~*.  Each half runs the code of the separate
+// launch (the same arithmetic in the same order), so the results are those
+// of a corrector launch followed by a predictor launch, bit for bit; a step
+// reads f~* and f~n and writes f~n+1 and the next f~*: four states instead
+// of five.  Each wave holds one stage's rings, so two waves (one of each
+// half) share a SIMD.  x is periodic (with x walls the host uses separate
+// launches); items are wide strips.
 template <class R, class S, bool TH>
-__device__ __forceinline__ void fv_block_fused(const FvArgs<R>& A, const int item, const bool narrow, R* lds_mem) {
+__global__ void __launch_bounds__(2 * FV_LANES, 1) fv_fused(FvArgs<R> A) {
     constexpr int NSP = TH ? 2 : 1;
-    if (narrow) {
-        R* mine = lds_mem + (threadIdx.x >> 6) * (2 * 6 * NSP * 64);
-        fv_item_fused<R, S, TH, 64>(A, item, threadIdx.x & 63, reinterpret_cast<R(*)[64]>(mine),
-                                    reinterpret_cast<R(*)[64]>(mine + 6 * NSP * 64));
+    __shared__ R x1[2][6 * NSP][FV_LANES], x2[2][6 * NSP][FV_LANES];
+    __shared__ uint32_t ring[FV_RING * ring_words<S, TH>() * FV_LANES];
+    const int b = xcd_item(blockIdx.x, A.n_items);
+    if (b >= A.n_items) return;
+    if (threadIdx.x < FV_LANES) {
+        fv_item<R, S, TH, true, FV_LANES, FV_FIRST>(A, b, threadIdx.x, x1, ring);
     } else {
-        fv_item_fused<R, S, TH, FV_LANES>(A, item, threadIdx.x, reinterpret_cast<R(*)[FV_LANES]>(lds_mem),
-                                          reinterpret_cast<R(*)[FV_LANES]>(lds_mem + 6 * NSP * FV_LANES));
+        FvArgs<R> P = A;   // the predictor's flux weights
+        P.xcoef = A.xcoef2;
+        P.ycoef = A.ycoef2;
+        fv_item<R, S, TH, false, FV_LANES, FV_SECOND>(P, b, threadIdx.x - FV_LANES, x2, ring);
     }
 }
-
-// Register budget of the fused pass: the thermal instances hold two sets of
-// rings for f and g (about 330 registers, one wave per SIMD); the others fit
-// two waves per SIMD.
-template <bool TH> constexpr int FV_FUSED_MIN_BLOCKS = TH ? 1 : 2;
-
-template <class R, class S, bool TH>
-__global__ void __launch_bounds__(FV_LANES, FV_FUSED_MIN_BLOCKS<TH>) fv_fused(FvArgs<R> A) {
-    __shared__ R lds_mem[2 * 6 * (TH ? 2 : 1) * FV_LANES];
-    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
-    const int b = xcd_item(blockIdx.x, nb);
-    if (b >= nb) return;
-    if (A.narrow) {
-        const int item = 4 * b + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (item >= A.n_items) return;
-        fv_block_fused<R, S, TH>(A, item, true, lds_mem);
-    } else {
-        fv_block_fused<R, S, TH>(A, b, false, lds_mem);
-    }
-}
-
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32
 // arithmetic) or one (FP64).
 template <class R> constexpr int FV_MIN_BLOCKS = (sizeof(R) == 4 ? 8 : 4) * 64 / FV_LANES;
@@ -1504,8 +1245,7 @@ static hipError_t launch_typed(bool thermal, bool corrector, const void* args, h
 template <class R, class S>
 static hipError_t launch_fused_typed(bool thermal, const void* args, hipStream_t s) {
     const FvArgs<R>& A = *static_cast<const FvArgs<R>*>(args);
-    const int nb = A.narrow ? (A.n_items + 3) / 4 : A.n_items;
-    dim3 grid(8 * ((nb + 7) / 8)), block(FV_LANES);
+    dim3 grid(8 * ((A.n_items + 7) / 8)), block(2 * FV_LANES);
     if (thermal) hipLaunchKernelGGL((fv_fused<R, S, true>), grid, block, 0, s, A);
     else hipLaunchKernelGGL((fv_fused<R, S, false>), grid, block, 0, s, A);
     return hipGetLastError();
@@ -1513,21 +1253,20 @@ static hipError_t launch_fused_typed(bool thermal, const void* args, hipStream_t
 
 hipError_t launch_fv_fused(int storage, bool thermal, const void* args, hipStream_t s) {
     switch (storage) {
-        case ST_F64: return launch_fused_typed<double, double>(thermal, args, s);
         case ST_F32: return launch_fused_typed<float, float>(thermal, args, s);
         case ST_BF16: return launch_fused_typed<float, bf16_t>(thermal, args, s);
         case ST_F16: return launch_fused_typed<float, f16_t>(thermal, args, s);
         case ST_BF16S: return launch_fused_typed<float, bf16s_t>(thermal, args, s);
         case ST_F16S: return launch_fused_typed<float, f16s_t>(thermal, args, s);
     }
-    return hipErrorInvalidValue;
+    return hipErrorInvalidValue;   // FP64 storage uses separate launches
 }
 
 template <class R, class S>
 static int fused_resident_typed(bool thermal) {
     int per_cu = 0, dev = 0, cus = 0;
     const void* k = thermal ? (const void*)fv_fused<R, S, true> : (const void*)fv_fused<R, S, false>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, FV_LANES, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 2 * FV_LANES, 0) != hipSuccess) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return per_cu * cus;
@@ -1535,7 +1274,6 @@ static int fused_resident_typed(bool thermal) {
 
 int fv_fused_resident_blocks(int storage, bool thermal) {
     switch (storage) {
-        case ST_F64: return fused_resident_typed<double, double>(thermal);
         case ST_F32: return fused_resident_typed<float, float>(thermal);
         case ST_BF16: return fused_resident_typed<float, bf16_t>(thermal);
         case ST_F16: return fused_resident_typed<float, f16_t>(thermal);

@@ -41,6 +41,8 @@ struct FvArgs {
     void* dst;         // output state (fused pass: f~n+1)
     void* aux;         // corrector, fused pass: the input f~n (read only); NULL otherwise
     void* dst2;        // fused pass: f~* of the next step; NULL otherwise
+    const R* xcoef2;   // fused pass: the predictor's weights (xcoef, ycoef: the corrector's)
+    const R* ycoef2;
     uint32_t state_bytes;  // whole state (grouped layout, see pop_index; or SplitLayout)
     uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
     uint32_t rest_off;     // byte offset of the rest plane (unused by split states)
