@@ -179,7 +179,16 @@ template <bool BF> struct Io16 {
         if (BF) return __builtin_bit_cast(uint16_t, (__bf16)x);    // v_cvt_pk_bf16_f32: round to nearest even
         return __builtin_bit_cast(uint16_t, (_Float16)x);          // round to nearest even
     }
-    __device__ static uint32_t enc2(float lo, float hi) { return uint32_t(enc(lo)) | (uint32_t(enc(hi)) << 16); }
+    // two values in one conversion instruction (round to nearest even)
+    __device__ static uint32_t enc2(float lo, float hi) {
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+        typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+        asm("" : "+v"(lo), "+v"(hi));   // as in enc
+        const f32x2 x{lo, hi};
+        if (BF) return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, b16x2));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, h16x2));
+    }
     template <class R> __device__ static void ld4(Buf b, uint32_t v, uint32_t s, R* d) {
         u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, 0);
         d[0] = R(dec(x[0], 0));
