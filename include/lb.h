@@ -227,7 +227,7 @@ int lb_set_state(lb_sim* sim, const void* host, size_t bytes);
  * HIP events on the handle's stream (and lb_step launches every kernel
  * itself instead of replaying captured graphs).  lb_kernel_times
  * synchronises and returns, per kernel kind (0: FV predictor or single FV
- * pass, 1: FV corrector, 2: ST, 3: FV fused pass), the number of launches
+ * pass, 1: FV corrector, 2: ST, 3: FV fused step), the number of launches
  * and their total milliseconds since the last reset (arrays of length 4). */
 int lb_set_timing(lb_sim* sim, int enable);
 int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
@@ -270,21 +270,17 @@ int lb_set_st_pairs(lb_sim* sim, int on);
  * LB_EINVAL if rows < 1. */
 int lb_set_fv_chunk(lb_sim* sim, int rows);
 
-/* Fused passes (a launch-shape knob): for the semi-implicit
- * + Heun scheme with periodic x, a run of m >= 2 steps within one lb_step
- * call is a predictor launch, m - 1 fused launches and a corrector launch;
- * a fused launch forms f~n+1 of a step (eq:semi-heun) and f~* of the next
- * (eq:semi) in one sweep, reading f~* and f~n once and writing both, so a
- * step moves four states instead of five.  It needs a second pair of state
- * buffers, allocated at the first such run (if that allocation fails, or
- * while the caller captures the stream before it was made, the steps use
- * separate launches).  The results are bit-identical either way.
+/* Fused steps (a launch-shape knob): for the semi-implicit + Heun scheme
+ * with periodic x, one launch runs the predictor (eq:semi) and the corrector
+ * (eq:semi-heun) of a step: each block forms f~* on its strip and two cells
+ * beyond it and hands it, in the form it would be stored in, to the
+ * corrector through on-chip memory, with the collision base f~n + C(f~n) of
+ * its cells, so a step reads f~n once and writes f~n+1 once instead of
+ * moving five states.  The results are bit-identical to separate launches.
  * on = 1 uses them wherever they apply, 0 never, -1 (the default) where they
- * measured faster on MI355X: FP32 storage from about 2048^2 cells with g
- * (+22 to +30%) and 4096^2 without (+14%), split BF16 storage with g at
- * 4096^2 (+2%); they are slower on smaller grids and on the other 16-bit
- * formats.  A setting under which they do not apply frees the second pair.
- * LB_EINVAL for other values. */
+ * measured faster on MI355X: with thermal populations in every storage
+ * format (FP32 about twice as fast at 4096^2, split 16-bit +5 to +12%), and
+ * without them except for split storage.  LB_EINVAL for other values. */
 int lb_set_fv_fused(lb_sim* sim, int on);
 /* The current setting (1, 0 or -1) in *on. */
 int lb_get_fv_fused(const lb_sim* sim, int* on);

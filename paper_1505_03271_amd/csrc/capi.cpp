@@ -139,7 +139,7 @@ void d_weights(double x0, double x1, double x2, double* w) {
 }  // namespace
 
 // kinds of timed launches: 0 FV predictor or single pass, 1 FV corrector,
-// 2 ST, 3 FV fused pass (corrector of a step and predictor of the next)
+// 2 ST, 3 FV fused step (predictor and corrector in one launch)
 constexpr int TIMED_KINDS = 4;
 
 struct lb_sim {
@@ -151,10 +151,8 @@ struct lb_sim {
     hipStream_t stream = nullptr;
     void* A = nullptr;  // current state
     void* B = nullptr;  // predictor / next state
-    void* A2 = nullptr; // fused passes: the second pair of states (allocated at the first use)
-    void* B2 = nullptr;
-    int fused = 1;      // lb_set_fv_fused: corrector and next predictor in one pass where possible
-    int chunk_f = 0;    // rows per work item of the fused pass (0: chosen at its first launch)
+    int fused = -1;     // lb_set_fv_fused: 1 fused steps, 0 separate launches, -1 where they pay
+    int chunk_f = 0;    // rows per work item of the fused step (0: chosen at its first launch)
     void* metric = nullptr;   // flux stencils: x pass0, y pass0, x pass1, y pass1 ([n][8] each)
     double* dxy = nullptr;    // dx[nx], dy[ny] in double
     double* partial = nullptr;
@@ -177,9 +175,9 @@ struct lb_sim {
     // captured step graphs of STEP_GRAPH_STEPS steps, by the state they start
     // from (buffer A and steps since the last rebase) and the state they leave
     struct StepGraph {
-        void* p0[4];        // A, B, A2, B2 at the start
+        void* p0[2];        // A, B at the start
         int64_t since0;
-        void* p1[4];        // and at the end
+        void* p1[2];        // and at the end
         int64_t since1;
         hipGraphExec_t exec;
     };
@@ -241,9 +239,6 @@ void drop_step_graphs(lb_sim* s) {
 // Release every device allocation of a handle (safe on partial creation).
 void release(lb_sim* s) {
     drop_step_graphs(s);
-    if (s->A2) (void)hipFree(s->A2);
-    if (s->B2) (void)hipFree(s->B2);
-    s->A2 = s->B2 = nullptr;
     if (s->cap) (void)hipStreamDestroy(s->cap);
     s->cap = nullptr;
     if (s->d_bad) (void)hipFree(s->d_bad);
@@ -418,22 +413,16 @@ int fv_launch(lb_sim* s, const void* src, void* dst, void* aux, bool corrector) 
     return LB_OK;
 }
 
-// ---- fused passes (x periodic, semi-implicit + Heun) ----
-// fused passes: semi-implicit + Heun, periodic x, FP32 arithmetic (not
-// FP64 storage), wide strips (not forced narrow)
+// ---- fused steps (x periodic, semi-implicit + Heun) ----
+// Fused steps: semi-implicit + Heun, periodic x, FP32 arithmetic (not FP64
+// storage), wide strips (not forced narrow).
 // The automatic setting uses them where they measured faster than separate
-// launches on MI355X: FP32 storage from 2048^2 cells with g (22-30%) and from
-// 4096^2 without (14%), split BF16 storage with g at 4096^2 (2%).  They lose
-// on smaller grids and on the other 16-bit formats, whose kernels are bound
-// by arithmetic more than by traffic.
-bool fused_pays(const lb_sim* s) {
-    const int64_t cells = s->plane;
-    switch (s->p.storage) {
-        case LB_F32: return cells >= (s->p.thermal ? (int64_t(3) << 20) : (int64_t(12) << 20));
-        case LB_BF16S: return s->p.thermal && cells >= (int64_t(12) << 20);
-        default: return false;
-    }
-}
+// launches on MI355X: with g for every storage format and grid from 1024^2
+// to 4096^2 (FP32 +21 to +100%, plain 16-bit +16 to +33%, split +1 to +12%),
+// without g for FP32 and plain 16-bit storage (+29 to +164%).  Split storage
+// without g is 0 to 13% slower fused (its separate kernels already run at a
+// high occupancy; the fused block is held to fewer waves).
+bool fused_pays(const lb_sim* s) { return s->p.thermal || !is_split_storage(s->p.storage); }
 bool fused_eligible(const lb_sim* s) {
     return s->p.scheme == LB_FV_HEUN && s->p.bc_x == LB_PERIODIC && s->p.storage != LB_F64 &&
            s->lanes != FV_NARROW && (s->fused > 0 || (s->fused < 0 && fused_pays(s)));
@@ -448,35 +437,12 @@ int auto_chunk_fused(const lb_sim* s) {
     h = ((h + 3) / 4) * 4;
     return std::max(8, h);
 }
-// the second pair of states, on first use (not while the caller captures the stream)
-int ensure_fused_states(lb_sim* s, bool capturing, bool* ok) {
-    *ok = false;
-    if (!fused_eligible(s)) return LB_OK;
-    if (!s->A2 || !s->B2) {
-        if (capturing) return LB_OK;
-        void* a = nullptr;
-        void* b = nullptr;
-        hipError_t e = hipMalloc(&a, s->state_bytes);
-        if (e == hipSuccess) e = hipMalloc(&b, s->state_bytes);
-        if (e != hipSuccess) {
-            if (a) (void)hipFree(a);
-            (void)hipGetLastError();
-            return LB_OK;   // no room: separate launches, as before
-        }
-        s->A2 = a;
-        s->B2 = b;
-    }
-    *ok = true;
-    return LB_OK;
-}
-
 template <class R>
-FvArgs<R> fv_args_fused(const lb_sim* s, const void* star, const void* cur, void* next, void* star2) {
-    FvArgs<R> a = fv_args<R>(s, star, next, const_cast<void*>(cur), true);   // the corrector's weights (dt/2)
-    const FvArgs<R> p = fv_args<R>(s, cur, star2, nullptr, false);
-    a.xcoef2 = p.xcoef;                                                       // and the predictor's (dt)
-    a.ycoef2 = p.ycoef;
-    a.dst2 = star2;
+FvArgs<R> fv_args_fused(const lb_sim* s, const void* cur, void* next) {
+    FvArgs<R> a = fv_args<R>(s, cur, next, nullptr, false);            // the predictor's weights (dt)
+    const FvArgs<R> c = fv_args<R>(s, cur, next, nullptr, true);
+    a.xcoef2 = c.xcoef;                                                  // and the corrector's (dt/2)
+    a.ycoef2 = c.ycoef;
     a.narrow = 0;
     a.strip_w = strip_width_fused(s);
     a.chunk_h = s->chunk_f;
@@ -485,15 +451,17 @@ FvArgs<R> fv_args_fused(const lb_sim* s, const void* star, const void* cur, void
     return a;
 }
 
-int fused_launch(lb_sim* s, const void* star, const void* cur, void* next, void* star2) {
+// One fused step: f~n in cur, f~n+1 to next.
+int fused_launch(lb_sim* s, const void* cur, void* next) {
     if (s->chunk_f <= 0) s->chunk_f = auto_chunk_fused(s);
+    if (s->chunk_h <= 0) s->chunk_h = auto_chunk(s);   // fv_args' item count of the separate launches
     if (int rc = record_event(s, 3)) return rc;
     hipError_t e;
     if (s->p.storage == LB_F64) {
-        FvArgs<double> a = fv_args_fused<double>(s, star, cur, next, star2);
+        FvArgs<double> a = fv_args_fused<double>(s, cur, next);
         e = launch_fv_fused(s->p.storage, s->p.thermal, &a, s->stream);
     } else {
-        FvArgs<float> a = fv_args_fused<float>(s, star, cur, next, star2);
+        FvArgs<float> a = fv_args_fused<float>(s, cur, next);
         e = launch_fv_fused(s->p.storage, s->p.thermal, &a, s->stream);
     }
     if (e != hipSuccess) return fail(LB_EDEVICE, "FV fused kernel launch failed: %s", hipGetErrorString(e));
@@ -597,38 +565,20 @@ bool flagged(lb_sim* s) {
 }
 
 // Enqueue n time steps as single launches (the stepping of lb_step).  With
-// fused passes, a run of m >= 2 semi-implicit + Heun steps is a predictor,
-// m - 1 fused passes (each the corrector of a step and the predictor of the
-// next, writing the other pair of states) and a corrector; a rebase ends a
-// run (it re-encodes the state that the next predictor reads).
-int enqueue_steps(lb_sim* s, int64_t nsteps, bool capturing = false) {
-    bool fused = false;
-    if (s->p.scheme == LB_FV_HEUN && nsteps >= 2)
-        if (int rc = ensure_fused_states(s, capturing, &fused)) return rc;
+// fused steps, a semi-implicit + Heun step is one launch from A to B, after
+// which the two swap.
+int enqueue_steps(lb_sim* s, int64_t nsteps) {
+    const bool fused = s->p.scheme == LB_FV_HEUN && fused_eligible(s);
     int64_t n = 0;
-    while (fused && n < nsteps) {
-        int64_t m = nsteps - n;
-        const bool rebasing = s->tref && s->rebase_every > 0;
-        if (rebasing) m = std::min<int64_t>(m, s->rebase_every - s->since_rebase);
-        int rc;
-        if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;   // f~* -> B
-        for (int64_t q = 1; q < m; ++q) {
-            if ((rc = fused_launch(s, s->B, s->A, s->A2, s->B2))) return rc;  // f~n+1 -> A2, next f~* -> B2
-            std::swap(s->A, s->A2);
-            std::swap(s->B, s->B2);
-        }
-        if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;        // f~n+1 -> A
-        n += m;
-        if (rebasing && (s->since_rebase += m) >= s->rebase_every) {
-            hipError_t e = launch_rebase(s->p.storage, aux_args(s), s->stream);
-            if (e != hipSuccess) return fail(LB_EDEVICE, "rebase launch failed: %s", hipGetErrorString(e));
-            s->since_rebase = 0;
-        }
-    }
     for (; n < nsteps; ++n) {
         int rc;
         switch (s->p.scheme) {
             case LB_FV_HEUN:
+                if (fused) {
+                    if ((rc = fused_launch(s, s->A, s->B))) return rc;               // f~n+1 -> B
+                    std::swap(s->A, s->B);
+                    break;
+                }
                 if ((rc = fv_launch(s, s->A, s->B, nullptr, false))) return rc;  // f~* -> B
                 if ((rc = fv_launch(s, s->B, s->A, s->A, true))) return rc;      // reads f~n at its cell, f~n+1 -> A
                 break;
@@ -657,21 +607,18 @@ int enqueue_steps(lb_sim* s, int64_t nsteps, bool capturing = false) {
 constexpr int64_t STEP_GRAPH_STEPS = 32;
 constexpr size_t STEP_GRAPHS_KEPT = 8;
 int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
-    void** bufs[4] = {&s->A, &s->B, &s->A2, &s->B2};
+    void** bufs[2] = {&s->A, &s->B};
     for (const auto& g : s->graphs) {
         bool same = g.since0 == s->since_rebase;
-        for (int q = 0; q < 4; ++q) same = same && g.p0[q] == *bufs[q];
+        for (int q = 0; q < 2; ++q) same = same && g.p0[q] == *bufs[q];
         if (same) { *out = &g; return LB_OK; }
     }
+    // launch shapes that are chosen at the first launch, chosen before the capture
     if (s->p.scheme != LB_ST && s->chunk_h <= 0) s->chunk_h = auto_chunk(s);
-    if (fused_eligible(s)) {
-        bool ok = false;
-        if (int rc = ensure_fused_states(s, false, &ok)) return rc;   // allocated before the capture
-        if (ok && s->chunk_f <= 0) s->chunk_f = auto_chunk_fused(s);
-    }
+    if (fused_eligible(s) && s->chunk_f <= 0) s->chunk_f = auto_chunk_fused(s);
     if (!s->cap) HIP_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));  // default priority
     lb_sim::StepGraph g{};
-    for (int q = 0; q < 4; ++q) g.p0[q] = *bufs[q];
+    for (int q = 0; q < 2; ++q) g.p0[q] = *bufs[q];
     g.since0 = s->since_rebase;
     hipStream_t user = s->stream;
     hipGraph_t graph = nullptr;
@@ -680,7 +627,7 @@ int step_graph(lb_sim* s, const lb_sim::StepGraph** out) {
     int rc = enqueue_steps(s, STEP_GRAPH_STEPS);
     s->stream = user;
     hipError_t e = hipStreamEndCapture(s->cap, &graph);
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2; ++q) {
         g.p1[q] = *bufs[q];
         *bufs[q] = g.p0[q];   // the graph has not run yet
     }
@@ -1019,12 +966,10 @@ int lb_step(lb_sim* s, int64_t nsteps) {
         HIP_TRY(hipGraphLaunch(g->exec, s->stream));
         s->A = g->p1[0];
         s->B = g->p1[1];
-        s->A2 = g->p1[2];
-        s->B2 = g->p1[3];
         s->since_rebase = g->since1;
         left -= STEP_GRAPH_STEPS;
     }
-    if (int rc = enqueue_steps(s, left, cap != hipStreamCaptureStatusNone)) return rc;
+    if (int rc = enqueue_steps(s, left)) return rc;
     if (int rc = record_event(s, -1)) return rc;
     // the flag as of the end of these steps, read by the next call
     HIP_TRY(hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(int), hipMemcpyDeviceToHost, s->stream));
@@ -1269,7 +1214,7 @@ int lb_kernel_times(lb_sim* s, int64_t* launches, double* total_ms) {
 
 size_t lb_device_bytes(const lb_sim* s) {
     if (!s) return 0;
-    return (s->A2 ? 4 : 2) * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
+    return 2 * s->state_bytes + s->metric_bytes + (s->tref ? sizeof(float) * size_t(s->p.ny) : 0) + (s->qref ? sizeof(float) * size_t(s->p.ny) : 0) + sizeof(double) * (size_t(s->p.nx) + s->p.ny) +
            sizeof(double) * (DIAG_BLOCKS * D_COUNT + D_COUNT);
 }
 
@@ -1329,13 +1274,7 @@ int lb_get_fv_fused(const lb_sim* s, int* on) {
 int lb_set_fv_fused(lb_sim* s, int on) {
     if (int rc = check_free(s, "lb_set_fv_fused")) return rc;
     if (on < -1 || on > 1) return fail(LB_EINVAL, "lb_set_fv_fused: on must be -1, 0 or 1");
-    HIP_TRY(hipStreamSynchronize(s->stream));
     s->fused = on;
-    if (!fused_eligible(s)) {   // release the second pair of states
-        if (s->A2) (void)hipFree(s->A2);
-        if (s->B2) (void)hipFree(s->B2);
-        s->A2 = s->B2 = nullptr;
-    }
     drop_step_graphs(s);
     return LB_OK;
 }

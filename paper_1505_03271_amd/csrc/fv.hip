@@ -607,31 +607,42 @@ __device__ inline int xcd_item(int b, int n_items) {
 }
 
 // Roles of fv_item: a stage launch of its own (the predictor, a single-pass
-// scheme, or the corrector), or one half of a fused pass, which runs the
-// corrector of a step and the predictor of the next side by side in one
-// block (see fv_fused).
+// scheme, or the corrector), or one half of a fused step, which runs the
+// predictor and the corrector of one Heun step side by side in one block
+// (see fv_fused).
 enum { FV_ALONE = 0, FV_FIRST = 1, FV_SECOND = 2 };
-constexpr int FV_RING = 5;   // rows of f~n+1 handed from the first half to the second (LDS)
+// LDS rings of the fused step: rows of f~* (as stored) handed from the first
+// half to the second one step after they are formed, and rows of the
+// collision base f~n + C(f~n) handed three steps after they are computed
+constexpr int FV_RING = 2, FV_RING_B = 4;
 
-// Words of one cell's record in the hand-over ring: the split record as
-// stored, or the offsets as read back from storage (FP32).
+// Words of one cell's record in the f~* ring: the split record as stored, or
+// the offsets as read back from storage.
 template <class S, bool TH> constexpr int ring_words() {
     return is_split<S>::value ? (TH ? 11 : 6) : (TH ? 18 : 9);
+}
+// words of the whole hand-over area of a fused step, per lane
+template <class S, bool TH> constexpr int fused_ring_words() {
+    return FV_RING * ring_words<S, TH>() + FV_RING_B * (TH ? 18 : 9);
 }
 
 // One FV stage over work item `item` (strip item % n_strips, chunk
 // item / n_strips) of the simulation described by A, on W lanes (lane t;
-// lds: this item's exchange rows).  In a fused pass (MODE != FV_ALONE) the
-// strips carry a halo of four columns; the first half forms f~n+1 on the
-// rows and columns the second half's stencils reach, stores its own cells
-// and hands every formed row to the second half through `ring`; the second
-// half reads its input rows there, `lag` steps of the march after they were
-// formed, and both halves meet at two barriers per step of the march.
+// lds: this item's exchange rows).  In a fused step (MODE != FV_ALONE) the
+// strips carry a halo of four columns; the first half (the predictor) forms
+// f~* on the rows and columns the second half's stencils reach and hands
+// every formed row, in its stored form, to the second half through `ring`,
+// with the collision base f~n + C(f~n) of each row of the chunk; the second
+// half (the corrector) reads its input rows there one step of the march
+// after they were formed, takes its own cells' base from the ring instead
+// of recomputing it, and stores f~n+1.  Both halves meet at one barrier per
+// step of the march: a ring row is written before a step's barrier and read
+// after it, and rewritten only after the next one.
 template <class R, class S, bool TH, bool CORR, int W, int MODE = FV_ALONE>
 __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, const int t,
                                         R (*lds)[6 * (TH ? 2 : 1)][W], uint32_t* ring = nullptr) {
-    static_assert(MODE == FV_ALONE || (W == FV_LANES && (MODE == FV_FIRST) == CORR && sizeof(R) == 4),
-                  "fused halves: wide items, FP32 arithmetic, the corrector first");
+    static_assert(MODE == FV_ALONE || (W == FV_LANES && (MODE == FV_SECOND) == CORR && sizeof(R) == 4),
+                  "fused halves: wide items, FP32 arithmetic, the predictor first");
     constexpr int NSP = TH ? 2 : 1;
     constexpr int HW = MODE == FV_ALONE ? FV_HALO : FV_FUSED_HALO;
     const int strip = item % A.n_strips, chunk = item / A.n_strips;
@@ -666,7 +677,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     const uint32_t gb = A.group_bytes, ro = A.rest_off;
     const uint32_t nxu = uint32_t(A.nx), colu = uint32_t(col);
     const Buf bsrc = make_buf(A.src, A.state_bytes);
-    const Buf bdst = make_buf(MODE == FV_SECOND ? A.dst2 : A.dst, A.state_bytes);
+    const Buf bdst = make_buf(A.dst, A.state_bytes);
     const Buf baux = make_buf(A.aux, A.state_bytes);
 
     const int y0 = chunk * A.chunk_h;
@@ -677,12 +688,22 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // half's stencils reach; at a y wall only the rows inside)
     const int f_lo = A.wall_y ? max(y0 - 2, 0) : y0 - 2;
     const int f_hi = A.wall_y ? min(y1 + 2, A.ny) : y1 + 2;
-    // the fused halves' hand-over ring, [FV_RING][ring_words][W] words
+    // the fused halves' hand-over rings: [FV_RING][ring_words][W] words of
+    // f~* records, then [FV_RING_B][9 NSP][W] words of collision bases
     constexpr int RW = ring_words<S, TH>();
     auto ring_at = [&](const int row, const int w) __attribute__((always_inline)) -> uint32_t& {
-        const int slot = (row - (y0 - 2) + 4 * FV_RING) % FV_RING;
+        const int slot = (row - (y0 - 4) + 4 * FV_RING) % FV_RING;
         return ring[(slot * RW + w) * W + t];
     };
+    auto base_at = [&](const int row, const int w) __attribute__((always_inline)) -> R& {
+        const int slot = (row - (y0 - 4)) % FV_RING_B;
+        return reinterpret_cast<R*>(ring + FV_RING * RW * W)[(slot * (9 * NSP) + w) * W + t];
+    };
+    // a fused step at a bottom wall: the second half's ghost rows -1 and -2
+    // are the mirrors of rows 0 and 1, which the first half forms after
+    // them; the second half skips those two steps and writes the ghost rows
+    // into its rings when it computes rows 0 and 1
+    const bool ghost_later = MODE == FV_SECOND && A.wall_y && y0 < 2;
 
     // rings: phi of c_y=+1 and c_y=-1 populations of the last four rows,
     // partial updates (all but the y flux) of the last two rows
@@ -734,11 +755,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if constexpr (!SPLIT) load_cell<R, S, TH>(b, cell, gb, ro, f, g);
     };
     // row of the corrector's own-cell input (f~n): rows outside the grid are
-    // wrapped in a fused pass (whose first half forms them) and clamped
-    // otherwise (their results are not used)
-    auto own_row = [&](const int r) __attribute__((always_inline)) {
-        return MODE == FV_FIRST ? map_row(r) : min(max(r, 0), A.ny - 1);
-    };
+    // clamped (their results are not used)
+    auto own_row = [&](const int r) __attribute__((always_inline)) { return min(max(r, 0), A.ny - 1); };
     auto prefetch = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
         const uint32_t cell = uint32_t(map_row(r)) * nxu + colu;
@@ -746,7 +764,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             load_split_raw<S, TH>(bsrc, cell, gb, PR[Q]);
         } else {
             load_any(bsrc, cell, PF[Q], PG[Q]);
-            if (CORR && AHEAD_OWN && formed)  // the corrector's own-cell input (f~n)
+            if (CORR && AHEAD_OWN && MODE == FV_ALONE && formed)  // the corrector's own-cell input (f~n)
                 load_any(baux, uint32_t(own_row(r)) * nxu + colu, PH[Q], PHG[Q]);
         }
     };
@@ -756,7 +774,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     auto prefetch_own = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
         if constexpr (SPLIT)
-            if (CORR) load_split_raw<S, TH>(baux, uint32_t(own_row(r)) * nxu + colu, gb, AR[Q]);
+            if (CORR && MODE == FV_ALONE) load_split_raw<S, TH>(baux, uint32_t(own_row(r)) * nxu + colu, gb, AR[Q]);
     };
     // The second half of a fused pass reads its input row from the ring, at
     // the row where it is used (the row after it may still be in the making).
@@ -802,18 +820,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         }
         bad = bad || !__builtin_isfinite(chk);
     };
-    // first half of a fused pass: store an owned cell of an owned row, and
-    // hand the formed row's record (as stored) to the second half
-    auto store_hand = [&](const int j, const bool store, const R* f, const R* g, const R trow, const R qrow)
+    // first half of a fused step: hand the formed row's record (as it
+    // would be stored) to the second half
+    auto store_hand = [&](const int j, const R* f, const R* g, const R trow, const R qrow)
                           __attribute__((always_inline)) {
-        const uint32_t cell = uint32_t(j) * nxu + colu;
         if constexpr (SPLIT) {
             SplitRaw<TH> w;
-            const R chk = encode_split<R, S, TH>(f, g, k, trow, qrow, w);
-            if (store) {
-                store_split_raw<TH>(bdst, cell, gb, w);
-                bad = bad || !__builtin_isfinite(chk);
-            }
+            (void)encode_split<R, S, TH>(f, g, k, trow, qrow, w);
             // words: the moments (4, or 3 without g), the f residuals and,
             // with g, its residuals, as in the stored record
             constexpr int NM = TH ? 4 : 3;
@@ -826,10 +839,6 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 for (int q = 0; q < 3; ++q) ring_at(j, 8 + q) = w.t[q];
             }
         } else {
-            if (store) {
-                store_cell<R, S, TH>(bdst, cell, gb, ro, f, g);
-                bad = bad || !__builtin_isfinite(TH ? f[0] + g[0] : f[0]);
-            }
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 ring_at(j, a) = __float_as_uint(float(stored_value<S>(f[a])));
@@ -840,6 +849,10 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
 
     auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
+        if (MODE == FV_SECOND && ghost_later && r < 0) {   // written at rows 0 and 1
+            lanes_sync<W>();
+            return;
+        }
         const bool my = A.wall_y && (r < 0 || r >= A.ny);
         // thermal reference of this row (uniform; ghost rows use their mirror's)
         R Tr = k.ref_g, Qr = 0;
@@ -866,7 +879,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 if (TH) dg[a] = PG[SL & 1][a];
             }
             if (AHEAD && MODE != FV_SECOND) prefetch(r + 1, Slot<SL + 1>{});
-            if (CORR && !AHEAD_OWN && formed)  // own-cell input of this row, used after the stage
+            if (CORR && !AHEAD_OWN && MODE == FV_ALONE && formed)  // own-cell input of this row, used after the stage
                 load_any(baux, uint32_t(own_row(r)) * nxu + colu, PH[SL & 1], PHG[SL & 1]);
         }
 
@@ -964,7 +977,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 }
             }
             if (MODE == FV_FIRST)
-                store_hand(j, owned && j >= y0 && j < y1, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
+                store_hand(j, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
             else
                 store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
         }
@@ -976,7 +989,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
 #pragma unroll
             for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
         lanes_sync<W>();
-        if (SPLIT && CORR && AHEAD) {
+        if (SPLIT && CORR && AHEAD && MODE == FV_ALONE) {
             __builtin_amdgcn_sched_barrier(0);
             prefetch_own(r + 1, Slot<SL + 1>{});
             __builtin_amdgcn_sched_barrier(0);
@@ -984,9 +997,15 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if (formed) {
             R base[NSP][9];
             if (CORR) {
-                // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this cell
+                // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this
+                // cell (in a fused step, from the first half, which computed it)
                 R phn[NSP][9], bn[NSP][9];
-                if constexpr (SPLIT) {
+                if constexpr (MODE == FV_SECOND) {
+#pragma unroll
+                    for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                        for (int a = 0; a < 9; ++a) bn[s][a] = base_at(r, s * 9 + a);
+                } else if constexpr (SPLIT) {
                     R hm[4], hf[9], hg[9];
                     decode_split<R, S, TH>(AR[SL & 1], hm, hf, hg);
                     stage_split<R, TH, true, false>(hm, hf, hg, k, Tr, Qr, phn, bn);
@@ -1003,6 +1022,12 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 for (int s = 0; s < NSP; ++s)
 #pragma unroll
                     for (int a = 0; a < 9; ++a) base[s][a] = bs[s][a];
+                if (MODE == FV_FIRST && r >= y0 && r < y1) {   // the second half's base of this row
+#pragma unroll
+                    for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                        for (int a = 0; a < 9; ++a) base_at(r, s * 9 + a) = bs[s][a];
+                }
             }
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
@@ -1032,72 +1057,86 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 UP[SL][s][p] = ph[s][upop(p)];
                 DN[SL][s][p] = ph[s][dpop(p)];
             }
-        // fused halves: the hand-over of this step is complete for both
-        if (MODE != FV_ALONE) lanes_sync<W>();
+        // ghost rows -1 (at row 0) and -2 (at row 1) of a fused step at a
+        // bottom wall, as the ghost-row code above forms them from the mirror
+        // row: double reflection of f, anti-reflection of g (opp(upop(p)) =
+        // dpop(p)); the slots are those of rows r - 1 and r - 3
+        if (MODE == FV_SECOND && ghost_later && (r == 0 || r == 1)) {
+            const R Twb = A.Tb - Tr;
+            auto ghost = [&](auto g_tag) __attribute__((always_inline)) {
+                constexpr int G = decltype(g_tag)::value;
+                TRg[G] = Tr;
+                QRg[G] = Qr;
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    UP[G][0][p] = ph[0][dpop(p)];
+                    DN[G][0][p] = ph[0][upop(p)];
+                    if (TH) {
+                        UP[G][NSP - 1][p] = R(2) * wt<R>(upop(p)) * Twb - ph[NSP - 1][dpop(p)];
+                        DN[G][NSP - 1][p] = R(2) * wt<R>(dpop(p)) * Twb - ph[NSP - 1][upop(p)];
+                    }
+                }
+            };
+            if (r == 0) ghost(Slot<(SL + 3) & 3>{});
+            else ghost(Slot<(SL + 1) & 3>{});
+        }
     };
 
     // Rows y0-2 .. y1+1 in trips of four; the trip may run up to three rows
     // past y1+1 (their results are never stored).  A chunk of height 4k
-    // needs exactly k+1 trips.  The first half of a fused pass marches two
-    // rows further each way (rows y0-4 .. y1+3 of f~*).  The second half
-    // starts when the first has formed row y0-2 and `lag` - 1 rows after it
-    // (at a bottom wall: rows 0 and 1, whose images are its first two
-    // rows), and both halves end on the same count of barriers.
+    // needs exactly k+1 trips.  The first half of a fused step marches two
+    // rows further each way (rows y0-4 .. y1+3 of f~n) and forms row j of
+    // f~* at its step j - y0 + 6; the second half reads row r at step
+    // r - y0 + 7, five idle steps after the first half began, and both
+    // halves end on the same count of barriers.
     const int r0 = MODE == FV_FIRST ? y0 - 4 : y0 - 2;
     const int r1 = MODE == FV_FIRST ? y1 + 3 : y1 + 1;
-    const int lag = (A.wall_y && y0 < 2) ? 4 : 1;
     const int steps1 = ((y1 + 3) - (y0 - 4) + 4) / 4 * 4;      // march steps of the first half
     const int steps2 = ((y1 + 1) - (y0 - 2) + 4) / 4 * 4;      // of the second
-    const int before = MODE == FV_SECOND ? 4 + lag : 0;         // idle steps before the march
-    const int total = max(steps1, 4 + lag + steps2);
-    for (int q = 0; q < before; ++q) {
-        lanes_sync<W>();
-        lanes_sync<W>();
-    }
+    const int before = MODE == FV_SECOND ? 5 : 0;               // idle steps before the march
+    const int total = max(steps1, 5 + steps2);
+    for (int q = 0; q < before; ++q) lanes_sync<W>();
     if (AHEAD && MODE != FV_SECOND) prefetch(r0, Slot<0>{});
-    if (AHEAD) prefetch_own(r0, Slot<0>{});
+    if (AHEAD && MODE == FV_ALONE) prefetch_own(r0, Slot<0>{});
     for (int r = r0; r <= r1; r += 4) {
         row_step(r, Slot<0>{});
         row_step(r + 1, Slot<1>{});
         row_step(r + 2, Slot<2>{});
         row_step(r + 3, Slot<3>{});
     }
-    if (MODE != FV_ALONE) {
-        for (int q = before + (MODE == FV_FIRST ? steps1 : steps2); q < total; ++q) {
-            lanes_sync<W>();
-            lanes_sync<W>();
-        }
-    }
+    if (MODE != FV_ALONE)
+        for (int q = before + (MODE == FV_FIRST ? steps1 : steps2); q < total; ++q) lanes_sync<W>();
     if (A.bad) raise_flag(A.bad, bad);
 }
 
-// ---- fused pass: the corrector of step n and the predictor of step n+1 ----
-// A block of 2 x FV_LANES lanes: the first FV_LANES run the corrector of step
-// n over a strip (eq:semi-heun), forming f~n+1 on the strip and two cells
-// beyond it (rows and columns) and storing the strip's cells; the others run
-// the predictor of step n+1 (eq:semi) over the same strip, reading the rows
-// of f~n+1 that the first half hands over through an LDS ring instead of
-// loading them, and store f~*.  Each half runs the code of the separate
-// launch (the same arithmetic in the same order), so the results are those
-// of a corrector launch followed by a predictor launch, bit for bit; a step
-// reads f~* and f~n and writes f~n+1 and the next f~*: four states instead
-// of five.  Each wave holds one stage's rings, so two waves (one of each
-// half) share a SIMD.  x is periodic (with x walls the host uses separate
-// launches); items are wide strips.
+// ---- fused step: the predictor and the corrector of one Heun step ----
+// A block of 2 x FV_LANES lanes on one strip: the first FV_LANES run the
+// predictor (eq:semi) over the strip and two cells beyond it (rows and
+// columns), forming f~* where the corrector's stencils reach, and hand each
+// formed row, as it would be stored, to the others through an LDS ring,
+// with the collision base f~n + C(f~n) of the strip's cells; the others run
+// the corrector (eq:semi-heun) on those rows and store f~n+1.  Each half
+// runs the code of the separate launch (the same arithmetic in the same
+// order, on the same stored values), so the results are those of a
+// predictor launch followed by a corrector launch, bit for bit, while a step
+// reads f~n once and writes f~n+1 once.  Each wave holds one stage's rings,
+// so two waves (one of each half) share a SIMD.  x is periodic (with x walls
+// the host uses separate launches); items are wide strips.
+// (without g a half holds few enough registers for two blocks per CU)
 template <class R, class S, bool TH>
-__global__ void __launch_bounds__(2 * FV_LANES, 1) fv_fused(FvArgs<R> A) {
+__global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2) fv_fused(FvArgs<R> A) {
     constexpr int NSP = TH ? 2 : 1;
     __shared__ R x1[2][6 * NSP][FV_LANES], x2[2][6 * NSP][FV_LANES];
-    __shared__ uint32_t ring[FV_RING * ring_words<S, TH>() * FV_LANES];
+    __shared__ uint32_t ring[fused_ring_words<S, TH>() * FV_LANES];
     const int b = xcd_item(blockIdx.x, A.n_items);
     if (b >= A.n_items) return;
     if (threadIdx.x < FV_LANES) {
-        fv_item<R, S, TH, true, FV_LANES, FV_FIRST>(A, b, threadIdx.x, x1, ring);
+        fv_item<R, S, TH, false, FV_LANES, FV_FIRST>(A, b, threadIdx.x, x1, ring);
     } else {
-        FvArgs<R> P = A;   // the predictor's flux weights
-        P.xcoef = A.xcoef2;
-        P.ycoef = A.ycoef2;
-        fv_item<R, S, TH, false, FV_LANES, FV_SECOND>(P, b, threadIdx.x - FV_LANES, x2, ring);
+        FvArgs<R> C = A;   // the corrector's flux weights
+        C.xcoef = A.xcoef2;
+        C.ycoef = A.ycoef2;
+        fv_item<R, S, TH, true, FV_LANES, FV_SECOND>(C, b, threadIdx.x - FV_LANES, x2, ring);
     }
 }
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32

@@ -16,8 +16,8 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3, ST_BF16S = 4, ST
 constexpr int FV_LANES = 256;
 constexpr int FV_NARROW = 64;
 constexpr int FV_HALO = 2;
-// The fused pass (corrector of a step and predictor of the next) forms f~n+1
-// two cells beyond its strip, so it reads f~* with a halo of four.
+// The fused step (predictor and corrector in one launch) forms f~* two cells
+// beyond its strip, so it reads f~n with a halo of four.
 constexpr int FV_FUSED_HALO = 4;
 
 // Stage constants of the FV kernel in offset arithmetic (see fv.hip), with
@@ -37,11 +37,10 @@ struct StageK {
 
 template <class R>
 struct FvArgs {
-    const void* src;   // state read with halo: f~n (predictor / single pass) or f~* (corrector, fused pass)
-    void* dst;         // output state (fused pass: f~n+1)
-    void* aux;         // corrector, fused pass: the input f~n (read only); NULL otherwise
-    void* dst2;        // fused pass: f~* of the next step; NULL otherwise
-    const R* xcoef2;   // fused pass: the predictor's weights (xcoef, ycoef: the corrector's)
+    const void* src;   // state read with halo: f~n (predictor / single pass / fused step) or f~* (corrector)
+    void* dst;         // output state (fused step: f~n+1)
+    void* aux;         // corrector: the input f~n (read only); NULL otherwise
+    const R* xcoef2;   // fused step: the corrector's weights (xcoef, ycoef: the predictor's)
     const R* ycoef2;
     uint32_t state_bytes;  // whole state (grouped layout, see pop_index; or SplitLayout)
     uint32_t group_bytes;  // one group plane: 4 elements per cell (split: 8 bytes per cell)
@@ -81,7 +80,8 @@ struct StArgs {
 // Host launchers (defined in the .hip files).  `storage` selects the
 // template instance; every launcher returns the hipError_t of the launch.
 hipError_t launch_fv_pass(int storage, bool thermal, bool corrector, const void* args, hipStream_t s);
-// One fused pass (x periodic): args as for the corrector, plus dst2.
+// One fused step (x periodic): args as for the predictor (src f~n, dst f~n+1),
+// plus the corrector's weights in xcoef2 / ycoef2.
 hipError_t launch_fv_fused(int storage, bool thermal, const void* args, hipStream_t s);
 int fv_fused_resident_blocks(int storage, bool thermal);
 // Serving: one launch over the work items of many simulations.  args holds

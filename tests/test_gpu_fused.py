@@ -1,13 +1,13 @@
-"""Fused passes (the corrector of a step and the predictor of the next in
-one launch, lb_set_fv_fused) against separate predictor and corrector
-launches: bit-identical states for every storage format that has them
-(FP32 arithmetic), with and without walls, every item height (the ghost
-rows of the second half at the walls fall at every position of an item),
-ragged widths, with renewed thermal references, through captured graphs,
-and at the 4096^2 benchmark shape.  The separate launches equal the oracle
-(FP64) and its bounds (narrower storage) in the parity tests, so the fused
-passes do too; FP64 storage has no fused pass (the setting is accepted and
-the steps use separate launches)."""
+"""Fused steps (the predictor and the corrector of a Heun step in one
+launch, lb_set_fv_fused) against separate predictor and corrector launches:
+bit-identical states for every storage format that has them (FP32
+arithmetic), with and without walls, every item height (the ghost rows of
+the second half at a bottom wall are written from rows 0 and 1 at every
+position of an item), ragged widths, with renewed thermal references,
+through captured graphs, and at the 4096^2 benchmark shape.  The separate
+launches equal the oracle (FP64) and its bounds (narrower storage) in the
+parity tests, so the fused steps do too; FP64 storage has no fused step (the
+setting is accepted and the steps use separate launches)."""
 import sys
 
 import numpy as np
@@ -105,9 +105,8 @@ def test_fused_through_captured_graphs(storage):
 
 
 def test_fused_pass_is_used_and_f64_runs_separate_launches():
-    """The kernel timing shows fused launches for FP32 storage (a predictor,
-    m - 1 fused passes and a corrector per run of m steps) and none for FP64
-    storage, whose results still equal the oracle's."""
+    """The kernel timing shows one fused launch per step for FP32 storage
+    and none for FP64 storage, whose results still equal the oracle's."""
     nx, ny = 133, 46
     say("fused launches counted")
     kw = dict(thermal=True, wall_y=True, dt=0.35, tau=0.3, tau_g=0.4, beta_g=2e-5, T_bottom=0.2, T_top=-0.2)
@@ -121,7 +120,7 @@ def test_fused_pass_is_used_and_f64_runs_separate_launches():
     a.set_timing(True)
     a.step(12)
     kt = a.kernel_times()
-    assert kt["fv_fused"][0] == 11 and kt["fv_first_pass"][0] == 1 and kt["fv_corrector"][0] == 1
+    assert kt["fv_fused"][0] == 12 and kt["fv_first_pass"][0] == 0 and kt["fv_corrector"][0] == 0
     a.close()
     sim, ref = make_pair(nx, ny, "heun", "f64", xf, yf, fields, **kw)
     sim.set_fv_fused(1)
@@ -154,17 +153,20 @@ def test_fused_at_the_benchmark_shape():
     assert np.array_equal(states[0], states[1])
 
 
-@pytest.mark.parametrize("storage,n,fused_by_default", [("f32", 64, False), ("f32", 2048, True),
-                                                        ("bf16s", 2048, False), ("bf16", 2048, False)])
-def test_automatic_setting(storage, n, fused_by_default):
-    """The default (-1) uses fused passes only where they pay: FP32 storage
-    with g from 2048^2 on, not on a small grid nor on 16-bit storage at
-    2048^2; 1 forces them, 0 turns them off, other values are refused."""
-    say(f"automatic fused setting {storage} {n}^2")
-    kw = dict(thermal=True, wall_y=True, dt=0.35, tau=0.3, tau_g=0.4, beta_g=2e-5, T_bottom=0.2, T_top=-0.2)
+@pytest.mark.parametrize("storage,thermal,fused_by_default", [("f32", True, True), ("bf16s", True, True),
+                                                              ("bf16s", False, False), ("f16", False, True)])
+def test_automatic_setting(storage, thermal, fused_by_default):
+    """The default (-1) uses fused steps where they measured faster: with
+    thermal populations in every format, without them except for split
+    storage; 1 forces them, 0 turns them off, other values are refused."""
+    n = 64
+    say(f"automatic fused setting {storage} thermal={thermal}")
+    kw = dict(thermal=thermal, wall_y=True, dt=0.35, tau=0.3, tau_g=0.4)
+    if thermal:
+        kw.update(beta_g=2e-5, T_bottom=0.2, T_top=-0.2)
     sim = lb.Sim(n, n, scheme="heun", storage=storage, stream=lb.current_stream(), **kw)
     sim.set_grid(workloads.faces_uniform(n, n), workloads.faces_tanh(n, n, 1.5))
-    sim.init(*random_fields(n, n, 3, amp=0.01))
+    sim.init(*random_fields(n, n, 3, thermal=thermal, amp=0.01))
     assert sim.fv_fused() == -1
     counts = {}
     for setting in (None, 1, 0):
@@ -174,8 +176,8 @@ def test_automatic_setting(storage, n, fused_by_default):
         sim.step(4)
         counts[setting] = sim.kernel_times()["fv_fused"][0]
         sim.set_timing(False)
-    assert counts[None] == (3 if fused_by_default else 0)
-    assert counts[1] == 3 and counts[0] == 0
+    assert counts[None] == (4 if fused_by_default else 0)
+    assert counts[1] == 4 and counts[0] == 0
     assert sim.fv_fused() == 0
     with pytest.raises(lb.LBError):
         sim.set_fv_fused(2)
