@@ -435,7 +435,7 @@ def main():
                 # plain 16-bit offsets: faster, but they stagnate under the FV
                 # time step and fail the accuracy bar (see the accuracy section)
                 extra["fv_bf16_plain"] = {"mlups": v, "accuracy_bar": "fails: the stored offsets stagnate "
-                                          "(Nu off by 12% after 500 steps at Ra=1e8, 56% at the Ra=1e4 steady roll)"}
+                                          "(Nu error far above 1%: the bf16 row of the accuracy section)"}
             else:
                 extra[f"fv_{st}_mlups"] = v
             log(f"FV {st}: {v} MLUPS")

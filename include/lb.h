@@ -242,10 +242,12 @@ int lb_kernel_times(lb_sim* sim, int64_t* launches, double* total_ms);
  * rounding step).  lb_rebase sets T_ref(row) to the current row means and
  * q(row) to 3 x the row mean of sum_a c_ay r_a, and re-encodes the stored g
  * (one rounding); with lb_set_rebase(every > 0) lb_step does this after
- * every `every` steps (0, the default, never), and so do group steps for a
- * member (its count of steps since the last renewal goes with it into and
- * out of the group, so the result is the same alone and in a group).
- * No-ops for FP64 storage or isothermal runs. */
+ * every `every` steps (0 never), and so do group steps for a member (its
+ * count of steps since the last renewal goes with it into and out of the
+ * group, so the result is the same alone and in a group).  The default is
+ * 100 for split thermal storage, whose residuals would otherwise hold a
+ * roll growing out of the conductive state below their rounding step, and
+ * 0 otherwise.  No-ops for FP64 storage or isothermal runs. */
 int lb_rebase(lb_sim* sim);
 int lb_set_rebase(lb_sim* sim, int64_t every);
 
@@ -271,16 +273,18 @@ int lb_set_st_pairs(lb_sim* sim, int on);
 int lb_set_fv_chunk(lb_sim* sim, int rows);
 
 /* Fused steps (a launch-shape knob): for the semi-implicit + Heun scheme
- * with periodic x, one launch runs the predictor (eq:semi) and the corrector
- * (eq:semi-heun) of a step: each block forms f~* on its strip and two cells
- * beyond it and hands it, in the form it would be stored in, to the
- * corrector through on-chip memory, with the collision base f~n + C(f~n) of
- * its cells, so a step reads f~n once and writes f~n+1 once instead of
- * moving five states.  The results are bit-identical to separate launches.
- * on = 1 uses them wherever they apply, 0 never, -1 (the default) where they
- * measured faster on MI355X: with thermal populations in every storage
- * format (FP32 about twice as fast at 4096^2, split 16-bit +5 to +12%), and
- * without them except for split storage.  LB_EINVAL for other values. */
+ * with periodic x and FP32 arithmetic (not FP64 storage), one launch runs
+ * the predictor (eq:semi) and the corrector (eq:semi-heun) of a step: each
+ * block forms f~* on its strip and two cells beyond it and hands it to the
+ * corrector through on-chip memory as FP32 offsets, with the collision base
+ * f~n + C(f~n) of its cells, so a step reads f~n once and writes f~n+1 once
+ * instead of moving five states.  With FP32 storage the results are
+ * bit-identical to separate launches; with 16-bit storage f~* is not rounded
+ * to the storage format (separate launches store it), one rounding fewer per
+ * step.  on = 1 uses them wherever they apply, 0 never, -1 (the default)
+ * where they measured faster on MI355X, which is everywhere they apply
+ * (4096^2 with thermal populations: FP32 twice as fast, split BF16 +21%).
+ * LB_EINVAL for other values. */
 int lb_set_fv_fused(lb_sim* sim, int on);
 /* The current setting (1, 0 or -1) in *on. */
 int lb_get_fv_fused(const lb_sim* sim, int* on);

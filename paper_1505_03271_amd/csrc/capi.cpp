@@ -141,6 +141,8 @@ void d_weights(double x0, double x1, double x2, double* w) {
 // kinds of timed launches: 0 FV predictor or single pass, 1 FV corrector,
 // 2 ST, 3 FV fused step (predictor and corrector in one launch)
 constexpr int TIMED_KINDS = 4;
+// default interval of lb_set_rebase for split thermal storage
+constexpr int64_t SPLIT_REBASE_EVERY = 100;
 
 struct lb_sim {
     lb_params p{};
@@ -417,12 +419,10 @@ int fv_launch(lb_sim* s, const void* src, void* dst, void* aux, bool corrector) 
 // Fused steps: semi-implicit + Heun, periodic x, FP32 arithmetic (not FP64
 // storage), wide strips (not forced narrow).
 // The automatic setting uses them where they measured faster than separate
-// launches on MI355X: with g for every storage format and grid from 1024^2
-// to 4096^2 (FP32 +21 to +100%, plain 16-bit +16 to +33%, split +1 to +12%),
-// without g for FP32 and plain 16-bit storage (+29 to +164%).  Split storage
-// without g is 0 to 13% slower fused (its separate kernels already run at a
-// high occupancy; the fused block is held to fewer waves).
-bool fused_pays(const lb_sim* s) { return s->p.thermal || !is_split_storage(s->p.storage); }
+// launches on MI355X: every format and grid measured, 1024^2 to 4096^2, with
+// and without g (with g: FP32 +21 to +99%, split 16-bit +10 to +23%, plain
+// 16-bit +17 to +34%).
+bool fused_pays(const lb_sim*) { return true; }
 bool fused_eligible(const lb_sim* s) {
     return s->p.scheme == LB_FV_HEUN && s->p.bc_x == LB_PERIODIC && s->p.storage != LB_F64 &&
            s->lanes != FV_NARROW && (s->fused > 0 || (s->fused < 0 && fused_pays(s)));
@@ -813,7 +813,12 @@ int lb_create(const lb_params* p, lb_sim** out) {
         s->p = *p;
         if (s->p.scheme == LB_ST) s->p.dt = 1.0;
         s->nsp = p->thermal ? 2 : 1;
-        s->fused = -1;   // fused passes where they pay (fused_pays)
+        s->fused = -1;   // fused steps where they pay (fused_pays)
+        // Split thermal storage renews its references every 100 steps by
+        // default: its 16-bit g residuals otherwise also carry the mean
+        // vertical heat flux, and small departures from it (a convection roll
+        // growing out of the conductive state) round away.
+        s->rebase_every = p->thermal && is_split_storage(p->storage) ? SPLIT_REBASE_EVERY : 0;
 
         s->plane = int64_t(p->nx) * p->ny;
         s->state_bytes = size_t(state_size(p->storage, p->thermal != 0, uint64_t(s->plane)));

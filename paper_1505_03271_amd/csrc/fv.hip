@@ -621,10 +621,9 @@ constexpr int FV_RING = 2, FV_RING_B = 4;
 template <class S, bool TH> constexpr int ring_words() {
     return is_split<S>::value ? (TH ? 11 : 6) : (TH ? 18 : 9);
 }
-// words of the whole hand-over area of a fused step, per lane
-template <class S, bool TH> constexpr int fused_ring_words() {
-    return FV_RING * ring_words<S, TH>() + FV_RING_B * (TH ? 18 : 9);
-}
+// words of the whole hand-over area of a fused step, per lane: f~* as FP32
+// offsets, and the bases
+template <class S, bool TH> constexpr int fused_ring_words() { return (FV_RING + FV_RING_B) * (TH ? 18 : 9); }
 
 // One FV stage over work item `item` (strip item % n_strips, chunk
 // item / n_strips) of the simulation described by A, on W lanes (lane t;
@@ -690,7 +689,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     const int f_hi = A.wall_y ? min(y1 + 2, A.ny) : y1 + 2;
     // the fused halves' hand-over rings: [FV_RING][ring_words][W] words of
     // f~* records, then [FV_RING_B][9 NSP][W] words of collision bases
-    constexpr int RW = ring_words<S, TH>();
+    constexpr int RW = 9 * NSP;
     auto ring_at = [&](const int row, const int w) __attribute__((always_inline)) -> uint32_t& {
         const int slot = (row - (y0 - 4) + 4 * FV_RING) % FV_RING;
         return ring[(slot * RW + w) * W + t];
@@ -748,6 +747,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // decodes a row where it is used: the stencil record at the top of its
     // row, the corrector's own-cell record only for the base.
     constexpr bool SPLIT = is_split<S>::value;
+    // whether the stage input is a split record (the second half of a fused
+    // step reads FP32 offsets from the ring)
+    constexpr bool SPLIT_IN = SPLIT && MODE != FV_SECOND;
     R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
     SplitRaw<TH> PR[2], AR[2];
 
@@ -782,27 +784,10 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     auto ring_read = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
         constexpr int Q = decltype(slot_tag)::value & 1;
         const int src = (A.wall_y && (r < 0 || r >= A.ny)) ? map_row(r) : r;
-        if constexpr (SPLIT) {
-            SplitRaw<TH> w;
-            if (TH) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) w.m[q] = ring_at(src, q);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) w.p[q] = ring_at(src, 4 + q);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) w.t[q] = ring_at(src, 8 + q);
-            } else {
-                w.m = u32x4{ring_at(src, 0), ring_at(src, 1), ring_at(src, 2), 0u};
-                w.p = u32x4{ring_at(src, 3), ring_at(src, 4), ring_at(src, 5), 0u};
-                w.t = u32x3{0u, 0u, 0u};
-            }
-            PR[Q] = w;
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                PF[Q][a] = __uint_as_float(ring_at(src, a));
-                if (TH) PG[Q][a] = __uint_as_float(ring_at(src, 9 + a));
-            }
+        for (int a = 0; a < 9; ++a) {
+            PF[Q][a] = __uint_as_float(ring_at(src, a));
+            if (TH) PG[Q][a] = __uint_as_float(ring_at(src, 9 + a));
         }
     };
     // store the offsets of a cell of a row whose thermal reference is trow,
@@ -820,30 +805,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         }
         bad = bad || !__builtin_isfinite(chk);
     };
-    // first half of a fused step: hand the formed row's record (as it
-    // would be stored) to the second half
-    auto store_hand = [&](const int j, const R* f, const R* g, const R trow, const R qrow)
-                          __attribute__((always_inline)) {
-        if constexpr (SPLIT) {
-            SplitRaw<TH> w;
-            (void)encode_split<R, S, TH>(f, g, k, trow, qrow, w);
-            // words: the moments (4, or 3 without g), the f residuals and,
-            // with g, its residuals, as in the stored record
-            constexpr int NM = TH ? 4 : 3;
+    // first half of a fused step: hand the formed row of f~* to the second
+    // half as FP32 offsets (it is never stored)
+    auto store_hand = [&](const int j, const R* f, const R* g) __attribute__((always_inline)) {
 #pragma unroll
-            for (int q = 0; q < NM; ++q) ring_at(j, q) = w.m[q];
-#pragma unroll
-            for (int q = 0; q < (TH ? 4 : 3); ++q) ring_at(j, NM + q) = w.p[q];
-            if (TH) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) ring_at(j, 8 + q) = w.t[q];
-            }
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                ring_at(j, a) = __float_as_uint(float(stored_value<S>(f[a])));
-                if (TH) ring_at(j, 9 + a) = __float_as_uint(float(stored_value<S>(g[a])));
-            }
+        for (int a = 0; a < 9; ++a) {
+            ring_at(j, a) = __float_as_uint(float(f[a]));
+            if (TH) ring_at(j, 9 + a) = __float_as_uint(float(g[a]));
         }
     };
 
@@ -864,7 +832,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if (MODE == FV_SECOND) ring_read(r, Slot<SL>{});
         else if (!AHEAD) prefetch(r, Slot<SL>{});
         R df[9], dg[9], mm[4];
-        if constexpr (SPLIT) {
+        if constexpr (SPLIT_IN) {
             // While stores are outstanding the compiler waits for all vector
             // memory operations at the first use of a load, so the decode of
             // this row's stencil record comes first and the next row's is
@@ -884,7 +852,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         }
 
         R ph[NSP][9], bs[NSP][9];
-        if constexpr (SPLIT) {  // decodes df, dg to offsets in place
+        if constexpr (SPLIT_IN) {  // decodes df, dg to offsets in place
             if (CORR) stage_split<R, TH, false, true>(mm, df, dg, k, Tr, Qr, ph, bs);
             else stage_split<R, TH, true, false>(mm, df, dg, k, Tr, Qr, ph, bs);
         } else {
@@ -921,7 +889,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             // brackets: phi_ghost = s phi, s = (2 rho_S - rho) / rho, i.e.
             // phi - w ref -> s (phi - w ref) + (s - 1) w ref.  Flow only.
             R rho;
-            if constexpr (SPLIT) rho = mm[0] + k.ref_f;
+            if constexpr (SPLIT_IN) rho = mm[0] + k.ref_f;
             else {
                 rho = df[0];
 #pragma unroll
@@ -977,7 +945,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 }
             }
             if (MODE == FV_FIRST)
-                store_hand(j, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
+                store_hand(j, out[0], out[NSP - 1]);
             else
                 store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
         }

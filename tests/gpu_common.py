@@ -46,3 +46,39 @@ def random_fields(nx, ny, seed, thermal=True, amp=0.03):
     uy = amp * r.standard_normal((ny, nx))
     T = 0.3 * r.uniform(-1, 1, (ny, nx)) if thermal else None
     return (rho, ux, uy, T) if thermal else (rho, ux, uy)
+
+
+def residual_scale(f, g, dt, ax, ay, beta_g, T0):
+    """max |f~ - (f_eq - dt/2 F)| and |g - g_eq| of an FP64 state: the size
+    of what moment-split storage rounds to 16 bits."""
+    c = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    cx, cy = c[:, 0, None, None], c[:, 1, None, None]
+    rho = f.sum(0)
+    T = g.sum(0) if g is not None else 0.0
+    Ay = ay + beta_g * (T - T0)
+    ux = (cx * f).sum(0) / rho + 0.5 * dt * ax
+    uy = (cy * f).sum(0) / rho + 0.5 * dt * Ay
+    cu = cx * ux + cy * uy
+    ca = cx * ax + cy * Ay
+    poly = 1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy)
+    frc = 3 * (ca - (ux * ax + uy * Ay)) + 9 * cu * ca
+    r = np.abs(f - w * rho * (poly - 0.5 * dt * frc)).max()
+    if g is not None:
+        r = max(r, np.abs(g - w * T * poly).max())
+    return r
+
+
+def storage_bound(storage, ref, steps, kw):
+    """max abs population error allowed after `steps` FV steps in a 16-bit
+    storage format against the oracle state `ref`: a few half-ulps per step
+    of what the format rounds (the largest stored offset, or for split
+    formats the largest residual from the forced equilibrium) plus FP32
+    arithmetic on values of size |f| <= 1."""
+    u = UNIT[storage]
+    if storage in ("bf16s", "f16s"):
+        scale = residual_scale(ref.f, ref.g, kw["dt"], kw.get("ax", 0.0), kw.get("ay", 0.0), kw.get("beta_g", 0.0),
+                               kw.get("T0", 0.0))
+    else:
+        scale = max(np.abs(offsets(ref.f, 1.0)).max(), np.abs(ref.g).max() if ref.g is not None else 0.0)
+    return steps * (8 * u * scale + 64 * 2.0 ** -24)

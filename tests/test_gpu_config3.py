@@ -65,8 +65,7 @@ def test_rb1024_500_steps_every_storage_against_the_oracle():
         sim = lb.Sim(n, n, scheme="heun", storage=storage, stream=lb.current_stream(), **_kw(cfg))
         sim.set_grid(cfg["xf"], cfg["yf"])
         sim.init(*fields)
-        if rebase:
-            sim.set_rebase(rebase)
+        sim.set_rebase(rebase)   # 0: none (the split formats' default is 100)
         sim.step(STEPS)
         r = dict(m=sim.moments(), nu=np.array(sim.nusselt()), d=sim.diagnostics())
         if storage == "f64":

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import paper_1505_03271_amd as lb
 import workloads
-from gpu_common import UNIT, make_pair, offsets, random_fields, rel_max
+from gpu_common import UNIT, make_pair, offsets, random_fields, rel_max, residual_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -178,25 +178,7 @@ def test_narrow_storage_against_oracle(storage, scheme):
         assert ef < bound and eg < bound
 
 
-def _residual_scale(f, g, dt, ax, ay, beta_g, T0):
-    """max |f~ - (f_eq - dt/2 F)| and |g - g_eq| of an FP64 state: the size
-    of what moment-split storage rounds to 16 bits."""
-    c = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]], float)
-    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
-    cx, cy = c[:, 0, None, None], c[:, 1, None, None]
-    rho = f.sum(0)
-    T = g.sum(0) if g is not None else 0.0
-    Ay = ay + beta_g * (T - T0)
-    ux = (cx * f).sum(0) / rho + 0.5 * dt * ax
-    uy = (cy * f).sum(0) / rho + 0.5 * dt * Ay
-    cu = cx * ux + cy * uy
-    ca = cx * ax + cy * Ay
-    poly = 1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy)
-    frc = 3 * (ca - (ux * ax + uy * Ay)) + 9 * cu * ca
-    r = np.abs(f - w * rho * (poly - 0.5 * dt * frc)).max()
-    if g is not None:
-        r = max(r, np.abs(g - w * T * poly).max())
-    return r
+_residual_scale = residual_scale
 
 
 SPLIT_CASES = [
@@ -361,8 +343,10 @@ def test_checkpoint_resume_is_bit_exact_and_runs_are_deterministic(storage):
 @pytest.mark.parametrize("wall_x", [False, True])
 def test_narrow_and_wide_strips_are_bit_identical(storage, wall_x):
     """The FV item width is a launch shape only: 64-lane items (four per
-    block) and 256-lane items give the same state bit for bit, on a width
-    that leaves a ragged last strip in both (nx = 300)."""
+    block) and 256-lane items of the separate predictor and corrector
+    launches give the same state bit for bit, on a width that leaves a
+    ragged last strip in both (nx = 300).  (Fused steps, which need wide
+    items, are compared with separate launches in test_gpu_fused.py.)"""
     nx, ny = 300, 53
     say(f"narrow vs wide strips {storage} wall_x={wall_x}")
     kw = dict(thermal=True, wall_x=wall_x, wall_y=True, dt=0.5, tau=0.3, tau_g=0.25, beta_g=1e-3, T_bottom=0.5,
@@ -373,6 +357,7 @@ def test_narrow_and_wide_strips_are_bit_identical(storage, wall_x):
     for lanes in (64, 256):
         sim, _ = make_pair(nx, ny, "heun", storage, xf, yf, fields, **kw)
         sim.set_fv_lanes(lanes)
+        sim.set_fv_fused(0)
         sim.step(12)
         states.append(sim.get_state())
     assert np.array_equal(states[0], states[1])

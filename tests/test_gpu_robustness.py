@@ -137,8 +137,7 @@ def _onset_run(storage, key, run, cfg, checkpoints, rebase=0):
                  stream=lb.current_stream())
     sim.set_grid(P["xf"], P["yf"])
     sim.init(rho, ux, uy, T)
-    if rebase:
-        sim.set_rebase(rebase)
+    sim.set_rebase(rebase)   # 0: none (split storage renews every 100 steps by default)
     got = []
     for _ in range(checkpoints):
         sim.step(run["steps_per_checkpoint"])

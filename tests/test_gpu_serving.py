@@ -42,6 +42,10 @@ def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
                  stream=lb.current_stream())
     sim.set_grid(P["xf"], P["yf"])
     sim.init(rho, ux, uy, T)
+    # group steps are separate predictor and corrector launches; a solo run
+    # compared with a member uses them too (fused solo steps give the same
+    # bits in FP32 and FP64 and keep f~* unrounded in 16-bit storage)
+    sim.set_fv_fused(0)
     return sim
 
 
@@ -176,6 +180,7 @@ def test_server_serves_a_trace_and_results_equal_alone(policy, min_cells):
     for req in trace:
         solo = Server(storage="bf16", max_sims=1)
         sim = solo._make(req)
+        sim.set_fv_fused(0)   # the group's launch shape
         sim.step(req["steps"])
         nu = sim.nusselt()
         sim.close()
@@ -200,6 +205,7 @@ def test_server_preempts_a_long_request_and_it_resumes_exactly():
     for req in trace:
         solo = Server(storage="bf16s", max_sims=1)
         sim = solo._make(req)
+        sim.set_fv_fused(0)   # the group's launch shape
         sim.step(req["steps"])
         nu = sim.nusselt()
         sim.close()
@@ -250,16 +256,14 @@ def test_group_members_renew_their_references_as_alone(storage):
     alone = []
     for k, (nx, ny, Ra, Pr, steps, every) in enumerate(cases):
         s = _rb_sim(nx, ny, Ra, Pr, storage, 300 + k)
-        if every:
-            s.set_rebase(every)
+        s.set_rebase(every)   # 0: none
         s.step(steps)
         alone.append(s.get_state())
         s.close()
     sims = []
     for k, (nx, ny, Ra, Pr, steps, every) in enumerate(cases):
         s = _rb_sim(nx, ny, Ra, Pr, storage, 300 + k)
-        if every:
-            s.set_rebase(every)
+        s.set_rebase(every)   # 0: none
         sims.append(s)
     g = lb.Group(4, lb.current_stream())
     slots = {k: g.add(sims[k], cases[k][4]) for k in (0, 1, 2)}
