@@ -407,9 +407,9 @@ def main():
                                                    for k, n in per_step_launches.items()), 1)
                                          if va and all(names[k] in va for k in kt) else None),
             "launch_shape": "fused" if head["fused"] else "two_pass",
-            # states this design moves per step: f~*, f~n in and f~n+1, f~* out
-            # (fused passes) or f~n in, f~* out, then f~*, f~n in, f~n+1 out
-            "design_bytes_per_cell_step": (4 if head["fused"] else 5) * b}
+            # states this design moves per step: f~n in, f~n+1 out (fused
+            # step) or f~n in, f~* out, then f~*, f~n in, f~n+1 out
+            "design_bytes_per_cell_step": (2 if head["fused"] else 5) * b}
     if not args.no_variants:
         # what plain streaming sweeps reach on this device (reads : writes
         # 2 : 1 and 1 : 1), measured after the timed region
@@ -421,7 +421,7 @@ def main():
              "kernel_avg_ms": {names[k]: round(v[1] / v[0], 4) for k, v in kt.items()},
              "launches_per_step": {names[k]: round(n, 3) for k, n in per_step_launches.items()},
              "step_GBps_algorithmic": round(alg * cells / step_s / 1e9, 1),
-             "step_GBps_design": round((4 if head["fused"] else 5) * b * cells / step_s / 1e9, 1),
+             "step_GBps_design": round((2 if head["fused"] else 5) * b * cells / step_s / 1e9, 1),
              "nusselt_bottom_top_vol_last": head["nusselt"][-1] if head["nusselt"] else None,
              "nonfinite": head["diag"]["nonfinite"]}
     if not args.no_variants:
