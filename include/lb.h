@@ -204,7 +204,9 @@ int lb_diagnostics(lb_sim* sim, double* out);
  * more is refused with LB_EINVAL.  All calls on one GPU share that array:
  * calls that overlap on one GPU (other streams, other threads) race, so
  * order them on one stream.  The handle's device must be current
- * (LB_EINVAL otherwise).  Unlike lb_diagnostics it leaves the handle's
+ * (LB_EINVAL otherwise).  A member of a group that runs fused steps gets
+ * LB_ESTATE (which of its buffers holds the state is known on the device
+ * only; lb_diagnostics finds out).  Unlike lb_diagnostics it leaves the handle's
  * stability state alone: read the non-finite slot (out[7]) from the output. */
 int lb_diagnostics_noalloc(lb_sim* sim, double* out_device);
 
@@ -296,9 +298,11 @@ size_t lb_device_bytes(const lb_sim* sim);
  *
  * A group holds up to max_sims FV semi-implicit + Heun simulations (same
  * storage format and thermal flag, any sizes, grids and parameters) and
- * advances all of them with one predictor and one corrector launch per
- * step over the work items of every member, captured with the group's
- * counter updates (and the members' renewals of their thermal references,
+ * advances all of them with one launch per step over the work items of
+ * every member: a fused step (predictor and corrector, lb_set_fv_fused)
+ * when every member takes fused steps alone, otherwise one predictor and
+ * one corrector launch.  The launches are captured with the group's counter
+ * updates (and the members' renewals of their thermal references,
  * lb_set_rebase) in a HIP graph of nsteps steps (re-captured only when the
  * membership or nsteps changes).  Each member carries its own remaining
  * step count and stops exactly there, so a member's state after its steps

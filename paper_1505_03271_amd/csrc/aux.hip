@@ -329,11 +329,13 @@ __global__ void __launch_bounds__(256) rebase_kernel(AuxArgs A) {
 // step counter kernel decides.  Blocks stride over the items.
 template <class S>
 __global__ void __launch_bounds__(256) rebase_multi_kernel(const AuxArgs* args, const int2* items, int n_items,
-                                                           const int* due) {
+                                                           const int* due, const int* phase) {
     for (int q = blockIdx.x; q < n_items; q += gridDim.x) {
         const int2 it = items[q];
         if (!due[it.x]) continue;   // uniform over the block
-        const AuxArgs A = args[it.x];
+        // two argument blocks per simulation: its state in the first or the
+        // second buffer (the phase of fused group steps; 0 without)
+        const AuxArgs A = args[2 * it.x + (phase ? phase[it.x] : 0)];
         rebase_row<S>(A, it.y);
     }
 }
@@ -346,21 +348,21 @@ static hipError_t rebase_typed(const AuxArgs& a, hipStream_t s) {
 
 template <class S>
 static hipError_t rebase_multi_typed(const AuxArgs* args, const int2* items, int n_items, const int* due,
-                                     hipStream_t s) {
+                                     const int* phase, hipStream_t s) {
     const int blocks = n_items < 2048 ? n_items : 2048;
-    hipLaunchKernelGGL(rebase_multi_kernel<S>, dim3(blocks), dim3(256), 0, s, args, items, n_items, due);
+    hipLaunchKernelGGL(rebase_multi_kernel<S>, dim3(blocks), dim3(256), 0, s, args, items, n_items, due, phase);
     return hipGetLastError();
 }
 
 hipError_t launch_rebase_multi(int storage, const AuxArgs* args, const int2* items, int n_items, const int* due,
-                               hipStream_t s) {
+                               const int* phase, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (storage) {
-        case ST_F32: return rebase_multi_typed<float>(args, items, n_items, due, s);
-        case ST_BF16: return rebase_multi_typed<bf16_t>(args, items, n_items, due, s);
-        case ST_F16: return rebase_multi_typed<f16_t>(args, items, n_items, due, s);
-        case ST_BF16S: return rebase_multi_typed<bf16s_t>(args, items, n_items, due, s);
-        case ST_F16S: return rebase_multi_typed<f16s_t>(args, items, n_items, due, s);
+        case ST_F32: return rebase_multi_typed<float>(args, items, n_items, due, phase, s);
+        case ST_BF16: return rebase_multi_typed<bf16_t>(args, items, n_items, due, phase, s);
+        case ST_F16: return rebase_multi_typed<f16_t>(args, items, n_items, due, phase, s);
+        case ST_BF16S: return rebase_multi_typed<bf16s_t>(args, items, n_items, due, phase, s);
+        case ST_F16S: return rebase_multi_typed<f16s_t>(args, items, n_items, due, phase, s);
     }
     return hipSuccess;
 }

@@ -259,9 +259,14 @@ void release(lb_sim* s) {
     s->events.clear();
 }
 
+// the buffer holding the current state: A, or for a member of a group that
+// runs fused steps, whichever its phase names (waits for the group's work)
+const void* member_state(const lb_sim* s);
+bool in_fused_group(const lb_sim* s);
+
 AuxArgs aux_args(const lb_sim* s) {
     AuxArgs a{};
-    a.state = s->A;
+    a.state = const_cast<void*>(member_state(s));
     a.nx = s->p.nx;
     a.ny = s->p.ny;
     a.plane = s->plane;
@@ -1017,6 +1022,8 @@ int lb_diagnostics_noalloc(lb_sim* s, double* out_device) {
     if (int rc = check_sim(s)) return rc;
     if (!out_device) return fail(LB_EINVAL, "lb_diagnostics_noalloc: NULL output");
     if (!s->has_init) return fail(LB_ESTATE, "lb_diagnostics_noalloc: no state");
+    if (in_fused_group(s))   // which buffer holds its state is known on the device only
+        return fail(LB_ESTATE, "lb_diagnostics_noalloc: a member of a group that runs fused steps");
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != s->device)
@@ -1173,7 +1180,7 @@ int lb_get_state(lb_sim* s, void* host, size_t bytes) {
     if (!s->has_init) return fail(LB_ESTATE, "lb_get_state: no state");
     char* h = static_cast<char*>(host);
     const size_t row = sizeof(float) * size_t(s->p.ny);
-    HIP_TRY(hipMemcpyAsync(h, s->A, s->state_bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h, member_state(s), s->state_bytes, hipMemcpyDeviceToHost, s->stream));
     h += s->state_bytes;
     if (s->tref) { HIP_TRY(hipMemcpyAsync(h, s->tref, row, hipMemcpyDeviceToHost, s->stream)); h += row; }
     if (s->qref) HIP_TRY(hipMemcpyAsync(h, s->qref, row, hipMemcpyDeviceToHost, s->stream));
@@ -1294,7 +1301,14 @@ struct lb_group {
     int max_sims = 0;
     std::vector<lb_sim*> sims;  // slot -> member (nullptr if free)
     int storage = -1, thermal = -1;
-    void* d_args = nullptr;     // 2 FvArgs per slot
+    // fused steps (every member eligible): per slot two argument blocks of
+    // the fused step, one per direction of the member's pair of buffers, and
+    // the phase that says which holds its state (flipped by the tick kernel;
+    // settled into the member's A and B at every rebuild and removal)
+    bool fused = false;
+    void* d_fargs = nullptr;
+    int* d_phase = nullptr;
+    void* d_args = nullptr;     // 2 FvArgs per slot (separate launches: predictor, corrector)
     int2* d_items = nullptr;
     size_t items_cap = 0;
     int n_items = 0;            // all items; the first n_wide are wide-strip items
@@ -1305,7 +1319,7 @@ struct lb_group {
     int64_t* d_every = nullptr;
     int64_t* d_since = nullptr;
     int* d_due = nullptr;
-    void* d_aux = nullptr;      // AuxArgs per slot
+    void* d_aux = nullptr;      // 2 AuxArgs per slot (the state in the member's A, in its B)
     int2* d_ritems = nullptr;   // (slot, row) of the members that renew their references
     size_t ritems_cap = 0;
     int n_ritems = 0;
@@ -1335,29 +1349,59 @@ void group_forget(lb_sim* s) {
 
 // Rows per work item for the current members.  All items of one launch have
 // the same height h, so with B(h) blocks and `cap` of them resident at once
-// a launch takes about ceil(B / cap) rounds of h + GROUP_ITEM_ROWS row times
-// (an item also marches two rows before and after its chunk and sets up its
-// rings).  Pick the h of 16..512 (steps of 8) with the least such time: tall
-// items when the members fill the chip many times over, short ones when few
-// members are left.
-constexpr int GROUP_ITEM_ROWS = 3;
-int group_chunk(const lb_group* g) {
-    int cap = fv_resident_blocks(g->storage, g->thermal != 0, false);
-    if (cap <= 0) cap = 512;
+// a launch takes about ceil(B / cap) rounds of h + extra row times (an item
+// also marches rows before and after its chunk and sets up its rings: 3 for
+// the separate passes, 6 for a fused step, whose first half marches four
+// rows more).  Pick the h of 16..512 (steps of 8) with the least such time:
+// tall items when the members fill the chip many times over, short ones
+// when few members are left.
+int group_chunk(const lb_group* g, bool fused) {
+    int cap = fused ? fv_fused_resident_blocks(g->storage, g->thermal != 0)
+                    : fv_resident_blocks(g->storage, g->thermal != 0, false);
+    if (cap <= 0) cap = fused ? 256 : 512;
+    const int extra = fused ? 6 : 3;
     int best_h = 64;
     int64_t best_t = INT64_MAX;
     for (int h = 16; h <= 512; h += 8) {
         int64_t wide = 0, narrow = 0;
         for (const lb_sim* s : g->sims) {
             if (!s) continue;
-            const int64_t n = int64_t((s->p.nx + strip_width(s) - 1) / strip_width(s)) * ((s->p.ny + h - 1) / h);
-            (narrow_strips(s) ? narrow : wide) += n;
+            const int sw = fused ? strip_width_fused(s) : strip_width(s);
+            const int64_t n = int64_t((s->p.nx + sw - 1) / sw) * ((s->p.ny + h - 1) / h);
+            (!fused && narrow_strips(s) ? narrow : wide) += n;
         }
         const int64_t blocks = wide + (narrow + 3) / 4;
-        const int64_t t = ((blocks + cap - 1) / cap) * (h + GROUP_ITEM_ROWS);
+        const int64_t t = ((blocks + cap - 1) / cap) * (h + extra);
         if (t <= best_t) { best_t = t; best_h = h; }
     }
     return best_h;
+}
+
+bool in_fused_group(const lb_sim* s) { return s->group && s->group->fused; }
+
+const void* member_state(const lb_sim* s) {
+    const lb_group* g = s->group;
+    if (!g || !g->fused) return s->A;
+    int ph = 0;
+    if (hipStreamSynchronize(g->stream) != hipSuccess ||
+        hipMemcpy(&ph, g->d_phase + s->group_slot, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return s->A;
+    return ph ? s->B : s->A;
+}
+
+// Settle the members' phases of fused group steps into their host state
+// pointers (a member whose state is in its B swaps A and B) and clear them,
+// so that every member's state is in its A again.
+int group_settle(lb_group* g) {
+    if (!g->fused) return LB_OK;
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    std::vector<int> ph(size_t(g->max_sims), 0);
+    HIP_TRY(hipMemcpy(ph.data(), g->d_phase, sizeof(int) * g->max_sims, hipMemcpyDeviceToHost));
+    for (int k = 0; k < g->max_sims; ++k)
+        if (g->sims[k] && ph[k]) std::swap(g->sims[k]->A, g->sims[k]->B);
+    std::fill(ph.begin(), ph.end(), 0);
+    HIP_TRY(hipMemcpy(g->d_phase, ph.data(), sizeof(int) * g->max_sims, hipMemcpyHostToDevice));
+    return LB_OK;
 }
 
 void group_drop_graph(lb_group* g) {
@@ -1371,37 +1415,50 @@ void group_fill_args(lb_group* g, std::vector<char>& host) {
     for (int k = 0; k < g->max_sims; ++k) {
         lb_sim* s = g->sims[k];
         if (!s) continue;
-        FvArgs<R> pa = fv_args<R>(s, s->A, s->B, nullptr, false);
-        FvArgs<R> ca = fv_args<R>(s, s->B, s->A, s->A, true);
+        FvArgs<R> pa, ca;
+        if (g->fused) {   // state in A: A -> B; state in B: B -> A
+            pa = fv_args_fused<R>(s, s->A, s->B);
+            ca = fv_args_fused<R>(s, s->B, s->A);
+        } else {
+            pa = fv_args<R>(s, s->A, s->B, nullptr, false);
+            ca = fv_args<R>(s, s->B, s->A, s->A, true);
+        }
         std::memcpy(&host[(2 * size_t(k)) * sizeof(FvArgs<R>)], &pa, sizeof pa);
         std::memcpy(&host[(2 * size_t(k) + 1) * sizeof(FvArgs<R>)], &ca, sizeof ca);
     }
 }
 
 int group_rebuild(lb_group* g) {
+    if (int rc = group_settle(g)) return rc;
+    // fused steps when every member can take them (otherwise separate passes)
+    bool fused = g->storage >= 0;
+    for (const lb_sim* s : g->sims)
+        if (s) fused = fused && fused_eligible(s);
+    g->fused = fused;
     if (g->storage >= 0) {
-        const int h = g->chunk > 0 ? g->chunk : group_chunk(g);
+        const int h = g->chunk > 0 ? g->chunk : group_chunk(g, fused);
         for (lb_sim* s : g->sims)
-            if (s) s->chunk_h = h;
+            if (s) s->chunk_h = s->chunk_f = h;
     }
     const size_t ab = fv_args_bytes(g->storage);
     std::vector<char> host(2 * size_t(g->max_sims) * ab, 0);
     if (g->storage == LB_F64) group_fill_args<double>(g, host);
     else group_fill_args<float>(g, host);
-    // the items of wide-strip members first, then those of narrow-strip ones
+    // fused: every member's items (wide strips); otherwise the items of
+    // wide-strip members first, then those of narrow-strip ones
     std::vector<int2> items;
     int n_wide = 0;
     for (int pass = 0; pass < 2; ++pass)
         for (int k = 0; k < g->max_sims; ++k) {
             lb_sim* s = g->sims[k];
-            if (!s || narrow_strips(s) != (pass == 1)) continue;
-            const int n_strips = (s->p.nx + strip_width(s) - 1) / strip_width(s);
-            const int n = n_strips * ((s->p.ny + s->chunk_h - 1) / s->chunk_h);
+            if (!s || (!fused && narrow_strips(s) != (pass == 1)) || (fused && pass == 1)) continue;
+            const int sw = fused ? strip_width_fused(s) : strip_width(s);
+            const int n = ((s->p.nx + sw - 1) / sw) * ((s->p.ny + s->chunk_h - 1) / s->chunk_h);
             for (int q = 0; q < n; ++q) items.push_back(int2{k, q});
             if (pass == 0) n_wide += n;
         }
     HIP_TRY(hipStreamSynchronize(g->stream));
-    HIP_TRY(hipMemcpy(g->d_args, host.data(), host.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(fused ? g->d_fargs : g->d_args, host.data(), host.size(), hipMemcpyHostToDevice));
     for (int k : g->stale) {
         const int64_t zero = 0;
         if (!g->sims[k]) HIP_TRY(hipMemcpy(g->d_left + k, &zero, sizeof zero, hipMemcpyHostToDevice));
@@ -1416,14 +1473,16 @@ int group_rebuild(lb_group* g) {
     if (!items.empty()) HIP_TRY(hipMemcpy(g->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
     g->n_items = int(items.size());
     g->n_wide = n_wide;
-    // the rows renewed by the members with a rebase interval, and their arguments
+    // the rows renewed by the members with a rebase interval, and their
+    // arguments (the state in A, and in B after an odd number of fused steps)
     std::vector<int2> ritems;
-    std::vector<AuxArgs> aux(size_t(g->max_sims));
+    std::vector<AuxArgs> aux(2 * size_t(g->max_sims));
     std::vector<int64_t> every(size_t(g->max_sims), 0);
     for (int k = 0; k < g->max_sims; ++k) {
         lb_sim* s = g->sims[k];
         if (!s || !s->tref || s->rebase_every <= 0) continue;
-        aux[k] = aux_args(s);
+        aux[2 * k] = aux[2 * k + 1] = aux_args(s);
+        if (fused) aux[2 * k + 1].state = s->B;
         every[k] = s->rebase_every;
         for (int j = 0; j < s->p.ny; ++j) ritems.push_back(int2{k, j});
     }
@@ -1443,18 +1502,25 @@ int group_rebuild(lb_group* g) {
     return LB_OK;
 }
 
-// Enqueue nsteps group steps on the group's stream (one predictor, one
-// corrector and one counter tick per step).
+// Enqueue nsteps group steps on the group's stream (one fused step, or one
+// predictor and one corrector, then one counter tick per step).
 hipError_t group_enqueue(lb_group* g, int64_t nsteps) {
+    int* phase = g->fused ? g->d_phase : nullptr;
     for (int64_t n = 0; n < nsteps; ++n) {
         const int nw = g->n_wide, nn = g->n_items - g->n_wide;
-        hipError_t e = launch_fv_multi(g->storage, g->thermal, false, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
-        if (e == hipSuccess)
-            e = launch_fv_multi(g->storage, g->thermal, true, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
-        if (e == hipSuccess) e = launch_tick(g->d_left, g->max_sims, g->d_every, g->d_since, g->d_due, g->stream);
+        hipError_t e;
+        if (g->fused) {
+            e = launch_fv_fused_multi(g->storage, g->thermal, g->d_fargs, g->d_items, g->n_items, g->d_left, phase,
+                                      g->stream);
+        } else {
+            e = launch_fv_multi(g->storage, g->thermal, false, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
+            if (e == hipSuccess)
+                e = launch_fv_multi(g->storage, g->thermal, true, g->d_args, g->d_items, nw, nn, g->d_left, g->stream);
+        }
+        if (e == hipSuccess) e = launch_tick(g->d_left, g->max_sims, g->d_every, g->d_since, g->d_due, phase, g->stream);
         if (e == hipSuccess && g->n_ritems > 0)
             e = launch_rebase_multi(g->storage, static_cast<const AuxArgs*>(g->d_aux), g->d_ritems, g->n_ritems,
-                                    g->d_due, g->stream);
+                                    g->d_due, phase, g->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1480,14 +1546,17 @@ int lb_group_create(int32_t max_sims, void* stream, lb_group** out) {
     }
     const size_t ab = std::max(fv_args_bytes(LB_F64), fv_args_bytes(LB_F32));
     if (e == hipSuccess) e = hipMalloc(&g->d_args, 2 * size_t(max_sims) * ab);
+    if (e == hipSuccess) e = hipMalloc(&g->d_fargs, 2 * size_t(max_sims) * ab);
+    if (e == hipSuccess) e = hipMalloc(&g->d_phase, sizeof(int) * max_sims);
     if (e == hipSuccess) e = hipMalloc(&g->d_left, sizeof(int64_t) * max_sims);
     if (e == hipSuccess) e = hipMalloc(&g->d_every, sizeof(int64_t) * max_sims);
     if (e == hipSuccess) e = hipMalloc(&g->d_since, sizeof(int64_t) * max_sims);
     if (e == hipSuccess) e = hipMalloc(&g->d_due, sizeof(int) * max_sims);
-    if (e == hipSuccess) e = hipMalloc(&g->d_aux, sizeof(AuxArgs) * max_sims);
+    if (e == hipSuccess) e = hipMalloc(&g->d_aux, 2 * sizeof(AuxArgs) * max_sims);
     if (e == hipSuccess) {
         std::vector<int64_t> z(max_sims, 0);
         e = hipMemcpy(g->d_left, z.data(), sizeof(int64_t) * max_sims, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g->d_phase, z.data(), sizeof(int) * max_sims, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(g->d_every, z.data(), sizeof(int64_t) * max_sims, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(g->d_since, z.data(), sizeof(int64_t) * max_sims, hipMemcpyHostToDevice);
     }
@@ -1502,10 +1571,13 @@ int lb_group_create(int32_t max_sims, void* stream, lb_group** out) {
 void lb_group_destroy(lb_group* g) {
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->d_phase) (void)group_settle(g);   // the members keep their latest state in A
     for (lb_sim* m : g->sims)
         if (m) { m->group = nullptr; m->group_slot = -1; m->chunk_h = 0; }
     group_drop_graph(g);
     if (g->d_args) (void)hipFree(g->d_args);
+    if (g->d_fargs) (void)hipFree(g->d_fargs);
+    if (g->d_phase) (void)hipFree(g->d_phase);
     if (g->d_items) (void)hipFree(g->d_items);
     if (g->d_left) (void)hipFree(g->d_left);
     if (g->d_every) (void)hipFree(g->d_every);
@@ -1531,8 +1603,10 @@ int lb_group_add(lb_group* g, lb_sim* s, int64_t steps, int32_t* slot) {
     if (k == g->max_sims) return fail(LB_ENOMEM, "lb_group_add: all %d slots are taken", g->max_sims);
     HIP_TRY(hipStreamSynchronize(g->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    const int zero = 0;
     HIP_TRY(hipMemcpy(g->d_left + k, &steps, sizeof(int64_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->d_since + k, &s->since_rebase, sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->d_phase + k, &zero, sizeof(int), hipMemcpyHostToDevice));   // its state is in its A
     g->storage = s->p.storage;
     g->thermal = s->p.thermal;
     g->sims[k] = s;
@@ -1551,6 +1625,13 @@ int lb_group_remove(lb_group* g, int32_t slot) {
     HIP_TRY(hipMemcpy(g->d_left + slot, &zero, sizeof zero, hipMemcpyHostToDevice));
     lb_sim* s = g->sims[slot];
     HIP_TRY(hipMemcpy(&s->since_rebase, g->d_since + slot, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (g->fused) {   // after an odd number of fused steps its state is in its B
+        int ph = 0;
+        HIP_TRY(hipMemcpy(&ph, g->d_phase + slot, sizeof(int), hipMemcpyDeviceToHost));
+        if (ph) std::swap(s->A, s->B);
+        const int zero = 0;
+        HIP_TRY(hipMemcpy(g->d_phase + slot, &zero, sizeof(int), hipMemcpyHostToDevice));
+    }
     s->chunk_h = 0;   // alone again: its own automatic item height
     s->group = nullptr;
     s->group_slot = -1;

@@ -1090,6 +1090,18 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
 // reads f~n once and writes f~n+1 once.  Each wave holds one stage's rings,
 // so two waves (one of each half) share a SIMD.  x is periodic (with x walls
 // the host uses separate launches); items are wide strips.
+template <class R, class S, bool TH>
+__device__ __forceinline__ void fused_halves(const FvArgs<R>& A, const int item, R (*x1)[6 * (TH ? 2 : 1)][FV_LANES],
+                                             R (*x2)[6 * (TH ? 2 : 1)][FV_LANES], uint32_t* ring) {
+    if (threadIdx.x < FV_LANES) {
+        fv_item<R, S, TH, false, FV_LANES, FV_FIRST>(A, item, threadIdx.x, x1, ring);
+    } else {
+        FvArgs<R> C = A;   // the corrector's flux weights
+        C.xcoef = A.xcoef2;
+        C.ycoef = A.ycoef2;
+        fv_item<R, S, TH, true, FV_LANES, FV_SECOND>(C, item, threadIdx.x - FV_LANES, x2, ring);
+    }
+}
 // (without g a half holds few enough registers for two blocks per CU)
 template <class R, class S, bool TH>
 __global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2) fv_fused(FvArgs<R> A) {
@@ -1098,14 +1110,37 @@ __global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2) fv_fused(FvArgs<R> A
     __shared__ uint32_t ring[fused_ring_words<S, TH>() * FV_LANES];
     const int b = xcd_item(blockIdx.x, A.n_items);
     if (b >= A.n_items) return;
-    if (threadIdx.x < FV_LANES) {
-        fv_item<R, S, TH, false, FV_LANES, FV_FIRST>(A, b, threadIdx.x, x1, ring);
-    } else {
-        FvArgs<R> C = A;   // the corrector's flux weights
-        C.xcoef = A.xcoef2;
-        C.ycoef = A.ycoef2;
-        fv_item<R, S, TH, true, FV_LANES, FV_SECOND>(C, b, threadIdx.x - FV_LANES, x2, ring);
-    }
+    fused_halves<R, S, TH>(A, b, x1, x2, ring);
+}
+
+// Fused steps of many simulations in one launch (serving): a work list of
+// (simulation, local item) pairs over a table of two argument blocks per
+// simulation, one per direction of its pair of state buffers, chosen by its
+// phase (0: the state is in the first buffer, 1: in the second; the tick
+// kernel flips it after each step the simulation takes).  A simulation with
+// no steps left is skipped.  Every item runs the code of fv_fused, so a
+// simulation's result does not depend on what else shares the launch.
+template <class R, class S, bool TH>
+__global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2)
+    fv_fused_multi(const FvArgs<R>* args, const int2* items, int n_items, const int64_t* left, const int* phase) {
+    constexpr int NSP = TH ? 2 : 1;
+    __shared__ R x1[2][6 * NSP][FV_LANES], x2[2][6 * NSP][FV_LANES];
+    __shared__ uint32_t ring[fused_ring_words<S, TH>() * FV_LANES];
+    const int b = xcd_item(blockIdx.x, n_items);
+    if (b >= n_items) return;
+    const int2 it = items[b];
+    if (left[it.x] <= 0) return;
+    // the argument block is uniform over the item: scalar loads
+    static_assert(sizeof(FvArgs<R>) % 4 == 0, "argument block in words");
+    typedef const __attribute__((address_space(4))) uint32_t CW;
+    const int ph = __builtin_amdgcn_readfirstlane(phase[it.x]);
+    CW* src = (CW*)(args + 2 * it.x + ph);
+    uint32_t words[sizeof(FvArgs<R>) / 4];
+#pragma unroll
+    for (int q = 0; q < int(sizeof(FvArgs<R>) / 4); ++q) words[q] = src[q];
+    FvArgs<R> A;
+    __builtin_memcpy(&A, words, sizeof(FvArgs<R>));
+    fused_halves<R, S, TH>(A, it.y, x1, x2, ring);
 }
 // Blocks per CU the register budget is sized for: two waves per SIMD (FP32
 // arithmetic) or one (FP64).
@@ -1181,14 +1216,16 @@ __global__ void __launch_bounds__(FV_LANES, FV_MIN_BLOCKS<R>)
 }
 
 // One group step done: every member that stepped has one step less to go,
-// and (every[i] > 0) counts towards its next renewal of the thermal
-// references, due[i] = 1 when the step count reaches it (as lb_step does).
-__global__ void tick_kernel(int64_t* left, int n, const int64_t* every, int64_t* since, int* due) {
+// its state moved to its other buffer (phase != NULL: fused steps), and
+// (every[i] > 0) counts towards its next renewal of the thermal references,
+// due[i] = 1 when the step count reaches it (as lb_step does).
+__global__ void tick_kernel(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, int* phase) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int d = 0;
     if (left[i] > 0) {
         left[i] -= 1;
+        if (phase) phase[i] ^= 1;
         if (every && every[i] > 0 && ++since[i] >= every[i]) {
             since[i] = 0;
             d = 1;
@@ -1231,9 +1268,10 @@ hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tick(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, hipStream_t s) {
+hipError_t launch_tick(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, int* phase,
+                       hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tick_kernel, dim3((n + 255) / 256), dim3(256), 0, s, left, n, every, since, due);
+    hipLaunchKernelGGL(tick_kernel, dim3((n + 255) / 256), dim3(256), 0, s, left, n, every, since, due, phase);
     return hipGetLastError();
 }
 
@@ -1274,6 +1312,29 @@ hipError_t launch_fv_fused(int storage, bool thermal, const void* args, hipStrea
         case ST_F16: return launch_fused_typed<float, f16_t>(thermal, args, s);
         case ST_BF16S: return launch_fused_typed<float, bf16s_t>(thermal, args, s);
         case ST_F16S: return launch_fused_typed<float, f16s_t>(thermal, args, s);
+    }
+    return hipErrorInvalidValue;   // FP64 storage uses separate launches
+}
+
+template <class R, class S>
+static hipError_t launch_fused_multi_typed(bool thermal, const void* args, const int2* items, int n_items,
+                                           const int64_t* left, const int* phase, hipStream_t s) {
+    const FvArgs<R>* a = static_cast<const FvArgs<R>*>(args);
+    dim3 grid(8 * ((n_items + 7) / 8)), block(2 * FV_LANES);
+    if (thermal) hipLaunchKernelGGL((fv_fused_multi<R, S, true>), grid, block, 0, s, a, items, n_items, left, phase);
+    else hipLaunchKernelGGL((fv_fused_multi<R, S, false>), grid, block, 0, s, a, items, n_items, left, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv_fused_multi(int storage, bool thermal, const void* args, const int2* items, int n_items,
+                                 const int64_t* left, const int* phase, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    switch (storage) {
+        case ST_F32: return launch_fused_multi_typed<float, float>(thermal, args, items, n_items, left, phase, s);
+        case ST_BF16: return launch_fused_multi_typed<float, bf16_t>(thermal, args, items, n_items, left, phase, s);
+        case ST_F16: return launch_fused_multi_typed<float, f16_t>(thermal, args, items, n_items, left, phase, s);
+        case ST_BF16S: return launch_fused_multi_typed<float, bf16s_t>(thermal, args, items, n_items, left, phase, s);
+        case ST_F16S: return launch_fused_multi_typed<float, f16s_t>(thermal, args, items, n_items, left, phase, s);
     }
     return hipErrorInvalidValue;   // FP64 storage uses separate launches
 }

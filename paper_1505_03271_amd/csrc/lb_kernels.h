@@ -91,9 +91,15 @@ int fv_fused_resident_blocks(int storage, bool thermal);
 // simulation s still has to do.
 hipError_t launch_fv_multi(int storage, bool thermal, bool corrector, const void* args, const int2* items,
                            int n_wide, int n_narrow, const int64_t* left, hipStream_t s);
-// left[i] -= 1 where positive; with every != NULL also the renewal count
-// since[i] of the thermal references and due[i] (1: renew after this step).
-hipError_t launch_tick(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, hipStream_t s);
+// Serving, fused steps: args holds 2 FvArgs per simulation (its state in the
+// first / second buffer of its pair), phase[s] which of the two applies.
+hipError_t launch_fv_fused_multi(int storage, bool thermal, const void* args, const int2* items, int n_items,
+                                 const int64_t* left, const int* phase, hipStream_t s);
+// left[i] -= 1 where positive, and then phase[i] ^= 1 (phase != NULL); with
+// every != NULL also the renewal count since[i] of the thermal references
+// and due[i] (1: renew after this step).
+hipError_t launch_tick(int64_t* left, int n, const int64_t* every, int64_t* since, int* due, int* phase,
+                       hipStream_t s);
 size_t fv_args_bytes(int storage);
 
 // Largest number of FV blocks of one launch that are resident at once.
@@ -126,9 +132,11 @@ hipError_t launch_set_pops(int storage, const AuxArgs& a, const double* in, hipS
 // stored g re-encoded.
 hipError_t launch_rebase(int storage, const AuxArgs& a, hipStream_t s);
 // The same for the rows items[q] = (simulation, row) of the simulations
-// whose due flag is set (args: one AuxArgs per simulation, device memory).
+// whose due flag is set (args: two AuxArgs per simulation, its state in the
+// first or the second buffer of its pair, chosen by phase[simulation], or
+// the first when phase is NULL; device memory).
 hipError_t launch_rebase_multi(int storage, const AuxArgs* args, const int2* items, int n_items, const int* due,
-                               hipStream_t s);
+                               const int* phase, hipStream_t s);
 
 // Diagnostics: per-block FP64 partial sums, then one block folds them in a
 // fixed order (bit-reproducible).  Output slots:

@@ -42,10 +42,6 @@ def _rb_sim(n_x, n_y, Ra, Pr, storage, seed, stretch=2.0):
                  stream=lb.current_stream())
     sim.set_grid(P["xf"], P["yf"])
     sim.init(rho, ux, uy, T)
-    # group steps are separate predictor and corrector launches; a solo run
-    # compared with a member uses them too (fused solo steps give the same
-    # bits in FP32 and FP64 and keep f~* unrounded in 16-bit storage)
-    sim.set_fv_fused(0)
     return sim
 
 
@@ -180,7 +176,6 @@ def test_server_serves_a_trace_and_results_equal_alone(policy, min_cells):
     for req in trace:
         solo = Server(storage="bf16", max_sims=1)
         sim = solo._make(req)
-        sim.set_fv_fused(0)   # the group's launch shape
         sim.step(req["steps"])
         nu = sim.nusselt()
         sim.close()
@@ -205,7 +200,6 @@ def test_server_preempts_a_long_request_and_it_resumes_exactly():
     for req in trace:
         solo = Server(storage="bf16s", max_sims=1)
         sim = solo._make(req)
-        sim.set_fv_fused(0)   # the group's launch shape
         sim.step(req["steps"])
         nu = sim.nusselt()
         sim.close()
