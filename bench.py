@@ -441,7 +441,7 @@ def main():
             log(f"FV {st}: {v} MLUPS")
         if "fv_f32_mlups" in extra:
             extra["fv_speedup_vs_f32"] = round(mlups / extra["fv_f32_mlups"], 3)
-        # the other launch shape of the same step (fused passes on/off)
+        # the other launch shape of the same step (fused steps on/off)
         r = run_fv(lb, torch, cfg, args.storage, vsteps, 20, fused=not head["fused"])
         extra[f"fv_{args.storage}_{'fused' if not head['fused'] else 'two_pass'}_mlups"] = round(
             r["cells"] * r["steps"] / r["seconds"] / 1e6, 1)

@@ -315,7 +315,7 @@ class Sim:
         return {names[k]: (int(n[k]), float(ms[k])) for k in range(4)}
 
     def set_fv_fused(self, on):
-        """on: 1 (True) fused passes wherever they apply, 0 (False) never,
+        """on: 1 (True) fused steps wherever they apply, 0 (False) never,
         -1 (None) where they pay (the default)."""
         _check(lib().lb_set_fv_fused(self.h, -1 if on is None else int(on)))
 

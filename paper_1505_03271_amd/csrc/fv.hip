@@ -575,13 +575,6 @@ __device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, c
     return chk;
 }
 
-// The value a stored offset reads back as (storage rounding).
-template <class S, class R> __device__ inline R stored_value(R x) {
-    if constexpr (sizeof(S) == 2) return R(Io16<std::is_same<S, bf16_t>::value>::dec(Io16<std::is_same<S, bf16_t>::value>::enc(float(x)), 0));
-    else if constexpr (sizeof(S) == 4) return R(float(x));
-    else return x;
-}
-
 // Make this row's LDS writes visible to the other lanes of the item.  A
 // 64-lane item (one wave) only needs the wave's own LDS operations kept in
 // program order (the LDS executes a wave's instructions in order); a block-
@@ -611,18 +604,11 @@ __device__ inline int xcd_item(int b, int n_items) {
 // predictor and the corrector of one Heun step side by side in one block
 // (see fv_fused).
 enum { FV_ALONE = 0, FV_FIRST = 1, FV_SECOND = 2 };
-// LDS rings of the fused step: rows of f~* (as stored) handed from the first
-// half to the second one step after they are formed, and rows of the
+// LDS rings of the fused step: rows of f~* (FP32 offsets) handed from the
+// first half to the second one step after they are formed, and rows of the
 // collision base f~n + C(f~n) handed three steps after they are computed
 constexpr int FV_RING = 2, FV_RING_B = 4;
-
-// Words of one cell's record in the f~* ring: the split record as stored, or
-// the offsets as read back from storage.
-template <class S, bool TH> constexpr int ring_words() {
-    return is_split<S>::value ? (TH ? 11 : 6) : (TH ? 18 : 9);
-}
-// words of the whole hand-over area of a fused step, per lane: f~* as FP32
-// offsets, and the bases
+// words of the whole hand-over area of a fused step, per lane
 template <class S, bool TH> constexpr int fused_ring_words() { return (FV_RING + FV_RING_B) * (TH ? 18 : 9); }
 
 // One FV stage over work item `item` (strip item % n_strips, chunk
@@ -666,7 +652,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     if (t >= lanes) { col = 0; mx = false; dxg = false; }  // idle lane of a live wave
     const bool owned = t >= HW && t < HW + own;
     // cells whose new values are formed: the owned ones, and in the first
-    // half of a fused pass every lane whose stencil lies in the strip
+    // half of a fused step every lane whose stencil lies in the strip
     const bool formed = MODE == FV_FIRST ? (t >= 2 && t < lanes - 2) : owned;
 
     R xc[8];
@@ -683,12 +669,12 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     const int y1 = min(y0 + A.chunk_h, A.ny);
     const StageK<R> k = A.k;
     typedef const __attribute__((address_space(4))) R CR;
-    // rows formed by the first half of a fused pass (those the second
+    // rows formed by the first half of a fused step (those the second
     // half's stencils reach; at a y wall only the rows inside)
     const int f_lo = A.wall_y ? max(y0 - 2, 0) : y0 - 2;
     const int f_hi = A.wall_y ? min(y1 + 2, A.ny) : y1 + 2;
-    // the fused halves' hand-over rings: [FV_RING][ring_words][W] words of
-    // f~* records, then [FV_RING_B][9 NSP][W] words of collision bases
+    // the fused halves' hand-over rings: [FV_RING][9 NSP][W] words of f~*
+    // offsets, then [FV_RING_B][9 NSP][W] words of collision bases
     constexpr int RW = 9 * NSP;
     auto ring_at = [&](const int row, const int w) __attribute__((always_inline)) -> uint32_t& {
         const int slot = (row - (y0 - 4) + 4 * FV_RING) % FV_RING;
@@ -778,7 +764,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if constexpr (SPLIT)
             if (CORR && MODE == FV_ALONE) load_split_raw<S, TH>(baux, uint32_t(own_row(r)) * nxu + colu, gb, AR[Q]);
     };
-    // The second half of a fused pass reads its input row from the ring, at
+    // The second half of a fused step reads its input row from the ring, at
     // the row where it is used (the row after it may still be in the making).
     // A ghost row at a y wall reads its mirror row.
     auto ring_read = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
