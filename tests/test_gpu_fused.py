@@ -91,7 +91,7 @@ def _same(a, b, ref, storage, steps, label, close=True):
 @pytest.mark.parametrize("thermal,wall_y", [(True, True), (True, False), (False, True), (False, False)])
 def test_fused_equals_separate_launches(storage, thermal, wall_y):
     say(f"fused vs separate {storage} thermal={thermal} wall_y={wall_y}")
-    for nx, ny, lanes in ((300, 77, 0), (300, 77, 256), (61, 40, 0), (530, 21, 256)):
+    for nx, ny, lanes in ((300, 77, 0), (300, 77, 256), (61, 40, 0), (530, 21, 256), (4, 4, 0), (5, 7, 0)):
         a, b, ref = _pair(nx, ny, storage, thermal, wall_y, lanes=lanes)
         for n in (9, 1, 4):
             _step(a, b, ref, n)
