@@ -1573,7 +1573,7 @@ void lb_group_destroy(lb_group* g) {
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     if (g->d_phase) (void)group_settle(g);   // the members keep their latest state in A
     for (lb_sim* m : g->sims)
-        if (m) { m->group = nullptr; m->group_slot = -1; m->chunk_h = 0; }
+        if (m) { m->group = nullptr; m->group_slot = -1; m->chunk_h = m->chunk_f = 0; }
     group_drop_graph(g);
     if (g->d_args) (void)hipFree(g->d_args);
     if (g->d_fargs) (void)hipFree(g->d_fargs);
@@ -1632,7 +1632,7 @@ int lb_group_remove(lb_group* g, int32_t slot) {
         const int zero = 0;
         HIP_TRY(hipMemcpy(g->d_phase + slot, &zero, sizeof(int), hipMemcpyHostToDevice));
     }
-    s->chunk_h = 0;   // alone again: its own automatic item height
+    s->chunk_h = s->chunk_f = 0;   // alone again: its own automatic item heights
     s->group = nullptr;
     s->group_slot = -1;
     drop_step_graphs(s);
