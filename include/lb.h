@@ -306,7 +306,12 @@ size_t lb_device_bytes(const lb_sim* sim);
  * lb_set_rebase) in a HIP graph of nsteps steps (re-captured only when the
  * membership or nsteps changes).  Each member carries its own remaining
  * step count and stops exactly there, so a member's state after its steps
- * is bit-identical to running it alone with lb_step.  Members stay owned by
+ * is bit-identical to running it alone with lb_step in the same launch
+ * shape: with fused group steps, alone with its settings; with separate
+ * group launches (a member that does not take fused steps is present),
+ * alone with lb_set_fv_fused(sim, 0), which for 16-bit storage differs from
+ * fused steps by the rounding of f~* (FP32 and FP64: the same bits).
+ * Members stay owned by
  * the caller.  While it is in a group, a member is advanced only by the
  * group: lb_step, lb_init, lb_set_grid, lb_set_state, lb_set_populations,
  * lb_rebase, lb_set_rebase, lb_set_fv_lanes, lb_set_fv_chunk and
