@@ -89,6 +89,37 @@ def test_group_members_match_alone_bit_exact(storage, chunk):
     g.close()
 
 
+def test_group_with_a_member_on_separate_launches():
+    """A member that does not take fused steps (lb_set_fv_fused(sim, 0))
+    makes the group run separate predictor and corrector launches for all
+    its members; every member then equals its solo run in that launch shape
+    bit for bit, also split 16-bit members, whose default solo steps are
+    fused."""
+    storage = "bf16s"
+    say("group on separate launches")
+    cases = CASES[:3]
+    alone = []
+    for k, (nx, ny, Ra, Pr, steps) in enumerate(cases):
+        s = _rb_sim(nx, ny, Ra, Pr, storage, 400 + k)
+        s.set_fv_fused(0)
+        s.step(steps)
+        alone.append(s.get_state())
+        s.close()
+    sims = [_rb_sim(nx, ny, Ra, Pr, storage, 400 + k) for k, (nx, ny, Ra, Pr, _) in enumerate(cases)]
+    sims[1].set_fv_fused(0)
+    g = lb.Group(4, lb.current_stream())
+    slots = [g.add(sims[k], cases[k][4]) for k in range(len(cases))]
+    g.step(max(c[4] for c in cases))
+    assert all(n == 0 for n in g.remaining())
+    for k in range(len(cases)):
+        assert np.array_equal(sims[k].get_state(), alone[k]), f"member {k}"
+    for sl in slots:
+        g.remove(sl)
+    g.close()
+    for sim in sims:
+        sim.close()
+
+
 def test_group_membership_rules():
     say("group rules")
     g = lb.Group(2, lb.current_stream())
