@@ -270,8 +270,8 @@ int lb_set_st_pairs(lb_sim* sim, int on);
 
 /* Rows per work item of the FV kernels (a launch-shape knob for tuning).
  * By default the height is chosen at the first step so that every item of a
- * launch is resident at once.  Any height >= 1 gives identical results.
- * LB_EINVAL if rows < 1. */
+ * launch is resident at once.  Any height >= 1 gives identical results
+ * (fused steps take at least 2).  LB_EINVAL if rows < 1. */
 int lb_set_fv_chunk(lb_sim* sim, int rows);
 
 /* Fused steps (a launch-shape knob): for the semi-implicit + Heun scheme

@@ -1272,7 +1272,7 @@ int lb_set_fv_chunk(lb_sim* s, int rows) {
     if (int rc = check_free(s, "lb_set_fv_chunk")) return rc;
     if (rows < 1) return fail(LB_EINVAL, "lb_set_fv_chunk: rows must be >= 1");
     s->chunk_h = rows;
-    s->chunk_f = rows;
+    s->chunk_f = std::max(rows, 2);   // a fused item holds at least two rows
     drop_step_graphs(s);
     return LB_OK;
 }
@@ -1436,7 +1436,8 @@ int group_rebuild(lb_group* g) {
         if (s) fused = fused && fused_eligible(s);
     g->fused = fused;
     if (g->storage >= 0) {
-        const int h = g->chunk > 0 ? g->chunk : group_chunk(g, fused);
+        int h = g->chunk > 0 ? g->chunk : group_chunk(g, fused);
+        if (fused) h = std::max(h, 2);   // a fused item holds at least two rows
         for (lb_sim* s : g->sims)
             if (s) s->chunk_h = s->chunk_f = h;
     }

@@ -687,8 +687,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // a fused step at a bottom wall: the second half's ghost rows -1 and -2
     // are the mirrors of rows 0 and 1, which the first half forms after
     // them; the second half skips those two steps and writes the ghost rows
-    // into its rings when it computes rows 0 and 1
-    const bool ghost_later = MODE == FV_SECOND && A.wall_y && y0 < 2;
+    // into its rings when it computes rows 0 and 1 (items of a fused step
+    // are at least two rows high: only the first chunk starts below row 2)
+    const bool ghost_later = MODE == FV_SECOND && A.wall_y && y0 == 0;
 
     // rings: phi of c_y=+1 and c_y=-1 populations of the last four rows,
     // partial updates (all but the y flux) of the last two rows
@@ -801,12 +802,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         }
     };
 
-    auto row_step = [&](const int r, auto slot_tag) __attribute__((always_inline)) {
+    // GH = 1 or 2: rows 0 and 1 of the corrector's first trip at a bottom
+    // wall, which also write the ghost rows -1 and -2 (0: any other row; the
+    // rows that write ghost rows are separate copies, so the march itself
+    // carries no code for them)
+    auto row_step = [&](const int r, auto slot_tag, auto gh_tag) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
-        if (MODE == FV_SECOND && ghost_later && r < 0) {   // written at rows 0 and 1
-            lanes_sync<W>();
-            return;
-        }
+        constexpr int GH = MODE == FV_SECOND ? decltype(gh_tag)::value : 0;
         const bool my = A.wall_y && (r < 0 || r >= A.ny);
         // thermal reference of this row (uniform; ghost rows use their mirror's)
         R Tr = k.ref_g, Qr = 0;
@@ -858,7 +860,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 if (TH) ph[NSP - 1][a] = my ? R(2) * wt<R>(a) * Tw - tmp[NSP - 1][opp(a)] : tmp[NSP - 1][a];
             }
         }
-        if (mx) {  // ghost column (x walls): double reflection of both species
+        if (MODE == FV_ALONE && mx) {  // ghost column (x walls; fused steps have none): double reflection of both species
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
                 R tmp[9];
@@ -868,7 +870,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 for (int a = 1; a < 9; ++a) ph[s][a] = tmp[opp(a)];
             }
         }
-        if (!TH && A.wall_x == 2) {
+        if (MODE == FV_ALONE && !TH && A.wall_x == 2) {
             // ghost column of a fixed-density boundary ("Boundary conditions",
             // second rule): the ghost density 2 rho_S - rho (linear through
             // the face value and the mirror cell) rescales the mirror cell's
@@ -1015,7 +1017,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         // bottom wall, as the ghost-row code above forms them from the mirror
         // row: double reflection of f, anti-reflection of g (opp(upop(p)) =
         // dpop(p)); the slots are those of rows r - 1 and r - 3
-        if (MODE == FV_SECOND && ghost_later && (r == 0 || r == 1)) {
+        if constexpr (GH != 0) {
             const R Twb = A.Tb - Tr;
             auto ghost = [&](auto g_tag) __attribute__((always_inline)) {
                 constexpr int G = decltype(g_tag)::value;
@@ -1031,8 +1033,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                     }
                 }
             };
-            if (r == 0) ghost(Slot<(SL + 3) & 3>{});
-            else ghost(Slot<(SL + 1) & 3>{});
+            ghost(Slot<GH == 1 ? (SL + 3) & 3 : (SL + 1) & 3>{});
         }
     };
 
@@ -1052,11 +1053,21 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     for (int q = 0; q < before; ++q) lanes_sync<W>();
     if (AHEAD && MODE != FV_SECOND) prefetch(r0, Slot<0>{});
     if (AHEAD && MODE == FV_ALONE) prefetch_own(r0, Slot<0>{});
-    for (int r = r0; r <= r1; r += 4) {
-        row_step(r, Slot<0>{});
-        row_step(r + 1, Slot<1>{});
-        row_step(r + 2, Slot<2>{});
-        row_step(r + 3, Slot<3>{});
+    int r = r0;
+    if constexpr (MODE == FV_SECOND) {
+        if (ghost_later) {   // the first trip (rows -2 .. 1): the ghost rows come with rows 0 and 1
+            lanes_sync<W>();
+            lanes_sync<W>();
+            row_step(0, Slot<2>{}, Slot<1>{});
+            row_step(1, Slot<3>{}, Slot<2>{});
+            r += 4;
+        }
+    }
+    for (; r <= r1; r += 4) {
+        row_step(r, Slot<0>{}, Slot<0>{});
+        row_step(r + 1, Slot<1>{}, Slot<0>{});
+        row_step(r + 2, Slot<2>{}, Slot<0>{});
+        row_step(r + 3, Slot<3>{}, Slot<0>{});
     }
     if (MODE != FV_ALONE)
         for (int q = before + (MODE == FV_FIRST ? steps1 : steps2); q < total; ++q) lanes_sync<W>();
@@ -1285,6 +1296,7 @@ static hipError_t launch_typed(bool thermal, bool corrector, const void* args, h
 template <class R, class S>
 static hipError_t launch_fused_typed(bool thermal, const void* args, hipStream_t s) {
     const FvArgs<R>& A = *static_cast<const FvArgs<R>*>(args);
+    if (A.chunk_h < 2) return hipErrorInvalidValue;   // items of at least two rows (the bottom wall's first trip)
     dim3 grid(8 * ((A.n_items + 7) / 8)), block(2 * FV_LANES);
     if (thermal) hipLaunchKernelGGL((fv_fused<R, S, true>), grid, block, 0, s, A);
     else hipLaunchKernelGGL((fv_fused<R, S, false>), grid, block, 0, s, A);

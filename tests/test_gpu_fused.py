@@ -102,7 +102,9 @@ def test_fused_equals_separate_launches(storage, thermal, wall_y):
 @pytest.mark.parametrize("chunk", [1, 2, 3, 4, 5, 6, 7, 8, 12])
 def test_fused_every_item_height(storage, chunk):
     """Heights below the second stage's reach put the wall images of rows
-    0, 1 and ny-1, ny-2 at every position of an item."""
+    0, 1 and ny-1, ny-2 at every position of an item (a fused item holds at
+    least two rows: height 1 gives fused items of 2 beside separate launches
+    of 1)."""
     say(f"fused item height {chunk} {storage}")
     a, b, ref = _pair(90, 23, storage, True, True, chunk=chunk)
     _step(a, b, ref, 6)
