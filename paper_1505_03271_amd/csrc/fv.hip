@@ -711,8 +711,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
 
     // One row of the march.  The body is free of block-uniform branches (so
     // the unrolled rings stay in fixed registers): every row is exchanged
-    // through LDS, ghost rows are selected arithmetically, and only the
-    // stores and the owned lanes' flux are masked.
+    // through LDS, ghost rows are selected arithmetically (in the trips that
+    // may hold them), and only the stores and the owned lanes' flux are
+    // masked.
     // Storage row of march row r (ghost rows mirror or wrap; rows past the
     // chunk end, the padding of the last unrolled trip, are clamped).
     auto map_row = [&](const int r) __attribute__((always_inline)) {
@@ -805,11 +806,11 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // GH = 1 or 2: rows 0 and 1 of the corrector's first trip at a bottom
     // wall, which also write the ghost rows -1 and -2 (0: any other row; the
     // rows that write ghost rows are separate copies, so the march itself
-    // carries no code for them)
-    auto row_step = [&](const int r, auto slot_tag, auto gh_tag) __attribute__((always_inline)) {
+    // carries no code for them).  YG: the row may lie beyond a y wall.
+    auto row_step = [&](const int r, auto slot_tag, auto gh_tag, auto yg_tag) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot_tag)::value;  // (r - y0 + 2) mod 4
         constexpr int GH = MODE == FV_SECOND ? decltype(gh_tag)::value : 0;
-        const bool my = A.wall_y && (r < 0 || r >= A.ny);
+        const bool my = decltype(yg_tag)::value && A.wall_y && (r < 0 || r >= A.ny);
         // thermal reference of this row (uniform; ghost rows use their mirror's)
         R Tr = k.ref_g, Qr = 0;
         if (TH && A.tref) Tr = ((const CR*)A.tref)[map_row(r)];
@@ -1058,16 +1059,34 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
         if (ghost_later) {   // the first trip (rows -2 .. 1): the ghost rows come with rows 0 and 1
             lanes_sync<W>();
             lanes_sync<W>();
-            row_step(0, Slot<2>{}, Slot<1>{});
-            row_step(1, Slot<3>{}, Slot<2>{});
+            row_step(0, Slot<2>{}, Slot<1>{}, Slot<1>{});
+            row_step(1, Slot<3>{}, Slot<2>{}, Slot<1>{});
             r += 4;
         }
     }
-    for (; r <= r1; r += 4) {
-        row_step(r, Slot<0>{}, Slot<0>{});
-        row_step(r + 1, Slot<1>{}, Slot<0>{});
-        row_step(r + 2, Slot<2>{}, Slot<0>{});
-        row_step(r + 3, Slot<3>{}, Slot<0>{});
+    auto trip = [&](const int r, auto yg_tag) __attribute__((always_inline)) {
+        row_step(r, Slot<0>{}, Slot<0>{}, yg_tag);
+        row_step(r + 1, Slot<1>{}, Slot<0>{}, yg_tag);
+        row_step(r + 2, Slot<2>{}, Slot<0>{}, yg_tag);
+        row_step(r + 3, Slot<3>{}, Slot<0>{}, yg_tag);
+    };
+    // Fused halves march the trips that may hold rows beyond a y wall (whose
+    // brackets are reflected) apart from the others, which carry no code for
+    // the reflection: the first half's trips below row 0, then every trip
+    // inside the grid, then those reaching row ny.  (The second half has
+    // none below row 0 at a wall: its first trip is the one above.)
+    if constexpr (MODE == FV_ALONE) {
+        for (; r <= r1; r += 4) {
+            row_step(r, Slot<0>{}, Slot<0>{}, Slot<1>{});
+            row_step(r + 1, Slot<1>{}, Slot<0>{}, Slot<1>{});
+            row_step(r + 2, Slot<2>{}, Slot<0>{}, Slot<1>{});
+            row_step(r + 3, Slot<3>{}, Slot<0>{}, Slot<1>{});
+        }
+    } else {
+        if (MODE == FV_FIRST && A.wall_y)
+            for (; r <= r1 && r < 0; r += 4) trip(r, Slot<1>{});
+        for (; r <= r1 && !(A.wall_y && r + 3 >= A.ny); r += 4) trip(r, Slot<0>{});
+        for (; r <= r1; r += 4) trip(r, Slot<1>{});
     }
     if (MODE != FV_ALONE)
         for (int q = before + (MODE == FV_FIRST ? steps1 : steps2); q < total; ++q) lanes_sync<W>();
