@@ -269,10 +269,27 @@ __device__ inline void stage_core(const R* df, const R* dg, const R rho_p, const
         bs[0][0] = k.omkc * df[0] + wt<R>(0) * (k.kc * rho_p - rho * (k.kc * uu + k.kf * ua3));
         if (TH) bs[NSP - 1][0] = k.omkcg * dg[0] + k.kcg * wt<R>(0) * (T_p - T * uu);
     }
+    // The weight w is common to a class of populations (axis 1/9, diagonal
+    // 1/36), so it enters through per-class products: w rho, w k1 rho' (and
+    // w kc rho'), and for g w k1g T, w k1g T' (and with kcg).
+    const R k1r = k.k1 * rho_p, kcr = k.kc * rho_p;
+    R wr[2], wk1[2], wkc[2], gT[2], gTp[2], cT[2], cTp[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const R w = wt<R>(c == 0 ? 1 : 5);
+        wr[c] = w * rho;
+        wk1[c] = w * k1r;
+        wkc[c] = w * kcr;
+        const R g1 = k.k1g * w, gc = k.kcg * w;
+        gT[c] = g1 * T;
+        gTp[c] = g1 * T_p;
+        cT[c] = gc * T;
+        cTp[c] = gc * T_p;
+    }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int a = pa(p), b = pb(p);
-        const R w = wt<R>(a);
+        const int c = p < 2 ? 0 : 1;
         R cu, ca;
         if (p == 0) { cu = ux; ca = ax; }
         else if (p == 1) { cu = uy; ca = ay; }
@@ -280,27 +297,29 @@ __device__ inline void stage_core(const R* df, const R* dg, const R rho_p, const
         else { cu = uy - ux; ca = ay - ax; }
         const R Em = (R(4.5) * cu) * cu - uu;     // even part of f_eq / (w rho), minus 1
         const R Fe = (R(9) * cu) * ca - ua3;      // even part of F / (w rho)
-        // advected bracket of f, minus w ref
-        const R Pe = k.k1 * rho_p + rho * (k.k1 * Em + k.kh * Fe);
-        const R Po = rho * (k.k1x3 * cu + k.khx3 * ca);
-        ph[0][a] = k.omk1 * df[a] + w * (Pe + Po);
-        ph[0][b] = k.omk1 * df[b] + w * (Pe - Po);
+        // advected bracket of f, minus w ref:
+        //   w (k1 rho' + rho (k1 Em + kh Fe)) +- w rho (3 k1 cu + 3 kh ca)
+        const R Pe = k.k1 * Em + k.kh * Fe;
+        const R Po = k.k1x3 * cu + k.khx3 * ca;
+        ph[0][a] = k.omk1 * df[a] + (wk1[c] + wr[c] * (Pe + Po));
+        ph[0][b] = k.omk1 * df[b] + (wk1[c] + wr[c] * (Pe - Po));
         if (TH) {
-            // bracket of g, minus w Tr
+            // bracket of g, minus w Tr: k1g w (T' + T Em +- 3 T cu)
             const R O = R(3) * cu;
-            const R Ge = T_p + T * Em, Go = T * O;
-            ph[NSP - 1][a] = k.omk1g * dg[a] + k.k1g * w * (Ge + Go);
-            ph[NSP - 1][b] = k.omk1g * dg[b] + k.k1g * w * (Ge - Go);
+            const R Ge = gTp[c] + gT[c] * Em, Go = gT[c] * O;
+            ph[NSP - 1][a] = k.omk1g * dg[a] + (Ge + Go);
+            ph[NSP - 1][b] = k.omk1g * dg[b] + (Ge - Go);
             if (BASE) {
-                bs[NSP - 1][a] = k.omkcg * dg[a] + k.kcg * w * (Ge + Go);
-                bs[NSP - 1][b] = k.omkcg * dg[b] + k.kcg * w * (Ge - Go);
+                const R Ce = cTp[c] + cT[c] * Em, Co = cT[c] * O;
+                bs[NSP - 1][a] = k.omkcg * dg[a] + (Ce + Co);
+                bs[NSP - 1][b] = k.omkcg * dg[b] + (Ce - Co);
             }
         }
         if (BASE) {
-            const R Ae = k.kc * rho_p + rho * (k.kc * Em + k.kf * Fe);
-            const R Ao = rho * (k.kcx3 * cu + k.kfx3 * ca);
-            bs[0][a] = k.omkc * df[a] + w * (Ae + Ao);
-            bs[0][b] = k.omkc * df[b] + w * (Ae - Ao);
+            const R Ae = k.kc * Em + k.kf * Fe;
+            const R Ao = k.kcx3 * cu + k.kfx3 * ca;
+            bs[0][a] = k.omkc * df[a] + (wkc[c] + wr[c] * (Ae + Ao));
+            bs[0][b] = k.omkc * df[b] + (wkc[c] + wr[c] * (Ae - Ao));
         }
     }
 }
@@ -521,21 +540,25 @@ __device__ inline void stage_split(const R* m, R* df, R* dg, const StageK<R>& k,
 // Offsets d of a cell -> its split record: moments (FP32 words) and rounded
 // residuals (16-bit words), as stored.  Returns m0 + m3, which is finite
 // exactly when the moments are.
-template <class R, class S, bool TH>
+// X2: df, dg hold twice the offsets (exactly: every operation that formed
+// them scales by two without rounding differently), halved here where it
+// costs least, in the four moments and inside the residuals' subtraction.
+template <class R, class S, bool TH, bool X2 = false>
 __device__ inline R encode_split(const R* df, const R* dg, const StageK<R>& k, const R Tr, const R q,
                                  SplitRaw<TH>& w) {
     using IO = Narrow<S>;
     constexpr float rs = split_scale<S>::value;
+    constexpr R hx = X2 ? R(0.5) : R(1);
     R m[4];
-    m[0] = ((df[0] + (df[1] + df[2])) + (df[3] + df[4])) + ((df[5] + df[6]) + (df[7] + df[8]));
-    m[1] = ((df[1] - df[3]) + (df[5] - df[6])) + (df[8] - df[7]);
-    m[2] = ((df[2] - df[4]) + (df[5] + df[6])) - (df[7] + df[8]);
-    m[3] = TH ? ((dg[0] + (dg[1] + dg[2])) + (dg[3] + dg[4])) + ((dg[5] + dg[6]) + (dg[7] + dg[8])) : R(0);
+    m[0] = hx * (((df[0] + (df[1] + df[2])) + (df[3] + df[4])) + ((df[5] + df[6]) + (df[7] + df[8])));
+    m[1] = hx * (((df[1] - df[3]) + (df[5] - df[6])) + (df[8] - df[7]));
+    m[2] = hx * (((df[2] - df[4]) + (df[5] + df[6])) - (df[7] + df[8]));
+    m[3] = TH ? hx * (((dg[0] + (dg[1] + dg[2])) + (dg[3] + dg[4])) + ((dg[5] + dg[6]) + (dg[7] + dg[8]))) : R(0);
     R rho, T, ux, uy, ay;
     split_macro<R, TH>(m, k, Tr, rho, T, ux, uy, ay);
     R rf[9], rg[9];
     split_eq<R, TH>(m, rho, T, ux, uy, ay, k, q, [&](int s, int a, R e) __attribute__((always_inline)) {
-        if (s == 0) rf[a] = df[a] - e; else rg[a] = dg[a] - e;
+        if (s == 0) rf[a] = hx * df[a] - e; else rg[a] = hx * dg[a] - e;
     });
     auto e2 = [&](R lo, R hi) __attribute__((always_inline)) { return IO::enc2(float(lo) * rs, float(hi) * rs); };
     w.m = u32x4{__float_as_uint(float(m[0])), __float_as_uint(float(m[1])), __float_as_uint(float(m[2])),
@@ -566,11 +589,11 @@ __device__ inline void store_split_raw(Buf b, uint32_t cell, uint32_t G, const S
 
 // Offsets d of a cell -> moments (FP32) and rounded residuals, stored.
 // Returns m0 + m3, which is finite exactly when the stored moments are.
-template <class R, class S, bool TH>
+template <class R, class S, bool TH, bool X2 = false>
 __device__ inline R store_split(Buf b, uint32_t cell, uint32_t G, const R* df, const R* dg, const StageK<R>& k,
                                 const R Tr, const R q) {
     SplitRaw<TH> w;
-    const R chk = encode_split<R, S, TH>(df, dg, k, Tr, q, w);
+    const R chk = encode_split<R, S, TH, X2>(df, dg, k, Tr, q, w);
     store_split_raw<TH>(b, cell, G, w);
     return chk;
 }
@@ -738,6 +761,12 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // whether the stage input is a split record (the second half of a fused
     // step reads FP32 offsets from the ring)
     constexpr bool SPLIT_IN = SPLIT && MODE != FV_SECOND;
+    // The second half of a fused step into split storage works with twice
+    // its update (base f~n + C(f~n) + f~* and the flux weights of dt, not
+    // dt/2): scaling by two is exact, so every value it forms is exactly
+    // twice that of the plain form, and the encoder halves the moments (four
+    // products instead of eighteen here).
+    constexpr bool X2 = SPLIT && MODE == FV_SECOND;
     R PF[2][9], PG[2][9], PH[2][9], PHG[2][9];
     SplitRaw<TH> PR[2], AR[2];
 
@@ -786,7 +815,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                          __attribute__((always_inline)) {
         R chk;
         if constexpr (SPLIT) {
-            chk = store_split<R, S, TH>(b, cell, gb, f, g, k, trow, qrow);
+            chk = store_split<R, S, TH, X2>(b, cell, gb, f, g, k, trow, qrow);
         } else {
             store_cell<R, S, TH>(b, cell, gb, ro, f, g);
             chk = TH ? f[0] + g[0] : f[0];
@@ -971,8 +1000,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 }
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
-                    base[0][a] = R(0.5) * (bn[0][a] + df[a]);
-                    if (TH) base[NSP - 1][a] = R(0.5) * (bn[NSP - 1][a] + dg[a]);
+                    base[0][a] = X2 ? bn[0][a] + df[a] : R(0.5) * (bn[0][a] + df[a]);
+                    if (TH) base[NSP - 1][a] = X2 ? bn[NSP - 1][a] + dg[a] : R(0.5) * (bn[NSP - 1][a] + dg[a]);
                 }
             } else {
 #pragma unroll
@@ -1113,8 +1142,10 @@ __device__ __forceinline__ void fused_halves(const FvArgs<R>& A, const int item,
         fv_item<R, S, TH, false, FV_LANES, FV_FIRST>(A, item, threadIdx.x, x1, ring);
     } else {
         FvArgs<R> C = A;   // the corrector's flux weights
-        C.xcoef = A.xcoef2;
-        C.ycoef = A.ycoef2;
+        if (!is_split<S>::value) {   // (split storage: twice them, see fv_item)
+            C.xcoef = A.xcoef2;
+            C.ycoef = A.ycoef2;
+        }
         fv_item<R, S, TH, true, FV_LANES, FV_SECOND>(C, item, threadIdx.x - FV_LANES, x2, ring);
     }
 }
