@@ -761,6 +761,11 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // whether the stage input is a split record (the second half of a fused
     // step reads FP32 offsets from the ring)
     constexpr bool SPLIT_IN = SPLIT && MODE != FV_SECOND;
+    // The halves of a fused step with g keep a lane's twelve exchanged
+    // brackets together in LDS (three 16-byte words per lane, those moving
+    // to +x first), so a neighbour's values come in a few wide reads.
+    constexpr bool XT = TH && MODE != FV_ALONE && sizeof(R) == 4;
+    auto xslot = [](int s, int p) { return (p < 3 ? 0 : 6) + 3 * s + p % 3; };
     // The second half of a fused step into split storage works with twice
     // its update (base f~n + C(f~n) + f~* and the flux weights of dt, not
     // dt/2): scaling by two is exact, so every value it forms is exactly
@@ -970,10 +975,21 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
 
         // ---- x flux and partial update (all but the y flux) of row r ----
         const int b = SL & 1;
+        if constexpr (XT) {
+            R xv[12];
 #pragma unroll
-        for (int s = 0; s < NSP; ++s)
+            for (int s = 0; s < NSP; ++s)
 #pragma unroll
-            for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
+                for (int p = 0; p < 6; ++p) xv[xslot(s, p)] = ph[s][xpop(p)];
+            float4* xw = reinterpret_cast<float4*>(&lds[b][0][0] + 12 * t);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) xw[q] = float4{xv[4 * q], xv[4 * q + 1], xv[4 * q + 2], xv[4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int s = 0; s < NSP; ++s)
+#pragma unroll
+                for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
+        }
         lanes_sync<W>();
         if (SPLIT && CORR && AHEAD && MODE == FV_ALONE) {
             __builtin_amdgcn_sched_barrier(0);
@@ -1015,6 +1031,22 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                         for (int a = 0; a < 9; ++a) base_at(r, s * 9 + a) = bs[s][a];
                 }
             }
+            R Lm2[12], Lm1[12], Lp1[12], Lp2[12];
+            if constexpr (XT) {
+                const R* xb = &lds[b][0][0];
+                auto ld4 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
+                    const float4 x = *reinterpret_cast<const float4*>(xb + 12 * lane + q);
+                    o[q] = x.x; o[q + 1] = x.y; o[q + 2] = x.z; o[q + 3] = x.w;
+                };
+                auto ld2 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
+                    const float2 x = *reinterpret_cast<const float2*>(xb + 12 * lane + q);
+                    o[q] = x.x; o[q + 1] = x.y;
+                };
+                ld4(Lm2, t - 2, 0); ld2(Lm2, t - 2, 4);
+                ld4(Lm1, t - 1, 0); ld4(Lm1, t - 1, 4); ld4(Lm1, t - 1, 8);
+                ld4(Lp1, t + 1, 0); ld4(Lp1, t + 1, 4); ld4(Lp1, t + 1, 8);
+                ld2(Lp2, t + 2, 6); ld4(Lp2, t + 2, 8);
+            }
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
 #pragma unroll
@@ -1023,7 +1055,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                     const R* L = lds[b][s * 6 + p];
                     const R v = ph[s][a];
                     R d;
-                    if (cx(a) > 0)
+                    if constexpr (XT) {
+                        const int q = xslot(s, p);
+                        if (cx(a) > 0)
+                            d = xc[0] * Lm2[q] + xc[1] * Lm1[q] + xc[2] * v + xc[3] * Lp1[q];
+                        else
+                            d = xc[4] * Lm1[q] + xc[5] * v + xc[6] * Lp1[q] + xc[7] * Lp2[q];
+                    } else if (cx(a) > 0)
                         d = xc[0] * L[t - 2] + xc[1] * L[t - 1] + xc[2] * v + xc[3] * L[t + 1];
                     else
                         d = xc[4] * L[t - 1] + xc[5] * v + xc[6] * L[t + 1] + xc[7] * L[t + 2];
