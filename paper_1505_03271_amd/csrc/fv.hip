@@ -1191,7 +1191,9 @@ __device__ __forceinline__ void fused_halves(const FvArgs<R>& A, const int item,
 template <class R, class S, bool TH>
 __global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2) fv_fused(FvArgs<R> A) {
     constexpr int NSP = TH ? 2 : 1;
-    __shared__ R x1[2][6 * NSP][FV_LANES], x2[2][6 * NSP][FV_LANES];
+    // (16-byte aligned: with g a lane's exchanged values are read as 16-byte words)
+    __shared__ __attribute__((aligned(16))) R x1[2][6 * NSP][FV_LANES];
+    __shared__ __attribute__((aligned(16))) R x2[2][6 * NSP][FV_LANES];
     __shared__ uint32_t ring[fused_ring_words<S, TH>() * FV_LANES];
     const int b = xcd_item(blockIdx.x, A.n_items);
     if (b >= A.n_items) return;
@@ -1209,7 +1211,9 @@ template <class R, class S, bool TH>
 __global__ void __launch_bounds__(2 * FV_LANES, TH ? 1 : 2)
     fv_fused_multi(const FvArgs<R>* args, const int2* items, int n_items, const int64_t* left, const int* phase) {
     constexpr int NSP = TH ? 2 : 1;
-    __shared__ R x1[2][6 * NSP][FV_LANES], x2[2][6 * NSP][FV_LANES];
+    // (16-byte aligned: with g a lane's exchanged values are read as 16-byte words)
+    __shared__ __attribute__((aligned(16))) R x1[2][6 * NSP][FV_LANES];
+    __shared__ __attribute__((aligned(16))) R x2[2][6 * NSP][FV_LANES];
     __shared__ uint32_t ring[fused_ring_words<S, TH>() * FV_LANES];
     const int b = xcd_item(blockIdx.x, n_items);
     if (b >= n_items) return;
