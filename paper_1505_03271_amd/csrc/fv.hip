@@ -996,7 +996,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             prefetch_own(r + 1, Slot<SL + 1>{});
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (formed) {
+        // (the partial update of a row is kept only where a later row's y
+        // flux finishes it: rows the half forms or owns)
+        if (formed && (MODE == FV_FIRST ? (r >= f_lo && r < f_hi) : (r >= y0 && r < y1))) {
             R base[NSP][9];
             if (CORR) {
                 // f~n+1 = (f~n + C(f~n) + f~*)/2 - dt/2 D(phi*): C from f~n at this
