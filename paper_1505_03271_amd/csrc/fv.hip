@@ -766,6 +766,13 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
     // to +x first), so a neighbour's values come in a few wide reads.
     constexpr bool XT = TH && MODE != FV_ALONE && sizeof(R) == 4;
     auto xslot = [](int s, int p) { return (p < 3 ? 0 : 6) + 3 * s + p % 3; };
+    // LATE: the second half into split storage encodes and stores its
+    // finished row after the row's barrier, behind the exchange reads, so
+    // that the encoder's arithmetic covers their latency
+    constexpr bool LATE = XT && MODE == FV_SECOND && SPLIT;   // (measured: faster with split storage only)
+    // neighbour lanes of the exchange, clamped to the item (lanes whose flux
+    // is formed never reach the clamp)
+    const int lm2 = max(t - 2, 0), lm1 = max(t - 1, 0), lp1 = min(t + 1, W - 1), lp2 = min(t + 2, W - 1);
     // The second half of a fused step into split storage works with twice
     // its update (base f~n + C(f~n) + f~* and the flux weights of dt, not
     // dt/2): scaling by two is exact, so every value it forms is exactly
@@ -947,8 +954,9 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             sU = yc[0] * (TRg[SL] - tj) + yc[1] * (TRg[(SL + 1) & 3] - tj) + yc[3] * (TRg[(SL + 3) & 3] - tj);
             sD = yc[4] * (TRg[(SL + 1) & 3] - tj) + yc[6] * (TRg[(SL + 3) & 3] - tj) + yc[7] * (Tr - tj);
         }
+        R out[NSP][9];
+        bool store_late = false;
         if (MODE == FV_FIRST ? (formed && j >= f_lo && j < f_hi) : (owned && j >= y0 && j < y1)) {
-            R out[NSP][9];
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
 #pragma unroll
@@ -969,6 +977,8 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
             }
             if (MODE == FV_FIRST)
                 store_hand(j, out[0], out[NSP - 1]);
+            else if (LATE)
+                store_late = true;
             else
                 store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
         }
@@ -991,6 +1001,32 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                 for (int p = 0; p < 6; ++p) lds[b][s * 6 + p][t] = ph[s][xpop(p)];
         }
         lanes_sync<W>();
+        R Lm2[12], Lm1[12], Lp1[12], Lp2[12];
+        auto x_reads = [&]() __attribute__((always_inline)) {
+            const R* xb = &lds[b][0][0];
+            auto ld4 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
+                const float4 x = *reinterpret_cast<const float4*>(xb + 12 * lane + q);
+                o[q] = x.x; o[q + 1] = x.y; o[q + 2] = x.z; o[q + 3] = x.w;
+            };
+            auto ld2 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
+                const float2 x = *reinterpret_cast<const float2*>(xb + 12 * lane + q);
+                o[q] = x.x; o[q + 1] = x.y;
+            };
+            // (reads issued for every lane take clamped neighbours; inside
+            // the flux block the lanes are those whose flux is formed)
+            const int m2 = LATE ? lm2 : t - 2, m1 = LATE ? lm1 : t - 1, p1 = LATE ? lp1 : t + 1, p2 = LATE ? lp2 : t + 2;
+            ld4(Lm2, m2, 0); ld2(Lm2, m2, 4);
+            ld4(Lm1, m1, 0); ld4(Lm1, m1, 4); ld4(Lm1, m1, 8);
+            ld4(Lp1, p1, 0); ld4(Lp1, p1, 4); ld4(Lp1, p1, 8);
+            ld2(Lp2, p2, 6); ld4(Lp2, p2, 8);
+        };
+        if constexpr (LATE) {
+            // the exchange reads first, then the store of the finished row
+            // while they arrive
+            x_reads();
+            if (store_late)
+                store_any(bdst, uint32_t(j) * nxu + colu, out[0], out[NSP - 1], TRg[(SL + 2) & 3], QRg[(SL + 2) & 3]);
+        }
         if (SPLIT && CORR && AHEAD && MODE == FV_ALONE) {
             __builtin_amdgcn_sched_barrier(0);
             prefetch_own(r + 1, Slot<SL + 1>{});
@@ -1033,22 +1069,7 @@ __device__ __forceinline__ void fv_item(const FvArgs<R>& A, const int item, cons
                         for (int a = 0; a < 9; ++a) base_at(r, s * 9 + a) = bs[s][a];
                 }
             }
-            R Lm2[12], Lm1[12], Lp1[12], Lp2[12];
-            if constexpr (XT) {
-                const R* xb = &lds[b][0][0];
-                auto ld4 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
-                    const float4 x = *reinterpret_cast<const float4*>(xb + 12 * lane + q);
-                    o[q] = x.x; o[q + 1] = x.y; o[q + 2] = x.z; o[q + 3] = x.w;
-                };
-                auto ld2 = [&](R* o, int lane, int q) __attribute__((always_inline)) {
-                    const float2 x = *reinterpret_cast<const float2*>(xb + 12 * lane + q);
-                    o[q] = x.x; o[q + 1] = x.y;
-                };
-                ld4(Lm2, t - 2, 0); ld2(Lm2, t - 2, 4);
-                ld4(Lm1, t - 1, 0); ld4(Lm1, t - 1, 4); ld4(Lm1, t - 1, 8);
-                ld4(Lp1, t + 1, 0); ld4(Lp1, t + 1, 4); ld4(Lp1, t + 1, 8);
-                ld2(Lp2, t + 2, 6); ld4(Lp2, t + 2, 8);
-            }
+            if constexpr (XT && !LATE) x_reads();
 #pragma unroll
             for (int s = 0; s < NSP; ++s) {
 #pragma unroll
