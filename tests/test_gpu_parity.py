@@ -228,7 +228,7 @@ def test_split_storage_against_oracle(storage, scheme, case):
     assert d["nonfinite"] == 0.0
 
 
-@pytest.mark.parametrize("storage", ["bf16s", "bf16"])
+@pytest.mark.parametrize("storage", ["bf16s", "f16s", "bf16"])
 def test_full_size_rb4096_one_step(storage):
     """The benchmark's workload and launch shape (4096^2, default chunking):
     two full steps against the oracle on every cell."""
@@ -241,7 +241,7 @@ def test_full_size_rb4096_one_step(storage):
     sim.step(2)
     ref.step(2)
     f, g = sim.populations()
-    if storage == "bf16s":
+    if storage in ("bf16s", "f16s"):
         R = _residual_scale(ref.f, ref.g, cfg["dt"], 0.0, 0.0, cfg["beta_g"], cfg["T0"])
         bound = 2 * (8 * UNIT[storage] * R + 64 * 2.0 ** -24)
     else:
